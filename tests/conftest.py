@@ -1,0 +1,28 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+_SCENES = {}
+
+
+@pytest.fixture(scope="session")
+def scene_cache():
+    from gen.scenes import make_scene
+
+    def get(name, seed=None):
+        key = (name, seed)
+        if key not in _SCENES:
+            _SCENES[key] = make_scene(name, seed)
+        return _SCENES[key]
+    return get

@@ -1,0 +1,183 @@
+"""Pins of the linear solves, the node update and whole Gauss-Newton frames."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.spatial.transform import Rotation
+
+from gen.scenes import Camera, SolverParams, corner_prims, poisson_nodes, ray_cast, reference_surfels
+from oracle import quat as Q
+from oracle import replica32 as R32
+from oracle import skin
+from oracle import solve as S
+
+
+def _spd(n, rng):
+    B = rng.normal(size=(n, n))
+    return B @ B.T + n * np.eye(n)
+
+
+def test_cholesky_matches_numpy_solve():
+    rng = np.random.default_rng(0)
+    A = _spd(60, rng)
+    g = rng.normal(size=60)
+    assert np.allclose(S.solve_cholesky(sp.csr_matrix(A), g), -np.linalg.solve(A, g), rtol=1e-12)
+
+
+def test_pcg_reaches_cholesky(scene_cache):
+    s = scene_cache("tiny")
+    pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
+    R, t = Q.se3_to_rt(S.identity_se3(s.node_pos.shape[0]))
+    lin = S.linearize(pb, R, t)
+    A, g = S.normal_equations(pb, lin)
+    x_chol = S.solve_cholesky(A, g)
+    x_pcg = S.solve_pcg(A, g, 3 * g.size)
+    assert np.linalg.norm(x_pcg - x_chol) <= 1e-8 * np.linalg.norm(x_chol)
+
+
+def test_pcg_block_jacobi_single_block_is_exact():
+    # with one 6x6 block, the preconditioner is the inverse: one step solves it
+    rng = np.random.default_rng(1)
+    A = _spd(6, rng)
+    g = rng.normal(size=6)
+    assert np.allclose(S.solve_pcg(sp.csr_matrix(A), g, 1), -np.linalg.solve(A, g), rtol=1e-12)
+
+
+def test_pcg_stops_on_zero_rho():
+    A = sp.identity(12, format="csr")
+    x = S.solve_pcg(A, np.zeros(12), 10)
+    assert np.array_equal(x, np.zeros(12))
+
+
+def test_node_update_composes_on_the_left_about_live_node():
+    rng = np.random.default_rng(2)
+    n = 10
+    p = rng.normal(size=(n, 3))
+    R = Rotation.random(n, random_state=4).as_matrix()
+    t = rng.normal(size=(n, 3))
+    delta = rng.normal(size=(n, 6)) * 0.1
+    R2, t2 = S.update_nodes(p, R, t, delta.ravel())
+    for k in range(n):
+        c = R[k] @ p[k] + t[k]
+        E = Rotation.from_rotvec(delta[k, :3]).as_matrix()
+        D = np.eye(4)
+        D[:3, :3] = E
+        D[:3, 3] = c + delta[k, 3:] - E @ c
+        T = np.eye(4)
+        T[:3, :3], T[:3, 3] = R[k], t[k]
+        M = D @ T
+        assert np.allclose(R2[k], M[:3, :3], atol=1e-12) and np.allclose(t2[k], M[:3, 3], atol=1e-12)
+
+
+def exact_identity_problem():
+    """A frame whose back-projection is exact in FP32 and FP64 (power-of-two
+    focal length, depth on a 2^-12 grid) with surfels taken from it."""
+    cam = Camera(64, 48, 64.0, 64.0, 32.0, 24.0)
+    ys, xs = np.mgrid[0:48, 0:64].astype(np.float64)
+    d = 1.0 + 0.08 * np.sin(xs / 7.0) * np.cos(ys / 5.0) + 0.002 * xs
+    d = (np.round(d * 4096) / 4096).astype(np.float32)
+    N32, ok = R32.normal_map(d, cam, 0.03)
+    yy, xx = np.nonzero(ok)
+    pos = R32.backproject(xx, yy, d[yy, xx], cam)
+    nrm = N32[yy, xx]
+    rng = np.random.default_rng(3)
+    nodes = pos[poisson_nodes(pos, 0.05, 60, rng)]
+    params = SolverParams(gn_iters=3, pcg_iters=10, lambda_reg=5.0, node_sigma=0.05,
+                          corr_dist=0.05, corr_normal=0.5, edge_gate=0.03, damping=1e-4)
+    return cam, d, pos, nrm, nodes, params
+
+
+def test_identity_frame_gives_zero_residual_and_step():
+    cam, d, pos, nrm, nodes, params = exact_identity_problem()
+    for linear in ("chol", "pcg"):
+        se3, tr = S.oracle_solve(cam, pos, nrm, nodes, d, params, linear=linear, keep=[0])
+        lin = tr["lin"][0]
+        assert lin["corr_idx"].size == pos.shape[0]
+        assert np.all(lin["r_data"] == 0) and lin["e_reg"] == 0
+        assert np.all(lin["g"] == 0)
+        assert all(np.all(st == 0) for st in tr["steps"])
+        assert np.array_equal(se3, S.identity_se3(nodes.shape[0]))
+
+
+def _rigid_scene():
+    """Box corner (three planes) moved rigidly; the live depth is ray-cast
+    exactly, so the rigid motion is the zero-energy optimum."""
+    cam = Camera(120, 90, 100.0, 100.0, 60.0, 45.0)
+    prims = corner_prims()
+    pos, nrm, _, _ = reference_surfels(cam, prims, margin=4)
+    rng = np.random.default_rng(12)
+    nodes = pos[poisson_nodes(pos, 0.08, 10 ** 6, rng)]
+    ax = np.array([0.3, 1.0, 0.2]) / np.linalg.norm([0.3, 1.0, 0.2])
+    Rs = Rotation.from_rotvec(np.deg2rad(2.0) * ax).as_matrix()
+    centre = np.array([0.0, 0.0, 1.2])
+    ts = centre - Rs @ centre + np.array([0.003, -0.002, 0.004])
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width].astype(np.float64)
+    t, _, _, _ = ray_cast(cam, [pl.moved(Rs, ts) for pl in prims], xs, ys)
+    depth = np.where(np.isfinite(t), t, 0.0).astype(np.float32)
+    # crease pixels get a mixed central-difference normal: the normal gate drops them
+    params = SolverParams(gn_iters=6, pcg_iters=10, lambda_reg=5.0, node_sigma=0.08,
+                          corr_dist=0.05, corr_normal=0.95, edge_gate=0.03, damping=1e-4)
+    return cam, pos, nrm, nodes, depth, params, Rs, ts
+
+
+def _rigid_point_to_plane_step(pb, lin):
+    """Textbook 6-DoF point-to-plane Gauss-Newton step (Omega, V) at the
+    identity, with the damping written on each node's (w, tau) = B_k (Omega, V)."""
+    ci = lin["corr_idx"]
+    v = lin["ws"]["v"][ci]
+    n = pb.N64[lin["uy"][ci], lin["ux"][ci]]
+    r = lin["r_data"]
+    Jr = np.concatenate([np.cross(v, n), n], axis=1)
+    H = Jr.T @ Jr
+    g = Jr.T @ r
+    Bs = []
+    for p in pb.node_pos.astype(np.float64):
+        B = np.zeros((6, 6))
+        B[:3, :3] = np.eye(3)
+        B[3:, :3] = -Q.skew(p[None])[0]
+        B[3:, 3:] = np.eye(3)
+        Bs.append(B)
+        H += pb.damping * B.T @ B
+    x = -np.linalg.solve(H, g)
+    return np.concatenate([B @ x for B in Bs])
+
+
+def test_large_lambda_reduces_to_rigid_point_to_plane(scene_cache):
+    # seed 8: every node is some node's neighbour, so the regulariser ties
+    # every node's rotation (a node nobody points to keeps a free rotation)
+    s = scene_cache("tiny", 8)
+    nn = s.node_pos.shape[0]
+    nbr = skin.node_graph(s.node_pos)
+    assert np.all(np.bincount(nbr.ravel(), minlength=nn) > 0)   # every rotation constrained
+    R, t = Q.se3_to_rt(S.identity_se3(nn))
+    gaps = []
+    for lam in (1e4, 1e5, 1e6):
+        params = SolverParams(**{**s.params.__dict__, "lambda_reg": lam})
+        pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, params)
+        lin = S.linearize(pb, R, t)
+        A, g = S.normal_equations(pb, lin)
+        step = S.solve_cholesky(A, g)
+        ref = _rigid_point_to_plane_step(pb, lin)
+        gaps.append(np.linalg.norm(step - ref) / np.linalg.norm(ref))
+    assert gaps[2] < 1e-3
+    assert gaps[1] < 0.2 * gaps[0] and gaps[2] < 0.2 * gaps[1]
+
+
+@pytest.mark.slow
+def test_energy_decreases_c1(scene_cache):
+    s = scene_cache("c1")
+    se3, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
+                             linear="pcg", final_energy=True)
+    e = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
+    ef = tr["e_final"][0] + s.params.lambda_reg * tr["e_final"][1]
+    assert ef < e[0] and e[-1] < e[0]
+    # along the surface normal at each node (point-to-plane cannot see
+    # tangential sliding on a sphere) the warp moves toward the ground truth
+    p = s.node_pos.astype(np.float64)
+    nrm = s.surfel_nrm[[int(np.flatnonzero(np.all(s.surfel_pos == q, axis=1))[0])
+                        for q in s.node_pos]].astype(np.float64)
+    R, t = Q.se3_to_rt(se3)
+    Rg, tg = Q.se3_to_rt(s.gt_se3)
+    gt = np.einsum("nij,nj->ni", Rg, p) + tg
+    err = np.abs(np.sum(nrm * (np.einsum("nij,nj->ni", R, p) + t - gt), axis=1))
+    err0 = np.abs(np.sum(nrm * (p - gt), axis=1))
+    assert np.median(err) < 0.3 * np.median(err0)
