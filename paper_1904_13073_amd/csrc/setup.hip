@@ -1,0 +1,516 @@
+// Setup kernels, run once per node set (Sec. 6.5, Initialization): skinning of
+// every surfel to its nearest nodes, the node graph, and the block pattern of
+// J^T J with the per-block lists the assembly walks.
+//
+// Every integer result is deterministic: nearest-node order is decided by an
+// FP32 key with a fixed operation order and ties to the lower index; sorts
+// compare full (key, value) pairs that are unique; the only atomics are
+// integer OR / ADD whose results do not depend on order.
+#include "swgn_impl.h"
+#include "swgn_launch.h"
+
+namespace swgn {
+
+// ---------------------------------------------------------------------------
+// Nearest nodes. Key ((dx*dx + dy*dy) + dz*dz), dx = x_query - x_node. The
+// list stays sorted by key; a candidate enters only with a key strictly below
+// the current last one and goes after every kept entry whose key is <= its
+// own. Nodes are visited in ascending index, so equal keys keep the lower
+// index first.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void knn_insert(float (&kd)[K], int (&ki)[K], float key, int j) {
+    if (!(key < kd[K - 1])) return;
+    int p = K - 1;
+#pragma unroll
+    for (int q = K - 1; q > 0; --q) {
+        if (key < kd[q - 1]) {
+            kd[q] = kd[q - 1];
+            ki[q] = ki[q - 1];
+            p = q - 1;
+        }
+    }
+    kd[p] = key;
+    ki[p] = j;
+}
+
+constexpr int kKnnTile = 1024;
+
+__global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restrict__ pos, int nn,
+        const float4* __restrict__ nodes, float inv_two_sigma2, int4* __restrict__ out_idx,
+        float4* __restrict__ out_w) {
+    __shared__ float4 tile[kKnnTile];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (i < ns) { x = pos[3 * i]; y = pos[3 * i + 1]; z = pos[3 * i + 2]; }
+    float kd[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    int ki[4] = {0, 0, 0, 0};
+    for (int base = 0; base < nn; base += kKnnTile) {
+        int cnt = min(kKnnTile, nn - base);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = nodes[base + t];
+        __syncthreads();
+        if (i < ns) {
+            for (int t = 0; t < cnt; ++t) {
+                float4 p = tile[t];
+                float dx = x - p.x, dy = y - p.y, dz = z - p.z;
+                float key = (dx * dx + dy * dy) + dz * dz;
+                knn_insert<4>(kd, ki, key, base + t);
+            }
+        }
+    }
+    if (i >= ns) return;
+    // weights exp(-(d_k^2 - d_0^2) / (2 sigma^2)), normalised
+    float e0 = 1.0f;
+    float e1 = expf(-(kd[1] - kd[0]) * inv_two_sigma2);
+    float e2 = expf(-(kd[2] - kd[0]) * inv_two_sigma2);
+    float e3 = expf(-(kd[3] - kd[0]) * inv_two_sigma2);
+    float inv = 1.0f / (((e0 + e1) + e2) + e3);
+    out_idx[i] = make_int4(ki[0], ki[1], ki[2], ki[3]);
+    out_w[i] = make_float4(e0 * inv, e1 * inv, e2 * inv, e3 * inv);
+}
+
+__global__ void __launch_bounds__(256) k_node_graph(int nn, const float4* __restrict__ nodes,
+                                                    int* __restrict__ nbr) {
+    __shared__ float4 tile[kKnnTile];
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    float4 me = j < nn ? nodes[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float kd[8];
+    int ki[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) { kd[q] = INFINITY; ki[q] = 0; }
+    for (int base = 0; base < nn; base += kKnnTile) {
+        int cnt = min(kKnnTile, nn - base);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = nodes[base + t];
+        __syncthreads();
+        if (j < nn) {
+            for (int t = 0; t < cnt; ++t) {
+                if (base + t == j) continue;
+                float4 p = tile[t];
+                float dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+                float key = (dx * dx + dy * dy) + dz * dz;
+                knn_insert<8>(kd, ki, key, base + t);
+            }
+        }
+    }
+    if (j >= nn) return;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) nbr[8 * j + q] = ki[q];
+}
+
+// ---------------------------------------------------------------------------
+// Bitonic sort of (u64 key, u32 val) pairs, ascending in (key, val).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool pair_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
+    return ka < kb || (ka == kb && va < vb);
+}
+
+__global__ void k_bitonic_global(uint64_t* __restrict__ key, uint32_t* __restrict__ val, int n,
+                                 int k, int j) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int p = i ^ j;
+    if (p <= i) return;
+    bool asc = (i & k) == 0;
+    uint64_t ka = key[i], kb = key[p];
+    uint32_t va = val[i], vb = val[p];
+    bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
+    if (sw) {
+        key[i] = kb; key[p] = ka;
+        val[i] = vb; val[p] = va;
+    }
+}
+
+constexpr int kSortLds = 1024;  // elements per block in the LDS stages
+
+// All stages with j < kSortLds for a given k (and, when k <= kSortLds, all k
+// up to it) on one 1024-element slice held in LDS.
+__global__ void __launch_bounds__(512) k_bitonic_lds(uint64_t* __restrict__ key,
+        uint32_t* __restrict__ val, int n, int k_from, int k_to) {
+    __shared__ uint64_t sk[kSortLds];
+    __shared__ uint32_t sv[kSortLds];
+    int base = blockIdx.x * kSortLds;
+    for (int t = threadIdx.x; t < kSortLds; t += blockDim.x) {
+        sk[t] = key[base + t];
+        sv[t] = val[base + t];
+    }
+    __syncthreads();
+    for (int k = k_from; k <= k_to; k <<= 1) {
+        int jstart = min(k >> 1, kSortLds >> 1);
+        for (int j = jstart; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < kSortLds; t += blockDim.x) {
+                int p = t ^ j;
+                if (p > t) {
+                    int gi = base + t;
+                    bool asc = (gi & k) == 0;
+                    uint64_t ka = sk[t], kb = sk[p];
+                    uint32_t va = sv[t], vb = sv[p];
+                    bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
+                    if (sw) { sk[t] = kb; sk[p] = ka; sv[t] = vb; sv[p] = va; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < kSortLds; t += blockDim.x) {
+        key[base + t] = sk[t];
+        val[base + t] = sv[t];
+    }
+}
+
+void sort_pairs(uint64_t* key, uint32_t* val, int n_pow2, hipStream_t st) {
+    // n_pow2 is a power of two >= kSortLds
+    int blocks = n_pow2 / kSortLds;
+    hipLaunchKernelGGL(k_bitonic_lds, dim3(blocks), dim3(512), 0, st, key, val, n_pow2, 2, kSortLds);
+    for (int k = 2 * kSortLds; k <= n_pow2; k <<= 1) {
+        for (int j = k >> 1; j >= kSortLds; j >>= 1) {
+            hipLaunchKernelGGL(k_bitonic_global, dim3((n_pow2 + 255) / 256), dim3(256), 0, st,
+                               key, val, n_pow2, k, j);
+        }
+        hipLaunchKernelGGL(k_bitonic_lds, dim3(blocks), dim3(512), 0, st, key, val, n_pow2, k, k);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 (n elements -> out[0..n], out[n] = total).
+// ---------------------------------------------------------------------------
+constexpr int kScanBlock = 1024;
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_block(const int* __restrict__ in, int* __restrict__ out,
+                                                           int* __restrict__ sums, int n) {
+    __shared__ int s[kScanBlock];
+    int i = blockIdx.x * kScanBlock + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_add(int* __restrict__ out, const int* __restrict__ offs, int n) {
+    int i = blockIdx.x * kScanBlock + threadIdx.x;
+    if (i < n) out[i] += offs[blockIdx.x];
+}
+
+__global__ void k_scan_total(int* __restrict__ out, const int* __restrict__ in, int n) {
+    out[n] = (n > 0 ? out[n - 1] + in[n - 1] : 0);
+}
+
+void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t st) {
+    // tmp must hold scan_tmp_size(n) ints
+    int nb = (n + kScanBlock - 1) / kScanBlock;
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, in, 0);
+        return;
+    }
+    int* sums = tmp;
+    int* sums_scan = tmp + nb;
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kScanBlock), 0, st, in, out, sums, n);
+    if (nb > 1) {
+        exclusive_scan(sums, sums_scan, nb, tmp + 2 * nb + 1, st);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, st, out, sums_scan, n);
+    }
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, in, n);
+}
+
+size_t scan_tmp_size(int n) {
+    size_t total = 0;
+    while (n > 1) {
+        int nb = (n + kScanBlock - 1) / kScanBlock;
+        total += 2 * (size_t)nb + 1;
+        n = nb;
+    }
+    return total + 4;
+}
+
+// ---------------------------------------------------------------------------
+// Surfel ordering by node set
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sort4(int& a, int& b, int& c, int& d) {
+    int t;
+#define SWGN_CS(p, q) if (p > q) { t = p; p = q; q = t; }
+    SWGN_CS(a, b) SWGN_CS(c, d) SWGN_CS(a, c) SWGN_CS(b, d) SWGN_CS(b, c)
+#undef SWGN_CS
+}
+
+__global__ void k_tuple_keys(int ns, int npad, const int4* __restrict__ idx, uint64_t* __restrict__ key,
+                             uint32_t* __restrict__ val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= ns) {
+        key[i] = ~0ull;
+        val[i] = 0xffffffffu;
+        return;
+    }
+    int4 q = idx[i];
+    int a = q.x, b = q.y, c = q.z, d = q.w;
+    sort4(a, b, c, d);
+    key[i] = ((uint64_t)a << 48) | ((uint64_t)b << 32) | ((uint64_t)c << 16) | (uint64_t)d;
+    val[i] = (uint32_t)i;
+}
+
+// Gather surfel arrays into sorted order; flag run starts.
+__global__ void k_permute_surfels(int ns, const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
+        const float* __restrict__ ipos, const float* __restrict__ inrm, const int4* __restrict__ iidx,
+        const float4* __restrict__ iw, float* __restrict__ px, float* __restrict__ py, float* __restrict__ pz,
+        float* __restrict__ nx, float* __restrict__ ny, float* __restrict__ nz, int4* __restrict__ oidx,
+        float4* __restrict__ ow, int* __restrict__ orig, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    int o = (int)val[i];
+    px[i] = ipos[3 * o + 0]; py[i] = ipos[3 * o + 1]; pz[i] = ipos[3 * o + 2];
+    nx[i] = inrm[3 * o + 0]; ny[i] = inrm[3 * o + 1]; nz[i] = inrm[3 * o + 2];
+    oidx[i] = iidx[o];
+    ow[i] = iw[o];
+    orig[i] = o;
+    flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_starts(int ns, const int* __restrict__ flag, const int* __restrict__ pos,
+                             int* __restrict__ run_start) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns && flag[i]) run_start[pos[i]] = i;
+    if (i == 0) run_start[pos[ns]] = ns;
+}
+
+// ---------------------------------------------------------------------------
+// Block pattern: bitmap of the upper triangle, one row of nn bits per node.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void set_bit(uint32_t* bm, int words, int r, int c) {
+    atomicOr(&bm[(size_t)r * words + (c >> 5)], 1u << (c & 31));
+}
+
+__global__ void k_pattern_runs(int nruns, const uint64_t* __restrict__ key, const int* __restrict__ run_start,
+                               uint32_t* __restrict__ bm, int words) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    uint64_t k = key[run_start[r]];
+    int t[4] = {(int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff)};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) set_bit(bm, words, t[a], t[b]);
+}
+
+__global__ void k_pattern_nodes(int nn, const int* __restrict__ nbr, uint32_t* __restrict__ bm, int words) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nn) return;
+    set_bit(bm, words, j, j);
+    for (int q = 0; q < 8; ++q) {
+        int m = nbr[8 * j + q];
+        set_bit(bm, words, min(j, m), max(j, m));
+    }
+}
+
+__global__ void k_row_counts(int nn, const uint32_t* __restrict__ bm, int words, int* __restrict__ cnt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nn) return;
+    int c = 0;
+    for (int w = 0; w < words; ++w) c += __popc(bm[(size_t)r * words + w]);
+    cnt[r] = c;
+}
+
+__global__ void k_row_fill(int nn, const uint32_t* __restrict__ bm, int words, const int* __restrict__ row_ptr,
+                           int* __restrict__ col_idx, int* __restrict__ blk_row) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nn) return;
+    int p = row_ptr[r];
+    for (int w = 0; w < words; ++w) {
+        uint32_t m = bm[(size_t)r * words + w];
+        while (m) {
+            int b = __ffs(m) - 1;
+            m &= m - 1;
+            col_idx[p] = w * 32 + b;
+            blk_row[p] = r;
+            ++p;
+        }
+    }
+}
+
+__device__ __forceinline__ int find_block(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                          int r, int c) {
+    int lo = row_ptr[r], hi = row_ptr[r + 1] - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (col_idx[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Per run, its 10 (block, run, position pair) entries as sortable keys.
+__global__ void k_run_entries(int nruns, const uint64_t* __restrict__ key,
+        const int* __restrict__ run_start, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+        uint64_t* __restrict__ ekey, uint32_t* __restrict__ eval, int* __restrict__ ecount) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    uint64_t k = key[run_start[r]];
+    int t[4] = {(int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff)};
+    int e = 10 * r;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+            int blk = find_block(row_ptr, col_idx, t[a], t[b]);
+            ekey[e] = ((uint64_t)blk << 32) | (uint64_t)(((uint32_t)r << 4) | (uint32_t)(a << 2) | (uint32_t)b);
+            eval[e] = 0;
+            atomicAdd(&ecount[blk], 1);
+            ++e;
+        }
+    }
+}
+
+__global__ void k_pad_keys(uint64_t* __restrict__ key, uint32_t* __restrict__ val, int from, int to) {
+    int i = from + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= to) return;
+    key[i] = ~0ull;
+    val[i] = 0xffffffffu;
+}
+
+__global__ void k_entries_store(int ne, const uint64_t* __restrict__ ekey, uint32_t* __restrict__ ent) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) ent[i] = (uint32_t)(ekey[i] & 0xffffffffull);
+}
+
+// Transposed uses of the upper off-diagonal blocks, keyed by (col, row).
+__global__ void k_transpose_keys(int nb, const int* __restrict__ blk_row, const int* __restrict__ col_idx,
+                                 uint64_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                 int* __restrict__ tcount) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int r = blk_row[b], c = col_idx[b];
+    if (r == c) {
+        tkey[b] = ~0ull;
+        tval[b] = 0xffffffffu;
+        return;
+    }
+    tkey[b] = ((uint64_t)c << 32) | (uint64_t)r;
+    tval[b] = (uint32_t)b;
+    atomicAdd(&tcount[c], 1);
+}
+
+__global__ void k_full_counts(int nn, const int* __restrict__ row_ptr, const int* __restrict__ tcount,
+                              int* __restrict__ fcount) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nn) fcount[r] = tcount[r] + (row_ptr[r + 1] - row_ptr[r]);
+}
+
+// Fill full rows: first the transposed blocks (ascending row), then the upper ones.
+__global__ void k_full_fill_t(int ntr, const uint64_t* __restrict__ tkey, const uint32_t* __restrict__ tval,
+                              const int* __restrict__ tstart, const int* __restrict__ frow_ptr,
+                              uint32_t* __restrict__ fblk, int* __restrict__ fcol) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntr) return;
+    int c = (int)(tkey[i] >> 32);
+    int r = (int)(tkey[i] & 0xffffffffull);
+    int slot = frow_ptr[c] + (i - tstart[c]);
+    fblk[slot] = tval[i] | kTransposed;
+    fcol[slot] = r;
+}
+
+__global__ void k_full_fill_u(int nn, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                              const int* __restrict__ tcount, const int* __restrict__ frow_ptr,
+                              uint32_t* __restrict__ fblk, int* __restrict__ fcol) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nn) return;
+    int p = frow_ptr[r] + tcount[r];
+    for (int b = row_ptr[r]; b < row_ptr[r + 1]; ++b) {
+        fblk[p] = (uint32_t)b;
+        fcol[p] = col_idx[b];
+        ++p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, float inv_two_sigma2, int4* idx,
+                     float4* w, hipStream_t st) {
+    if (ns <= 0) return;
+    hipLaunchKernelGGL(k_knn_skin, dim3((ns + 255) / 256), dim3(256), 0, st, ns, pos_aos, nn, nodes,
+                       inv_two_sigma2, idx, w);
+}
+
+void launch_node_graph(int nn, const float4* nodes, int* nbr, hipStream_t st) {
+    hipLaunchKernelGGL(k_node_graph, dim3((nn + 255) / 256), dim3(256), 0, st, nn, nodes, nbr);
+}
+
+void launch_tuple_keys(int ns, int npad, const int4* idx, uint64_t* key, uint32_t* val, hipStream_t st) {
+    hipLaunchKernelGGL(k_tuple_keys, dim3((npad + 255) / 256), dim3(256), 0, st, ns, npad, idx, key, val);
+}
+
+void launch_permute_surfels(int ns, const uint64_t* key, const uint32_t* val, const float* ipos,
+                            const float* inrm, const int4* iidx, const float4* iw, float* px, float* py,
+                            float* pz, float* nx, float* ny, float* nz, int4* oidx, float4* ow, int* orig,
+                            int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute_surfels, dim3((ns + 255) / 256), dim3(256), 0, st, ns, key, val, ipos, inrm,
+                       iidx, iw, px, py, pz, nx, ny, nz, oidx, ow, orig, flag);
+}
+
+void launch_run_starts(int ns, const int* flag, const int* pos, int* run_start, hipStream_t st) {
+    hipLaunchKernelGGL(k_run_starts, dim3((ns + 255) / 256), dim3(256), 0, st, ns, flag, pos, run_start);
+}
+
+void launch_pattern(int nruns, const uint64_t* key, const int* run_start, int nn, const int* nbr,
+                    uint32_t* bm, int words, hipStream_t st) {
+    if (nruns > 0)
+        hipLaunchKernelGGL(k_pattern_runs, dim3((nruns + 255) / 256), dim3(256), 0, st, nruns, key,
+                           run_start, bm, words);
+    hipLaunchKernelGGL(k_pattern_nodes, dim3((nn + 255) / 256), dim3(256), 0, st, nn, nbr, bm, words);
+}
+
+void launch_row_counts(int nn, const uint32_t* bm, int words, int* cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_row_counts, dim3((nn + 255) / 256), dim3(256), 0, st, nn, bm, words, cnt);
+}
+
+void launch_row_fill(int nn, const uint32_t* bm, int words, const int* row_ptr, int* col_idx, int* blk_row,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_row_fill, dim3((nn + 255) / 256), dim3(256), 0, st, nn, bm, words, row_ptr,
+                       col_idx, blk_row);
+}
+
+void launch_run_entries(int nruns, int npad, const uint64_t* key, const int* run_start, const int* row_ptr,
+                        const int* col_idx, uint64_t* ekey, uint32_t* eval, int* ecount, hipStream_t st) {
+    if (nruns > 0)
+        hipLaunchKernelGGL(k_run_entries, dim3((nruns + 255) / 256), dim3(256), 0, st, nruns, key,
+                           run_start, row_ptr, col_idx, ekey, eval, ecount);
+    int from = nruns * 10;
+    if (npad > from)
+        hipLaunchKernelGGL(k_pad_keys, dim3((npad - from + 255) / 256), dim3(256), 0, st, ekey, eval, from,
+                           npad);
+}
+
+void launch_entries_store(int ne, const uint64_t* ekey, uint32_t* ent, hipStream_t st) {
+    if (ne > 0)
+        hipLaunchKernelGGL(k_entries_store, dim3((ne + 255) / 256), dim3(256), 0, st, ne, ekey, ent);
+}
+
+void launch_transpose_keys(int nb, int npad, const int* blk_row, const int* col_idx, uint64_t* tkey,
+                           uint32_t* tval, int* tcount, hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose_keys, dim3((nb + 255) / 256), dim3(256), 0, st, nb, blk_row, col_idx,
+                       tkey, tval, tcount);
+    if (npad > nb)
+        hipLaunchKernelGGL(k_pad_keys, dim3((npad - nb + 255) / 256), dim3(256), 0, st, tkey, tval, nb, npad);
+}
+
+void launch_full_rows(int nn, int ntr, const int* row_ptr, const int* col_idx, const int* tcount,
+                      const int* tstart, const int* frow_ptr, const uint64_t* tkey, const uint32_t* tval,
+                      uint32_t* fblk, int* fcol, hipStream_t st) {
+    if (ntr > 0)
+        hipLaunchKernelGGL(k_full_fill_t, dim3((ntr + 255) / 256), dim3(256), 0, st, ntr, tkey, tval, tstart,
+                           frow_ptr, fblk, fcol);
+    hipLaunchKernelGGL(k_full_fill_u, dim3((nn + 255) / 256), dim3(256), 0, st, nn, row_ptr, col_idx, tcount,
+                       frow_ptr, fblk, fcol);
+}
+
+void launch_full_counts(int nn, const int* row_ptr, const int* tcount, int* fcount, hipStream_t st) {
+    hipLaunchKernelGGL(k_full_counts, dim3((nn + 255) / 256), dim3(256), 0, st, nn, row_ptr, tcount, fcount);
+}
+
+}  // namespace swgn

@@ -1,0 +1,148 @@
+// Internal layout and device helpers of the swgn library (gfx950, wave64).
+//
+// Device-resident state of one stream, all structure-of-arrays:
+//   surfels (sorted so that surfels with the same set of 4 nodes are
+//   contiguous; `orig` maps back to the caller's index):
+//     px,py,pz,nx,ny,nz  float[ns]    reference position and normal
+//     idx                int4[ns]     4 nearest nodes, nearest first
+//     w                  float4[ns]   normalised blend weights
+//     orig               int[ns]
+//   runs: run_start[nruns+1], maximal ranges of surfels with one node set
+//   nodes:
+//     pref  float4[nn]   reference position p_j
+//     rq    float4[nn]   rotation quaternion (w,x,y,z), w >= 0
+//     tt    float4[nn]   translation
+//     dq    float4[2nn]  dual quaternion (r_j, d_j), d = 1/2 (0,t) r
+//     cl    float4[nn]   live node position c_j = T_j p_j
+//     nbr   int[8nn]     8 nearest other nodes
+//   J^T J in block-sparse form: upper blocks (row <= col), 6x6 row-major fp32
+//     row_ptr[nn+1], col_idx[nb], blk_row[nb]   (diagonal first in each row)
+//     ent_ptr[nb+1], ent[ne]   per block: (run << 4 | pos_a << 2 | pos_b), the
+//                              runs whose node set holds both block nodes
+//     frow_ptr[nn+1], fblk[nf] full symmetric rows for the product: block id,
+//                              bit 31 set when the block is used transposed
+//   per frame: depth float[npx], nmap float4[npx] (normal, depth; depth 0 =
+//   no normal), zbuf u64[npx]; per iteration: J float[24][pitch] (node
+//   positions in ascending node order x 6), res float[pitch].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swgn {
+
+constexpr int kWave = 64;
+constexpr uint32_t kTransposed = 0x80000000u;
+constexpr float kBlendEps = 1e-12f;
+
+// --- quaternion helpers (w, x, y, z) in float4 as (x=w, y=x, z=y, w=z) -----
+// A quaternion q is stored as float4{q.w, q.x, q.y, q.z} in fields .x .y .z .w
+struct Q4 {
+    float w, x, y, z;
+};
+
+__device__ __forceinline__ Q4 q4(float4 v) { return Q4{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ float4 f4(Q4 q) { return make_float4(q.w, q.x, q.y, q.z); }
+
+__device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
+    Q4 r;
+    r.w = ((a.w * b.w - a.x * b.x) - a.y * b.y) - a.z * b.z;
+    r.x = ((a.w * b.x + a.x * b.w) + a.y * b.z) - a.z * b.y;
+    r.y = ((a.w * b.y - a.x * b.z) + a.y * b.w) + a.z * b.x;
+    r.z = ((a.w * b.z + a.x * b.y) - a.y * b.x) + a.z * b.w;
+    return r;
+}
+
+// vector part of x (x) conj(y)
+__device__ __forceinline__ float3 vec_mul_conj(Q4 x, Q4 y) {
+    float3 r;
+    r.x = (y.w * x.x - x.w * y.x) - (x.y * y.z - x.z * y.y);
+    r.y = (y.w * x.y - x.w * y.y) - (x.z * y.x - x.x * y.z);
+    r.z = (y.w * x.z - x.w * y.z) - (x.x * y.y - x.y * y.x);
+    return r;
+}
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 scale3(float3 a, float s) { return make_float3(a.x * s, a.y * s, a.z * s); }
+
+// Rotate v by unit quaternion (c0, u): v + 2 c0 (u x v) + 2 u x (u x v).
+__device__ __forceinline__ float3 qrot(float c0, float3 u, float3 v) {
+    float3 uv = cross3(u, v);
+    float3 uuv = cross3(u, uv);
+    return add3(add3(v, scale3(uv, 2.0f * c0)), scale3(uuv, 2.0f));
+}
+
+// Result of warping one surfel by the blend of its 4 nodes.
+struct Warp {
+    Q4 cr, cd;        // normalised blend c = b / |b_r|
+    float inv_beta;   // 1 / |b_r|
+    float sgn[4];     // hemisphere signs s_k
+    float3 v, n;      // live position and normal
+    bool ok;          // |b_r|^2 >= 1e-12
+};
+
+// Dual-quaternion blend (hemisphere of the nearest node) and application:
+// c = b / |b_r|, v' = rot(c_r) v + 2 vec(c_d c_r*), n' = rot(c_r) n.
+// Every value feeding an integer decision goes through this one function.
+__device__ __forceinline__ Warp warp_surfel(int4 idx, float4 w, float3 v, float3 n,
+                                            const float4* __restrict__ dq) {
+    Warp out;
+    const int id[4] = {idx.x, idx.y, idx.z, idx.w};
+    const float wk[4] = {w.x, w.y, w.z, w.w};
+    Q4 r0 = q4(dq[2 * id[0]]);
+    Q4 br = {0.f, 0.f, 0.f, 0.f}, bd = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Q4 rk = q4(dq[2 * id[k]]);
+        Q4 dk = q4(dq[2 * id[k] + 1]);
+        float dt = ((r0.w * rk.w + r0.x * rk.x) + r0.y * rk.y) + r0.z * rk.z;
+        float s = dt >= 0.f ? 1.f : -1.f;
+        out.sgn[k] = s;
+        float a = wk[k] * s;
+        br.w += a * rk.w; br.x += a * rk.x; br.y += a * rk.y; br.z += a * rk.z;
+        bd.w += a * dk.w; bd.x += a * dk.x; bd.y += a * dk.y; bd.z += a * dk.z;
+    }
+    float br2 = ((br.w * br.w + br.x * br.x) + br.y * br.y) + br.z * br.z;
+    out.ok = br2 >= kBlendEps;
+    float ib = 1.0f / sqrtf(out.ok ? br2 : 1.0f);
+    out.inv_beta = ib;
+    out.cr = Q4{br.w * ib, br.x * ib, br.y * ib, br.z * ib};
+    out.cd = Q4{bd.w * ib, bd.x * ib, bd.y * ib, bd.z * ib};
+    float3 u = make_float3(out.cr.x, out.cr.y, out.cr.z);
+    float3 t = vec_mul_conj(out.cd, out.cr);
+    out.v = add3(qrot(out.cr.w, u, v), scale3(t, 2.0f));
+    out.n = qrot(out.cr.w, u, n);
+    return out;
+}
+
+// Camera intrinsics and gates as passed to kernels.
+struct Cam {
+    int W, H;
+    float fx, fy, cx, cy;
+};
+
+// Pixel of a live point: floor(fx*(x/z) + cx + 0.5), inside the image, z > 0.
+__device__ __forceinline__ bool project(const Cam& c, float3 v, int& ux, int& uy) {
+    float px = c.fx * (v.x / v.z) + c.cx;
+    float py = c.fy * (v.y / v.z) + c.cy;
+    float hx = px + 0.5f;
+    float hy = py + 0.5f;
+    bool in = (v.z > 0.f) && (hx >= 0.f) && (hx < (float)c.W) && (hy >= 0.f) && (hy < (float)c.H);
+    ux = in ? (int)floorf(hx) : 0;
+    uy = in ? (int)floorf(hy) : 0;
+    return in;
+}
+
+// Back-projection ((u - cx)/fx * d, (v - cy)/fy * d, d).
+__device__ __forceinline__ float3 backproject(const Cam& c, int ux, int uy, float d) {
+    return make_float3((((float)ux - c.cx) / c.fx) * d, (((float)uy - c.cy) / c.fy) * d, d);
+}
+
+__device__ __forceinline__ bool depth_ok(float d) { return (d > 0.f) && (d < INFINITY); }
+
+}  // namespace swgn

@@ -1,0 +1,299 @@
+"""ctypes binding of the swgn C ABI (include/swgn.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Functions keep the C names; a failing status raises SwError with the stream's
+last error message. Arrays are NumPy (host, on_device=0) or torch tensors on
+the GPU (device, on_device=1); anything else with a `data_ptr()` is taken as
+a device pointer.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libswgn.so")
+
+SW_OK, SW_EINVAL, SW_ESTATE, SW_ENOMEM, SW_EHIP, SW_ENUMERIC = 0, -1, -2, -3, -4, -5
+
+
+class SwConfig(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("gn_iters", C.c_int32), ("pcg_iters", C.c_int32),
+                ("lambda_reg", C.c_float), ("node_sigma", C.c_float), ("corr_dist", C.c_float),
+                ("corr_normal", C.c_float), ("edge_gate", C.c_float), ("damping", C.c_float),
+                ("jac_dtype", C.c_int32), ("dot_fp64", C.c_int32), ("debug_iter", C.c_int32),
+                ("stage_timing", C.c_int32)]
+
+
+class SwFrameStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("e_data", C.c_float * 16), ("e_reg", C.c_float * 16),
+                ("n_corr", C.c_int32 * 16), ("pcg_resid", C.c_float * 16),
+                ("stage_us", C.c_float * 12), ("alg_bytes", C.c_double)]
+
+    def as_dict(self) -> dict:
+        n = self.iters
+        return dict(iters=n, e_data=list(self.e_data[:n]), e_reg=list(self.e_reg[:n]),
+                    n_corr=list(self.n_corr[:n]), pcg_resid=list(self.pcg_resid[:n]),
+                    stage_us=list(self.stage_us[:7]), alg_bytes=self.alg_bytes)
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_stream",
+           "sw_destroy_stream", "sw_set_reference_surfels", "sw_set_node_graph", "sw_set_node_se3",
+           "sw_solve_frame", "sw_get_node_se3", "sw_get_sizes", "sw_get_skinning",
+           "sw_get_node_graph", "sw_get_pattern", "sw_get_last_maps", "sw_get_last_system",
+           "sw_get_last_jacobian"]
+
+
+def lib() -> C.CDLL:
+    """The loaded library. Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"swgn HIP library missing at {_LIB_PATH}: build it with __graft_entry__.build()")
+    L = C.CDLL(_LIB_PATH)
+    vp, i32, i64, fp, ip = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p
+    sig = {
+        "sw_config_default": (None, [C.POINTER(SwConfig)]),
+        "sw_status_string": (C.c_char_p, [i32]),
+        "sw_last_error": (C.c_char_p, [vp]),
+        "sw_create_stream": (i32, [C.POINTER(SwConfig), vp, C.POINTER(vp)]),
+        "sw_destroy_stream": (i32, [vp]),
+        "sw_set_reference_surfels": (i32, [vp, i64, fp, fp, i32]),
+        "sw_set_node_graph": (i32, [vp, i32, fp, fp, i32]),
+        "sw_set_node_se3": (i32, [vp, fp, i32, i32]),
+        "sw_solve_frame": (i32, [vp, fp, i32, C.POINTER(SwFrameStats)]),
+        "sw_get_node_se3": (i32, [vp, fp, i32]),
+        "sw_get_sizes": (i32, [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
+        "sw_get_skinning": (i32, [vp, ip, fp]),
+        "sw_get_node_graph": (i32, [vp, ip]),
+        "sw_get_pattern": (i32, [vp, ip, ip]),
+        "sw_get_last_maps": (i32, [vp, ip, ip, fp, fp]),
+        "sw_get_last_system": (i32, [vp, fp, fp, fp]),
+        "sw_get_last_jacobian": (i32, [vp, fp, fp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(handle, st: int):
+    if st != SW_OK:
+        msg = lib().sw_last_error(handle).decode() if handle else ""
+        name = lib().sw_status_string(st).decode()
+        raise SwError(st, f"{name}: {msg}" if msg else name)
+
+
+def _ptr(a, dtype):
+    """(pointer, on_device, keepalive) for a host NumPy array or a device tensor."""
+    if a is None:
+        return None, 0, None
+    if isinstance(a, np.ndarray):
+        arr = np.ascontiguousarray(a, dtype=dtype)
+        return arr.ctypes.data_as(C.c_void_p), 0, arr
+    if hasattr(a, "data_ptr"):
+        if hasattr(a, "is_contiguous") and not a.is_contiguous():
+            raise ValueError("device tensor must be contiguous")
+        if hasattr(a, "is_cuda") and not a.is_cuda:
+            return _ptr(a.numpy(), dtype)
+        return C.c_void_p(a.data_ptr()), 1, a
+    return _ptr(np.asarray(a), dtype)
+
+
+def sw_config_default(**overrides) -> SwConfig:
+    c = SwConfig()
+    lib().sw_config_default(C.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def sw_create_stream(cfg: SwConfig, hip_stream: Optional[int] = None):
+    h = C.c_void_p()
+    st = lib().sw_create_stream(C.byref(cfg), C.c_void_p(hip_stream) if hip_stream else None, C.byref(h))
+    if st != SW_OK:
+        raise SwError(st, lib().sw_status_string(st).decode())
+    return h
+
+
+def sw_destroy_stream(h):
+    _check(None, lib().sw_destroy_stream(h))
+
+
+def sw_set_reference_surfels(h, pos, nrm):
+    p, dev, ka = _ptr(pos, np.float32)
+    q, dev2, kb = _ptr(nrm, np.float32)
+    if dev != dev2:
+        raise ValueError("positions and normals must both be host or both device")
+    n = ka.shape[0] if hasattr(ka, "shape") else len(ka)
+    _check(h, lib().sw_set_reference_surfels(h, int(n), p, q, dev))
+
+
+def sw_set_node_graph(h, node_pos, node_se3=None):
+    p, dev, ka = _ptr(node_pos, np.float32)
+    q, dev2, kb = _ptr(node_se3, np.float32)
+    if node_se3 is not None and dev != dev2:
+        raise ValueError("node positions and transforms must both be host or both device")
+    _check(h, lib().sw_set_node_graph(h, int(ka.shape[0]), p, q, dev))
+
+
+def sw_set_node_se3(h, se3):
+    p, dev, ka = _ptr(se3, np.float32)
+    _check(h, lib().sw_set_node_se3(h, p, int(ka.shape[0]), dev))
+
+
+def sw_solve_frame(h, depth, with_stats: bool = True):
+    p, dev, ka = _ptr(depth, np.float32)
+    stats = SwFrameStats()
+    _check(h, lib().sw_solve_frame(h, p, dev, C.byref(stats) if with_stats else None))
+    return stats.as_dict() if with_stats else None
+
+
+def sw_get_sizes(h):
+    ns, nn, nb = C.c_int64(), C.c_int32(), C.c_int32()
+    _check(h, lib().sw_get_sizes(h, C.byref(ns), C.byref(nn), C.byref(nb)))
+    return ns.value, nn.value, nb.value
+
+
+def sw_get_node_se3(h) -> np.ndarray:
+    _, nn, _ = sw_get_sizes(h)
+    out = np.empty((nn, 12), np.float32)
+    _check(h, lib().sw_get_node_se3(h, out.ctypes.data_as(C.c_void_p), nn))
+    return out
+
+
+def sw_get_skinning(h):
+    ns, _, _ = sw_get_sizes(h)
+    idx = np.empty((ns, 4), np.int32)
+    w = np.empty((ns, 4), np.float32)
+    _check(h, lib().sw_get_skinning(h, idx.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
+    return idx, w
+
+
+def sw_get_node_graph(h) -> np.ndarray:
+    _, nn, _ = sw_get_sizes(h)
+    out = np.empty((nn, 8), np.int32)
+    _check(h, lib().sw_get_node_graph(h, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def sw_get_pattern(h):
+    _, nn, nb = sw_get_sizes(h)
+    rp = np.empty(nn + 1, np.int32)
+    ci = np.empty(nb, np.int32)
+    _check(h, lib().sw_get_pattern(h, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p)))
+    return rp, ci
+
+
+def sw_get_last_maps(h, width: int, height: int):
+    ns, _, _ = sw_get_sizes(h)
+    I = np.empty((height, width), np.int32)
+    Cm = np.empty((height, width), np.int32)
+    live = np.empty((ns, 3), np.float32)
+    nrm = np.empty((3, height, width), np.float32)
+    _check(h, lib().sw_get_last_maps(h, I.ctypes.data_as(C.c_void_p), Cm.ctypes.data_as(C.c_void_p),
+                                     live.ctypes.data_as(C.c_void_p), nrm.ctypes.data_as(C.c_void_p)))
+    return I, Cm, live, nrm
+
+
+def sw_get_last_system(h):
+    _, nn, nb = sw_get_sizes(h)
+    blocks = np.empty((nb, 6, 6), np.float32)
+    g = np.empty((nn, 6), np.float32)
+    delta = np.empty((nn, 6), np.float32)
+    _check(h, lib().sw_get_last_system(h, blocks.ctypes.data_as(C.c_void_p), g.ctypes.data_as(C.c_void_p),
+                                       delta.ctypes.data_as(C.c_void_p)))
+    return blocks, g, delta
+
+
+def sw_get_last_jacobian(h):
+    ns, _, _ = sw_get_sizes(h)
+    r = np.empty(ns, np.float32)
+    J = np.empty((ns, 4, 6), np.float32)
+    _check(h, lib().sw_get_last_jacobian(h, r.ctypes.data_as(C.c_void_p), J.ctypes.data_as(C.c_void_p)))
+    return r, J
+
+
+class Stream:
+    """One depth stream: owns a library handle (convenience over the functions above)."""
+
+    def __init__(self, cfg: Optional[SwConfig] = None, hip_stream: Optional[int] = None, **overrides):
+        self.cfg = cfg if cfg is not None else sw_config_default()
+        for k, v in overrides.items():
+            setattr(self.cfg, k, v)
+        self.h = sw_create_stream(self.cfg, hip_stream)
+
+    def close(self):
+        if self.h:
+            sw_destroy_stream(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_reference_surfels(self, pos, nrm):
+        sw_set_reference_surfels(self.h, pos, nrm)
+
+    def set_node_graph(self, node_pos, node_se3=None):
+        sw_set_node_graph(self.h, node_pos, node_se3)
+
+    def set_node_se3(self, se3):
+        sw_set_node_se3(self.h, se3)
+
+    def solve_frame(self, depth, with_stats: bool = True):
+        return sw_solve_frame(self.h, depth, with_stats)
+
+    def node_se3(self) -> np.ndarray:
+        return sw_get_node_se3(self.h)
+
+    def sizes(self):
+        return sw_get_sizes(self.h)
+
+    def skinning(self):
+        return sw_get_skinning(self.h)
+
+    def node_graph(self):
+        return sw_get_node_graph(self.h)
+
+    def pattern(self):
+        return sw_get_pattern(self.h)
+
+    def last_maps(self):
+        return sw_get_last_maps(self.h, self.cfg.width, self.cfg.height)
+
+    def last_system(self):
+        return sw_get_last_system(self.h)
+
+    def last_jacobian(self):
+        return sw_get_last_jacobian(self.h)
+
+
+def config_for(scene, **overrides) -> SwConfig:
+    """Config of a generated scene (camera and solver settings)."""
+    p = scene.params
+    c = sw_config_default(width=scene.cam.width, height=scene.cam.height, fx=scene.cam.fx,
+                          fy=scene.cam.fy, cx=scene.cam.cx, cy=scene.cam.cy, gn_iters=p.gn_iters,
+                          pcg_iters=p.pcg_iters, lambda_reg=p.lambda_reg, node_sigma=p.node_sigma,
+                          corr_dist=p.corr_dist, corr_normal=p.corr_normal, edge_gate=p.edge_gate,
+                          damping=p.damping)
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c

@@ -1,0 +1,65 @@
+"""The C-ABI library: loads, exports every declared symbol, validates
+arguments on the host (no GPU call is made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swgn.h")
+LIB = os.path.join(ROOT, "paper_1904_13073_amd", "libswgn.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ("sw_create_stream", "sw_set_reference_surfels", "sw_set_node_graph",
+              "sw_solve_frame", "sw_get_node_se3", "sw_destroy_stream"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    for n in declared_symbols():
+        assert hasattr(lib, n), n
+    from paper_1904_13073_amd import swgn
+    assert sorted(swgn.EXPORTS) == declared_symbols()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_defaults_and_status_strings():
+    from paper_1904_13073_amd import swgn
+    c = swgn.sw_config_default()
+    assert (c.width, c.height, c.fx, c.cx, c.cy) == (640, 480, 570.0, 320.0, 240.0)
+    assert c.gn_iters == 10 and c.pcg_iters == 10
+    assert abs(c.node_sigma - 0.025) < 1e-9 and c.lambda_reg == 5.0
+    assert c.debug_iter == -1 and c.dot_fp64 == 1
+    L = swgn.lib()
+    assert L.sw_status_string(0) == b"ok"
+    assert L.sw_status_string(-5) == b"numerical failure"
+    assert L.sw_last_error(None) == b"null stream"
+    assert L.sw_destroy_stream(None) == 0
+    assert L.sw_solve_frame(None, None, 0, None) == swgn.SW_EINVAL
+    assert L.sw_get_sizes(None, None, None, None) == swgn.SW_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("field,value", [
+    ("width", 0), ("height", -3), ("fx", 0.0), ("fy", float("nan")), ("cx", float("inf")),
+    ("gn_iters", 17), ("gn_iters", -1), ("pcg_iters", 5000), ("lambda_reg", -1.0),
+    ("node_sigma", 0.0), ("corr_dist", 0.0), ("corr_normal", 1.5), ("edge_gate", -0.1),
+    ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
+])
+def test_create_rejects_bad_config(field, value):
+    from paper_1904_13073_amd import swgn
+    c = swgn.sw_config_default(**{field: value})
+    h = C.c_void_p()
+    st = swgn.lib().sw_create_stream(C.byref(c), None, C.byref(h))
+    assert st == swgn.SW_EINVAL and not h.value

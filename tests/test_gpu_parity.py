@@ -1,0 +1,164 @@
+"""GPU parity against the oracle, through the C ABI.
+
+Integer outputs (nearest nodes, node graph, block pattern, index map,
+correspondence map, normal-map validity) are compared bit for bit with the
+FP32 decisions of the oracle; floating-point outputs within tolerances derived
+from FP32 arithmetic; node transforms after a whole frame within 1e-4 rad and
+1e-5 m of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import expected_pattern, gpu_lib, se3_errors, stream_for
+from oracle import replica32 as R32
+from oracle import skin
+from oracle import solve as S
+from oracle.quat import se3_to_rt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swgn():
+    return gpu_lib()
+
+
+@pytest.mark.parametrize("name", ["tiny", "c1", "c2"])
+def test_skinning_graph_pattern_bit_exact(swgn, scene_cache, name):
+    s = scene_cache(name)
+    st = stream_for(swgn, s)
+    idx, w = st.skinning()
+    nbr = st.node_graph()
+    rp, ci = st.pattern()
+    st.close()
+    ref_idx = skin.knn_fp32(s.surfel_pos, s.node_pos, 4)
+    assert np.array_equal(idx, ref_idx)
+    ref_w = skin.skin_weights(s.surfel_pos, s.node_pos, ref_idx, s.params.node_sigma)
+    assert np.max(np.abs(w - ref_w)) < 2e-6
+    assert np.allclose(w.sum(axis=1), 1.0, atol=1e-6)
+    ref_nbr = skin.node_graph(s.node_pos)
+    assert np.array_equal(nbr, ref_nbr)
+    erp, eci = expected_pattern(ref_idx, ref_nbr, s.node_pos.shape[0])
+    assert np.array_equal(rp, erp) and np.array_equal(ci, eci)
+
+
+def test_identity_frame_exact(swgn):
+    from test_oracle_solve import exact_identity_problem
+    cam, d, pos, nrm, nodes, params = exact_identity_problem()
+    cfg = swgn.sw_config_default(width=cam.width, height=cam.height, fx=cam.fx, fy=cam.fy, cx=cam.cx,
+                                 cy=cam.cy, gn_iters=3, pcg_iters=10, lambda_reg=params.lambda_reg,
+                                 node_sigma=params.node_sigma, corr_dist=params.corr_dist,
+                                 corr_normal=params.corr_normal, edge_gate=params.edge_gate,
+                                 damping=params.damping, debug_iter=0)
+    st = swgn.Stream(cfg)
+    st.set_reference_surfels(pos, nrm)
+    st.set_node_graph(nodes)
+    stats = st.solve_frame(d)
+    I, Cm, live, N = st.last_maps()
+    blocks, g, delta = st.last_system()
+    r, J = st.last_jacobian()
+    se3 = st.node_se3()
+    st.close()
+    assert np.array_equal(live, pos)
+    assert np.array_equal(I, R32.index_map(pos, cam))
+    N32, ok = R32.normal_map(d, cam, params.edge_gate)
+    yy, xx = np.nonzero(ok)                  # the surfels were cast from these pixels
+    C_ref = np.full(Cm.shape, -1, np.int32)
+    C_ref[yy, xx] = np.arange(pos.shape[0])
+    assert np.array_equal(Cm, C_ref)
+    assert np.array_equal(np.moveaxis(N, 0, -1), N32)
+    assert np.all(r == 0) and np.all(g == 0) and np.all(delta == 0)
+    ident = np.tile(np.float32([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]), (nodes.shape[0], 1))
+    assert np.array_equal(se3, ident)
+    assert stats["e_data"] == [0.0] * 3 and stats["e_reg"] == [0.0] * 3
+    assert stats["n_corr"] == [pos.shape[0]] * 3
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_identity_state_maps_bit_exact(swgn, scene_cache, name):
+    s = scene_cache(name)
+    st = stream_for(swgn, s, debug_iter=0, gn_iters=1)
+    st.solve_frame(s.depth)
+    I, Cm, live, N = st.last_maps()
+    st.close()
+    assert np.array_equal(live, s.surfel_pos)      # the identity blend is exact
+    N32, ok = R32.normal_map(s.depth, s.cam, s.params.edge_gate)
+    assert np.array_equal(np.moveaxis(N, 0, -1), N32)
+    I_ref = R32.index_map(s.surfel_pos, s.cam)
+    assert np.array_equal(I, I_ref)
+    m, ux, uy = R32.correspondence(s.surfel_pos, s.surfel_nrm, I_ref, s.depth, N32, ok, s.cam,
+                                   s.params.corr_dist, s.params.corr_normal)
+    C_ref = np.full(I.shape, -1, np.int64)
+    C_ref[uy[m], ux[m]] = np.flatnonzero(m)
+    assert np.array_equal(Cm, C_ref)
+
+
+@pytest.fixture(scope="module")
+def tiny_gt_case(swgn, scene_cache):
+    """Tiny scene linearised at a non-identity state (the ground truth)."""
+    s = scene_cache("tiny")
+    st = stream_for(swgn, s, se3=s.gt_se3, debug_iter=0, gn_iters=1)
+    st.solve_frame(s.depth)
+    out = dict(maps=st.last_maps(), system=st.last_system(), jac=st.last_jacobian(),
+               pattern=st.pattern())
+    st.close()
+    pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
+    R, t = se3_to_rt(s.gt_se3.astype(np.float32).astype(np.float64))
+    lin = S.linearize(pb, R, t)
+    A, g = S.normal_equations(pb, lin)
+    return s, out, pb, lin, A, g
+
+
+def test_warp_and_association_at_non_identity_state(tiny_gt_case):
+    s, out, pb, lin, A, g = tiny_gt_case
+    I, Cm, live, N = out["maps"]
+    v64 = lin["ws"]["v"]
+    assert np.max(np.abs(live.astype(np.float64) - v64)) < 1e-6
+    # index and correspondence maps: the FP32 decisions agree except where the
+    # FP32 rounding of the live positions crosses a pixel or gate boundary
+    diff_I = np.count_nonzero(I != lin["I"])
+    diff_C = np.count_nonzero(Cm != lin["corr_map"])
+    assert diff_I <= 2 and diff_C <= 2, (diff_I, diff_C)
+
+
+def test_jacobian_and_system_at_non_identity_state(tiny_gt_case):
+    s, out, pb, lin, A, g = tiny_gt_case
+    I, Cm, live, N = out["maps"]
+    if not np.array_equal(Cm, lin["corr_map"]):
+        pytest.skip("association differs at a near-tie; covered by the previous test")
+    r, J = out["jac"]
+    ci = lin["corr_idx"]
+    assert np.max(np.abs(r[ci] - lin["r_data"])) < 2e-6
+    other = np.setdiff1d(np.arange(r.size), ci)
+    assert np.all(r[other] == 0) and np.all(J[other] == 0)
+    scale = np.abs(lin["J_data"]).max()
+    assert np.max(np.abs(J[ci] - lin["J_data"])) < 1e-4 * scale
+    blocks, gg, delta = out["system"]
+    rp, cols = out["pattern"]
+    Ad = A.toarray()
+    ref = np.stack([Ad[6 * k:6 * k + 6, 6 * c:6 * c + 6]
+                    for k in range(rp.size - 1) for c in cols[rp[k]:rp[k + 1]]])
+    assert np.linalg.norm(blocks - ref) <= 1e-5 * np.linalg.norm(ref)
+    # every nonzero block of the oracle's matrix is in the pattern
+    mask = np.zeros((rp.size - 1, rp.size - 1), bool)
+    for k in range(rp.size - 1):
+        mask[k, cols[rp[k]:rp[k + 1]]] = True
+    nzb = np.abs(Ad).reshape(rp.size - 1, 6, rp.size - 1, 6).sum(axis=(1, 3)) > 0
+    assert not np.any(nzb & ~(mask | mask.T))
+    assert np.linalg.norm(gg.ravel() - g) <= 1e-4 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("name", ["tiny", "c1"])
+def test_frame_solve_matches_oracle_pcg(swgn, scene_cache, name):
+    s = scene_cache(name)
+    st = stream_for(swgn, s)
+    stats = st.solve_frame(s.depth)
+    got = st.node_se3()
+    st.close()
+    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg")
+    ang, dpos = se3_errors(got, want, s.node_pos)
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
+    e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
+    e_ref = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
+    assert np.allclose(e_gpu, e_ref, rtol=1e-4)
+    assert abs(stats["n_corr"][0] - tr["n_corr"][0]) <= 2
