@@ -1,0 +1,204 @@
+"""Benchmark: Gauss-Newton frame solves per second on the 640x480 workload.
+
+One step = one whole frame solve (10 GN x 10 PCG iterations over ~250k
+surfels and ~1.8k nodes: depth normals, warp + index map, correspondence +
+Jacobians, assembly, block-Jacobi + PCG + node update), with the depth frame
+and all stream state resident in HBM. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "assemble", "pcg_init", "pcg_spmv", "pcg_update",
+           "node_update"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-gn-iters", type=int, default=2,
+                    help="oracle Gauss-Newton iterations timed for the CPU baseline")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_bytes(ns, nn, nb, ne, npx, pcg_iters):
+    """Algorithmic bytes per launch of each kernel (fp32 Jacobians): the data
+    each kernel must move at minimum, node tables counted once."""
+    return {
+        # depth in, normal map out, index map reset
+        "depth_prep": 28.0 * npx,
+        # per surfel: position 12, node ids 16, weights 16, index 4; atomic 8
+        "warp_zbuf": 56.0 * ns + 32.0 * nn,
+        # per surfel: position + normal 24, node ids 16, weights 16, index 4,
+        # index map 8, normal map 16; Jacobian + residual out 100
+        "corr_jac": 184.0 * ns + 48.0 * nn,
+        # Jacobians + residuals in once, run entries, blocks + gradient out
+        "assemble": 100.0 * ns + 4.0 * ne + 144.0 * nb + 24.0 * nn,
+        # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
+        "pcg_init": 144.0 * nn + 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
+        # upper blocks once (each is used for a row and, transposed, a column),
+        # z and p_old in, p and q out
+        "pcg_spmv": 144.0 * nb + 4 * 24.0 * nn,
+        # x, r, q, p and the inverses in; x, r, z out
+        "pcg_update": 4 * 24.0 * nn + 288.0 * nn + 3 * 24.0 * nn,
+        # twist in; node state and tables out; index map reset
+        "node_update": 24.0 * nn + 32.0 * nn + 96.0 * nn + 8.0 * npx,
+    }
+
+
+def cpu_baseline(scene, gn_iters):
+    """The FP64 oracle timed on this host: one frame's depth preparation and a
+    bounded number of its Gauss-Newton iterations, scaled to frames/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import solve as S
+    from oracle.quat import se3_to_rt
+
+    p = scene.params
+    pb = S.make_problem(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos,
+                        scene.depth, p)                        # skinning: setup, untimed
+    t0 = time.perf_counter()
+    pb2 = S.make_problem(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos,
+                         scene.depth, p, idx=pb.idx, w=pb.w, nbr=pb.nbr)
+    t_prep = time.perf_counter() - t0
+    R, t = se3_to_rt(S.identity_se3(scene.node_pos.shape[0]))
+    t0 = time.perf_counter()
+    for _ in range(gn_iters):
+        lin = S.linearize(pb2, R, t)
+        A, g = S.normal_equations(pb2, lin)
+        delta = S.solve_pcg(A, g, p.pcg_iters)
+        R, t = S.update_nodes(pb2.node_pos, R, t, delta)
+    t_iter = (time.perf_counter() - t0) / gn_iters
+    frame_s = t_prep + p.gn_iters * t_iter
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": round(1.0 / frame_s, 5), "unit": "frames/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"640x480 workload: depth preparation + {gn_iters} of {p.gn_iters} Gauss-Newton "
+                      f"iterations (sparse J^T J, block-Jacobi PCG x{p.pcg_iters}, FP64) timed, "
+                      f"scaled to one frame ({frame_s:.2f} s/frame); skinning excluded as setup",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: a depth stream's solve is not split across GPUs "
+              "(streams shard across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from gen.scenes import make_scene
+    from paper_1904_13073_amd import swgn
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    scene = make_scene("c2")
+    p = scene.params
+    ns, nn = scene.surfel_pos.shape[0], scene.node_pos.shape[0]
+    print(f"[bench] 640x480 workload: {ns} surfels, {nn} nodes, {p.gn_iters} GN x {p.pcg_iters} PCG",
+          file=sys.stderr, flush=True)
+    hip_stream = torch.cuda.current_stream().cuda_stream
+
+    def make_stream(**over):
+        st = swgn.Stream(swgn.config_for(scene, **over), hip_stream=hip_stream)
+        st.set_reference_surfels(torch.from_numpy(scene.surfel_pos).to(dev),
+                                 torch.from_numpy(scene.surfel_nrm).to(dev))
+        st.set_node_graph(torch.from_numpy(scene.node_pos).to(dev))
+        return st
+
+    depth = torch.from_numpy(scene.depth).to(dev)
+    st = make_stream()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        st.solve_frame(depth, with_stats=False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        st.solve_frame(depth, with_stats=False)
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fps = args.steps / elapsed
+    _, _, nb = st.sizes()
+    idx4, _ = st.skinning()
+    nruns = int(np.unique(np.sort(idx4, axis=1), axis=0).shape[0])   # surfel runs sharing a node set
+    st.close()
+    print(f"[bench] {args.steps} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # per-kernel times: HIP events around every launch on the solve's stream
+    tst = make_stream(stage_timing=1)
+    reps = max(5, min(50, args.steps))
+    tot = np.zeros(len(KERNELS))
+    stats = None
+    for _ in range(reps):
+        stats = tst.solve_frame(depth)
+        tot += np.array(stats["stage_us"])
+    tst.close()
+    per_frame_us = tot / reps
+    G, Pi = p.gn_iters, p.pcg_iters
+    launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G], dtype=float)
+    per_launch_us = per_frame_us / launches
+    kb = kernel_bytes(ns, nn, nb, 10 * nruns, scene.cam.width * scene.cam.height, p.pcg_iters)
+    dom = int(np.argmax(per_frame_us))
+    name = KERNELS[dom]
+    achieved = kb[name] / (per_launch_us[dom] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": kb[name], "avg_launch_us": round(float(per_launch_us[dom]), 3)}
+
+    out = {
+        "metric": "GN frame solves/s at 640x480 ~2k nodes; p50/p99 solve latency, served vs plain",
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "640x480 depth (f=570), 3 spheres + bumpy plane, plain single stream",
+                   "surfels": ns, "nodes": nn, "blocks": nb, "surfel_runs": nruns, "gn_iters": p.gn_iters,
+                   "pcg_iters": p.pcg_iters, "mode": "plain"},
+        "latency_ms": {"p50": round(1000 * percentile(lat, 0.5), 4),
+                       "p99": round(1000 * percentile(lat, 0.99), 4)},
+        "kernel_us_per_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, per_frame_us)},
+        "roofline": roofline,
+        "n_corr": stats["n_corr"][-1],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_gn_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,7 @@ typedef struct sw_config {
     int32_t jac_dtype;         /* Jacobian storage: 0 = fp32 */
     int32_t dot_fp64;          /* 1 = accumulate PCG dot products in fp64 (default 1) */
     int32_t debug_iter;        /* -1 = capture nothing; k = capture GN iteration k */
-    int32_t stage_timing;      /* 1 = time stages with HIP events into stage_us */
+    int32_t stage_timing;      /* 1 = time every kernel with HIP events into stage_us */
 } sw_config;
 
 /* Per-frame statistics, one entry per Gauss-Newton iteration (<= 16). */
@@ -64,8 +64,12 @@ typedef struct sw_frame_stats {
     float e_reg[16];           /* E_regulation (unweighted) at the same point */
     int32_t n_corr[16];        /* correspondences |P| */
     float pcg_resid[16];       /* |r| of the linear system when PCG stops */
-    float stage_us[12];        /* with stage_timing: depth, warp, corr, assemble,
-                                  jacobi, pcg, update (microseconds, summed) */
+    float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
+                                  over the frame: [0] depth preprocessing, [1] warp +
+                                  index map, [2] correspondence + Jacobians,
+                                  [3] assembly, [4] block-Jacobi + PCG start,
+                                  [5] PCG products, [6] PCG updates, [7] node
+                                  update; measured with HIP events */
     double alg_bytes;          /* algorithmic bytes moved by the frame (model) */
 } sw_frame_stats;
 

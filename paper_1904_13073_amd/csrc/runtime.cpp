@@ -2,6 +2,7 @@
 // pipeline and the per-frame Gauss-Newton driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -63,10 +64,7 @@ int pow2_at_least(int64_t n, int lo) {
 
 bool finite(float v) { return std::isfinite(v); }
 
-struct IterStatsHost {
-    double e_data, e_reg, pcg_resid;
-    int n_corr, pad;
-};
+using IterStatsHost = IterStats;
 
 }  // namespace
 
@@ -113,6 +111,7 @@ struct sw_stream_s {
     int* part_n;
     float *x, *r, *z, *q, *p0, *p1;
     double *sc, *part_rho, *part_rr, *part_pq;
+    int* offlist;
     // captured iteration
     float *dbg_live, *dbg_H, *dbg_g, *dbg_x, *dbg_J, *dbg_res;
     bool captured = false;
@@ -310,10 +309,13 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     size_t n6 = 6 * (size_t)nn;
     s->x = G.alloc<float>(n6); s->r = G.alloc<float>(n6); s->z = G.alloc<float>(n6); s->q = G.alloc<float>(n6);
     s->p0 = G.alloc<float>(n6); s->p1 = G.alloc<float>(n6);
+    const int nparts = solve_partials_size(nn);
     s->sc = G.alloc<double>(2 * (kMaxPcg + 1));
-    s->part_rho = G.alloc<double>(pcg_update_blocks(nn));
-    s->part_rr = G.alloc<double>(pcg_update_blocks(nn));
-    s->part_pq = G.alloc<double>(pcg_spmv_blocks(nn));
+    s->part_rho = G.alloc<double>(nparts);
+    s->part_rr = G.alloc<double>(nparts);
+    s->part_pq = G.alloc<double>(nparts);
+    s->offlist = G.alloc<int>(std::max(1, s->nb - nn));
+    launch_offlist(s->nb, s->blk_row, s->col_idx, s->offlist, st);
     s->dbg_live = G.alloc<float>(3 * (size_t)ns);
     s->dbg_H = G.alloc<float>(36 * (size_t)s->nb);
     s->dbg_g = G.alloc<float>(n6);
@@ -412,7 +414,7 @@ sw_status sw_create_stream(const sw_config* cfg, void* hip_stream, sw_stream* ou
         s->dbg_index = s->frame_mem.alloc<int>(npx);
         s->dbg_corr = s->frame_mem.alloc<int>(npx);
         s->flags = s->frame_mem.alloc<int>(4);
-        s->stats_d = s->frame_mem.alloc<char>(iter_stats_size() * kMaxIters);
+        s->stats_d = s->frame_mem.alloc<char>(sizeof(IterStats) * kMaxIters);
         void* h = nullptr;
         SWGN_HIP(hipHostMalloc(&h, sizeof(IterStatsHost) * kMaxIters + 64, hipHostMallocDefault));
         s->stats_h = static_cast<IterStatsHost*>(h);
@@ -496,8 +498,11 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
         const int npx = s->cam.W * s->cam.H;
         const bool timing = c.stage_timing != 0;
         size_t ev = 0;
-        auto mark = [&]() {
-            if (timing) SWGN_HIP(hipEventRecord(event_at(s, ev++), st));
+        std::vector<int> ev_kernel;
+        auto mark = [&](int kernel) {
+            if (!timing) return;
+            SWGN_HIP(hipEventRecord(event_at(s, ev++), st));
+            ev_kernel.push_back(kernel);
         };
         const float* d = depth;
         if (!on_device) {
@@ -506,51 +511,64 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
         }
         SWGN_HIP(hipMemcpyAsync(s->rq_bak, s->rq, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
         SWGN_HIP(hipMemcpyAsync(s->tt_bak, s->tt, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
-        launch_fill_i32(s->flags, 4, 0, st);
-        mark();
-        launch_depth_prep(s->cam, d, c.edge_gate, s->nmap, st);
-        mark();
+        mark(0);
+        launch_depth_prep(s->cam, d, c.edge_gate, s->nmap, s->zbuf, s->flags, st);
+        mark(-1);
         const SurfelView sv = surfel_view(s);
         const float dist2 = c.corr_dist * c.corr_dist;
         char* stats_d = static_cast<char*>(s->stats_d);
-        const size_t iss = iter_stats_size();
-        AssembleArgs aa{s->nb, nn, s->pitch, s->blk_row, s->col_idx, s->ent_ptr, s->ent, s->run_start, s->J, s->res,
-                        s->nbr, s->pref, s->rq, s->cl, s->frow_ptr, s->fcol, c.lambda_reg, c.damping, s->H, s->g,
-                        s->ereg};
-        PcgArgs pa{nn, s->g, s->H, s->frow_ptr, s->fblk, s->fcol, s->Minv, s->x, s->r, s->z, s->q, s->p0, s->p1,
-                   s->sc, s->part_rho, s->part_rr, s->part_pq};
+        const size_t iss = sizeof(IterStats);
+        AssembleArgs aa{s->nb, nn, s->pitch, s->blk_row, s->col_idx, s->row_ptr, s->offlist, s->ent_ptr, s->ent,
+                        s->run_start, s->J, s->res, s->nbr, s->pref, s->rq, s->cl, s->frow_ptr, s->fcol,
+                        c.lambda_reg, c.damping, s->H, s->g, s->ereg};
+        SolveStepArgs sa{nn, npx, s->row_ptr, s->H, s->g, s->frow_ptr, s->fblk, s->fcol, s->Minv,
+                         s->x, s->r, s->z, s->q, s->p0, s->p1, s->sc, s->part_rho, s->part_rr, s->part_pq, s->flags,
+                         s->part_e, s->part_n, corr_blocks(ns), s->ereg, nullptr, s->pref, s->rq, s->tt, s->dq,
+                         s->cl, s->zbuf};
         bool capture_done = false;
         for (int it = 0; it < c.gn_iters; ++it) {
             const bool cap = (it == c.debug_iter);
-            launch_clear_z(s->zbuf, npx, st);
+            mark(1);
             launch_warp_zbuf(ns, sv, s->dq, s->cam, s->zbuf, st);
-            mark();
+            mark(-1);
             if (cap) {
                 launch_export_index_map(npx, s->zbuf, s->dbg_index, st);
                 launch_fill_i32(s->dbg_corr, npx, -1, st);
             }
+            mark(2);
             launch_corr_jac(ns, sv, s->dq, s->cl, s->cam, s->zbuf, s->nmap, dist2, c.corr_normal, s->J, s->res,
                             s->pitch, s->part_e, s->part_n, cap ? s->dbg_corr : nullptr,
                             cap ? s->dbg_live : nullptr, st);
-            mark();
+            mark(-1);
+            mark(3);
             launch_assemble(aa, st);
-            mark();
-            launch_jacobi(nn, s->row_ptr, s->H, s->Minv, s->flags, s->part_e, s->part_n, corr_blocks(ns), s->ereg,
-                          stats_d + iss * it, st);
-            mark();
-            launch_pcg(pa, c.pcg_iters, st);
-            mark();
+            mark(-1);
             if (cap) {
-                SWGN_HIP(hipMemcpyAsync(s->dbg_H, s->H, sizeof(float) * 36 * s->nb, hipMemcpyDeviceToDevice, st));
-                SWGN_HIP(hipMemcpyAsync(s->dbg_g, s->g, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, st));
-                SWGN_HIP(hipMemcpyAsync(s->dbg_x, s->x, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, st));
+                // the solve step updates the node state: keep this iteration's system first
                 SWGN_HIP(hipMemcpyAsync(s->dbg_J, s->J, sizeof(float) * 24 * s->pitch, hipMemcpyDeviceToDevice, st));
                 SWGN_HIP(hipMemcpyAsync(s->dbg_res, s->res, sizeof(float) * s->pitch, hipMemcpyDeviceToDevice, st));
+                SWGN_HIP(hipMemcpyAsync(s->dbg_H, s->H, sizeof(float) * 36 * s->nb, hipMemcpyDeviceToDevice, st));
+                SWGN_HIP(hipMemcpyAsync(s->dbg_g, s->g, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, st));
+            }
+            sa.stats = stats_d + iss * it;
+            mark(4);
+            launch_pcg_init(sa, st);
+            mark(-1);
+            for (int pit = 0; pit < c.pcg_iters; ++pit) {
+                mark(5);
+                launch_pcg_spmv(sa, pit, st);
+                mark(-1);
+                mark(6);
+                launch_pcg_update(sa, pit, st);
+                mark(-1);
+            }
+            mark(7);
+            launch_node_update(sa, c.pcg_iters, st);
+            mark(-1);
+            if (cap) {
+                SWGN_HIP(hipMemcpyAsync(s->dbg_x, s->x, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, st));
                 capture_done = true;
             }
-            launch_node_update(nn, s->x, s->pref, s->rq, s->tt, s->dq, s->cl, s->part_rr, pcg_update_blocks(nn),
-                               stats_d + iss * it, s->flags, st);
-            mark();
         }
         SWGN_HIP(hipGetLastError());
         const int G = c.gn_iters;
@@ -577,17 +595,12 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
                 stats->n_corr[it] = h.n_corr;
                 stats->pcg_resid[it] = (float)h.pcg_resid;
             }
-            if (timing && ev > 1) {
-                // stage order per iteration: warp, corr, assemble, jacobi, pcg, update
-                float ms = 0.f;
-                SWGN_HIP(hipEventElapsedTime(&ms, s->events[0], s->events[1]));
-                stats->stage_us[0] = 1000.f * ms;
-                for (int it = 0; it < G; ++it) {
-                    for (int k = 0; k < 6; ++k) {
-                        size_t a = 1 + 6 * (size_t)it + k;
-                        SWGN_HIP(hipEventElapsedTime(&ms, s->events[a], s->events[a + 1]));
-                        stats->stage_us[1 + k] += 1000.f * ms;
-                    }
+            if (timing) {
+                // events come in (start of kernel id, end) pairs
+                for (size_t a = 0; a + 1 < ev; a += 2) {
+                    float ms = 0.f;
+                    SWGN_HIP(hipEventElapsedTime(&ms, s->events[a], s->events[a + 1]));
+                    stats->stage_us[ev_kernel[a]] += 1000.f * ms;
                 }
             }
             stats->alg_bytes = model_bytes(s, ncorr_total);

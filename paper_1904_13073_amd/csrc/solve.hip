@@ -1,0 +1,333 @@
+// Linear solve and node update of one Gauss-Newton iteration (Sec. 7, Sec. 8):
+//
+//   pcg_init     block-Jacobi preconditioner (FP64 inverses of H_kk + mu I) and
+//                the start of preconditioned conjugate gradients on
+//                (J^T J + mu I) delta = -g: r = -g, z = M r, p = z, x = 0
+//   pcg_spmv     q = A p with p = z + beta p_old formed on the fly (one wave per
+//                block row)
+//   pcg_update   x += alpha p, r -= alpha q, z = M r (8 lanes per node)
+//   node_update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
+//                and the reset of the index map for the next iteration
+//
+// PCG runs a fixed number of iterations and stops early only if rho = r^T z is
+// exactly 0. Its scalars never leave the device: every workgroup sums the same
+// per-workgroup partials (FP64) in the same order, so all workgroups take
+// identical decisions and a solve is bit-reproducible.
+#include <algorithm>
+
+#include "swgn_impl.h"
+#include "swgn_launch.h"
+
+namespace swgn {
+
+namespace {
+
+struct SolveArgs {
+    int nn, npx;
+    const int* row_ptr;
+    const float* H;
+    const float* g;
+    const int* frow_ptr;
+    const uint32_t* fblk;
+    const int* fcol;
+    double* Minv;
+    float *x, *r, *z, *q, *p0, *p1;
+    double* sc;          // sc[2 it] = rho_it
+    double* part_rho;    // per-workgroup partials of r.z (init or update)
+    double* part_rr;     // ... of r.r
+    double* part_pq;     // per-workgroup partials of p.q (spmv)
+    int* flags;
+    const double* part_e;
+    const int* part_n;
+    int nparts;
+    const float* ereg;
+    IterStats* stats;
+    const float4* pref;
+    float4 *rq, *tt, *dq, *cl;
+    unsigned long long* zbuf;
+};
+
+constexpr int kInitBlock = 64;
+constexpr int kUpdBlock = 256;      // 32 nodes x 8 lanes
+constexpr int kRowsPerSpmvBlock = 4;
+
+int init_blocks(int nn) { return (nn + kInitBlock - 1) / kInitBlock; }
+int upd_blocks(int nn) { return (8 * nn + kUpdBlock - 1) / kUpdBlock; }
+int spmv_blocks(int nn) { return (nn + kRowsPerSpmvBlock - 1) / kRowsPerSpmvBlock; }
+
+// FP64 inverse of a symmetric positive-definite 6x6 block (Cholesky, then
+// L^-T L^-1). Returns false (and the identity) if a pivot is not positive.
+__device__ bool spd_inverse6(const float* __restrict__ A, double* __restrict__ M) {
+    double L[6][6];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L[a][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double d = (double)A[c * 6 + c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) d -= L[c][t] * L[c][t];
+        ok = ok && (d > 0.0);
+        double lc = sqrt(ok ? d : 1.0);
+        L[c][c] = lc;
+#pragma unroll
+        for (int a = c + 1; a < 6; ++a) {
+            double v = (double)A[c * 6 + a];
+#pragma unroll
+            for (int t = 0; t < c; ++t) v -= L[a][t] * L[c][t];
+            L[a][c] = v / lc;
+        }
+    }
+    if (!ok) {
+#pragma unroll
+        for (int t = 0; t < 36; ++t) M[t] = (t % 7 == 0) ? 1.0 : 0.0;
+        return false;
+    }
+    double Li[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Li[a][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        Li[c][c] = 1.0 / L[c][c];
+#pragma unroll
+        for (int a = c + 1; a < 6; ++a) {
+            double v = 0.0;
+#pragma unroll
+            for (int t = c; t < a; ++t) v -= L[a][t] * Li[t][c];
+            Li[a][c] = v / L[a][a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int t = (a > c ? a : c); t < 6; ++t) v += Li[t][a] * Li[t][c];
+            M[a * 6 + c] = v;
+        }
+    return true;
+}
+
+__device__ __forceinline__ void apply_minv(const double* __restrict__ M, const float* r, float* z) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v += M[a * 6 + c] * (double)r[c];
+        z[a] = (float)v;
+    }
+}
+
+__device__ void update_node(const SolveArgs& a, int k) {
+    const float* x = a.x + 6 * k;
+    float3 w = make_float3(x[0], x[1], x[2]);
+    float3 tau = make_float3(x[3], x[4], x[5]);
+    float th = sqrtf(dot3(w, w));
+    Q4 e;
+    if (th < 1e-8f) {
+        e = Q4{1.f, 0.5f * w.x, 0.5f * w.y, 0.5f * w.z};
+    } else {
+        float sn, cs;
+        sincosf(0.5f * th, &sn, &cs);
+        float sc = sn / th;
+        e = Q4{cs, sc * w.x, sc * w.y, sc * w.z};
+    }
+    float en = sqrtf(((e.w * e.w + e.x * e.x) + e.y * e.y) + e.z * e.z);
+    e = Q4{e.w / en, e.x / en, e.y / en, e.z / en};
+    Q4 r = q4(a.rq[k]);
+    float4 t4 = a.tt[k];
+    float3 t = make_float3(t4.x, t4.y, t4.z);
+    float4 p = a.pref[k];
+    float3 c = add3(qrot(r.w, make_float3(r.x, r.y, r.z), make_float3(p.x, p.y, p.z)), t);
+    Q4 rn = qmul(e, r);
+    float nr = sqrtf(((rn.w * rn.w + rn.x * rn.x) + rn.y * rn.y) + rn.z * rn.z);
+    float sg = rn.w < 0.f ? -1.f : 1.f;
+    rn = Q4{sg * rn.w / nr, sg * rn.x / nr, sg * rn.y / nr, sg * rn.z / nr};
+    float3 tn = add3(add3(qrot(e.w, make_float3(e.x, e.y, e.z), sub3(t, c)), c), tau);
+    bool fin = fabsf(rn.w) <= 1.f && fabsf(tn.x) < INFINITY && fabsf(tn.y) < INFINITY && fabsf(tn.z) < INFINITY;
+    if (!fin) atomicOr(a.flags, 4);
+    a.rq[k] = f4(rn);
+    a.tt[k] = make_float4(tn.x, tn.y, tn.z, 0.f);
+    node_tables(p, rn, tn, a.dq, a.cl, k);
+}
+
+
+__global__ void __launch_bounds__(kInitBlock) k_pcg_init(SolveArgs a) {
+    __shared__ double sh[40];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double rho = 0.0, rr = 0.0;
+    if (k < a.nn) {
+        double* M = a.Minv + (size_t)k * 36;
+        if (!spd_inverse6(a.H + (size_t)a.row_ptr[k] * 36, M)) atomicOr(a.flags, 1);
+        float r[6], z[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r[c] = -a.g[6 * k + c];
+        apply_minv(M, r, z);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            a.r[6 * k + c] = r[c];
+            a.z[6 * k + c] = z[c];
+            a.p0[6 * k + c] = z[c];
+            a.x[6 * k + c] = 0.f;
+            rho += (double)r[c] * (double)z[c];
+            rr += (double)r[c] * (double)r[c];
+        }
+    }
+    rho = block_sum(rho, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        a.part_rho[blockIdx.x] = rho;
+        a.part_rr[blockIdx.x] = rr;
+    }
+    if (blockIdx.x == 0) {
+        // energies at this linearisation point
+        double e = 0.0, n = 0.0, er = 0.0;
+        for (int t = threadIdx.x; t < a.nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
+        for (int t = threadIdx.x; t < a.nn; t += blockDim.x) er += (double)a.ereg[t];
+        e = block_sum(e, sh);
+        n = block_sum(n, sh);
+        er = block_sum(er, sh);
+        if (threadIdx.x == 0) {
+            a.stats->e_data = e;
+            a.stats->e_reg = er;
+            a.stats->n_corr = (int)n;
+            if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a, int it, int n_rho_parts) {
+    __shared__ double sh[40];
+    const double rho = reduce_partials(a.part_rho, n_rho_parts, sh);
+    const bool stop = (rho == 0.0);
+    const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[2 * (it - 1)]) : 0.f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.sc[2 * it] = rho;
+    // p_it lives in p[it & 1]; p_0 was written by the init kernel
+    float* const pbuf[2] = {a.p0, a.p1};
+    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];   // p_{it-1} (p_0 at it = 0)
+    float* pcur = pbuf[it & 1];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int k = blockIdx.x * kRowsPerSpmvBlock + wave;
+    double pq = 0.0;
+    if (!stop && k < a.nn) {
+        const int sub = lane & 7, fl = lane >> 3;
+        float acc = 0.f;
+        if (sub < 6) {
+            const int f1 = a.frow_ptr[k + 1];
+            for (int f = a.frow_ptr[k] + fl; f < f1; f += 8) {
+                const uint32_t bb = a.fblk[f];
+                const int col = a.fcol[f];
+                const float* B = a.H + (size_t)(bb & ~kTransposed) * 36;
+                const bool tr = (bb & kTransposed) != 0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    float pc = it > 0 ? a.z[6 * col + c] + beta * pold[6 * col + c] : pold[6 * col + c];
+                    float h = tr ? B[c * 6 + sub] : B[sub * 6 + c];
+                    acc = fmaf(h, pc, acc);
+                }
+            }
+        }
+        acc += __shfl_xor(acc, 8, kWave);
+        acc += __shfl_xor(acc, 16, kWave);
+        acc += __shfl_xor(acc, 32, kWave);
+        if (lane < 6) {
+            const int t = 6 * k + lane;
+            const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
+            if (it > 0) pcur[t] = pk;
+            a.q[t] = acc;
+            pq = (double)pk * (double)acc;
+        }
+    }
+    pq = block_sum(pq, sh);
+    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = pq;
+}
+
+__global__ void __launch_bounds__(kUpdBlock) k_pcg_update(SolveArgs a, int it, int n_pq_parts) {
+    __shared__ double sh[40];
+    const double rho = a.sc[2 * it];
+    const bool stop = (rho == 0.0);
+    const double pq = reduce_partials(a.part_pq, n_pq_parts, sh);
+    const float* p = (it & 1) ? a.p1 : a.p0;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = gid >> 3, c = gid & 7;
+    const bool on = (k < a.nn) && (c < 6);
+    float rc = on ? a.r[6 * k + c] : 0.f;
+    double rz = 0.0, rr = 0.0;
+    if (!stop) {
+        const float alpha = (float)(rho / pq);
+        if (on) {
+            a.x[6 * k + c] = a.x[6 * k + c] + alpha * p[6 * k + c];
+            rc = rc - alpha * a.q[6 * k + c];
+            a.r[6 * k + c] = rc;
+        }
+        // z_c = sum_j M[c][j] r_j: the node's 6 residual entries from its lanes
+        const int base = (threadIdx.x & ~7);
+        double zc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            float rj = __shfl(rc, base + j, kWave);
+            if (on) zc += a.Minv[(size_t)k * 36 + c * 6 + j] * (double)rj;
+        }
+        if (on) {
+            const float zf = (float)zc;
+            a.z[6 * k + c] = zf;
+            rz = (double)rc * (double)zf;
+        }
+    }
+    if (on) rr = (double)rc * (double)rc;
+    rz = block_sum(rz, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        a.part_rho[blockIdx.x] = rz;
+        a.part_rr[blockIdx.x] = rr;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_node_update(SolveArgs a, int n_rr_parts) {
+    __shared__ double sh[40];
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.nn) update_node(a, gid);
+    if (gid < a.npx) a.zbuf[gid] = ~0ull;     // index map of the next iteration
+    if (blockIdx.x == 0) {
+        double rr = reduce_partials(a.part_rr, n_rr_parts, sh);
+        if (threadIdx.x == 0) a.stats->pcg_resid = sqrt(rr);
+    }
+}
+
+}  // namespace
+
+int solve_partials_size(int nn) { return std::max(std::max(init_blocks(nn), upd_blocks(nn)), spmv_blocks(nn)); }
+
+static SolveArgs solve_args(const SolveStepArgs& s) {
+    return SolveArgs{s.nn, s.npx, s.row_ptr, s.H, s.g, s.frow_ptr, s.fblk, s.fcol, s.Minv, s.x, s.r, s.z, s.q, s.p0,
+                     s.p1, s.sc, s.part_rho, s.part_rr, s.part_pq, s.flags, s.part_e, s.part_n, s.nparts, s.ereg,
+                     static_cast<IterStats*>(s.stats), s.pref, s.rq, s.tt, s.dq, s.cl, s.zbuf};
+}
+
+void launch_pcg_init(const SolveStepArgs& s, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(init_blocks(s.nn)), dim3(kInitBlock), 0, st, solve_args(s));
+}
+
+void launch_pcg_spmv(const SolveStepArgs& s, int it, hipStream_t st) {
+    const int n_rho = it == 0 ? init_blocks(s.nn) : upd_blocks(s.nn);
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(spmv_blocks(s.nn)), dim3(64 * kRowsPerSpmvBlock), 0, st, solve_args(s), it,
+                       n_rho);
+}
+
+void launch_pcg_update(const SolveStepArgs& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(upd_blocks(s.nn)), dim3(kUpdBlock), 0, st, solve_args(s), it,
+                       spmv_blocks(s.nn));
+}
+
+void launch_node_update(const SolveStepArgs& s, int pcg_iters, hipStream_t st) {
+    const int n_rr = pcg_iters == 0 ? init_blocks(s.nn) : upd_blocks(s.nn);
+    const int grid = (std::max(s.nn, s.npx) + 255) / 256;
+    hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(256), 0, st, solve_args(s), n_rr);
+}
+
+}  // namespace swgn

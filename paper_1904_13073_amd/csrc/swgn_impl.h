@@ -145,4 +145,89 @@ __device__ __forceinline__ float3 backproject(const Cam& c, int ux, int uy, floa
 
 __device__ __forceinline__ bool depth_ok(float d) { return (d > 0.f) && (d < INFINITY); }
 
+// Node dual quaternion (r, d = 1/2 (0,t) r) and live position c = R p + t.
+__device__ __forceinline__ void node_tables(float4 p, Q4 r, float3 t, float4* dq, float4* cl, int k) {
+    float3 u = make_float3(r.x, r.y, r.z);
+    float3 c = add3(qrot(r.w, u, make_float3(p.x, p.y, p.z)), t);
+    Q4 d = qmul(Q4{0.f, t.x, t.y, t.z}, r);
+    dq[2 * k] = f4(r);
+    dq[2 * k + 1] = make_float4(0.5f * d.w, 0.5f * d.x, 0.5f * d.y, 0.5f * d.z);
+    cl[k] = make_float4(c.x, c.y, c.z, 0.f);
+}
+
+// Per Gauss-Newton iteration statistics written by the device.
+struct IterStats {
+    double e_data, e_reg, pcg_resid;
+    int n_corr, pad;
+};
+
+// ---------------------------------------------------------------------------
+// Wave and block reductions (fixed butterfly order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_sumi(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Block sum over blockDim.x (multiple of 64, <= 1024) threads; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x / kWave;
+        for (int q = 0; q < nw; ++q) t += sh[q];
+    }
+    __syncthreads();
+    return t;
+}
+
+// Sum of n partials in a fixed order by one block; result valid in all threads.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    double t = block_sum(v, sh);
+    if (threadIdx.x == 0) sh[32] = t;
+    __syncthreads();
+    double r = sh[32];
+    __syncthreads();
+    return r;
+}
+
+// Cross-lane sums with DPP (gfx9): every lane of a 16-lane row ends with the
+// row's sum after mirror, half-mirror and two quad permutations. The order of
+// additions is fixed per lane, so results are reproducible.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp<0x140>(v);   // row_mirror
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// Sum over the whole wave (all lanes active), uniform result.
+__device__ __forceinline__ float wave64_sum(float v) {
+    v = row16_sum(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
 }  // namespace swgn

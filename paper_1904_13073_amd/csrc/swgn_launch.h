@@ -20,6 +20,8 @@ struct AssembleArgs {
     int nb, nn, pitch;
     const int* blk_row;
     const int* col_idx;
+    const int* row_ptr;
+    const int* offlist;
     const int* ent_ptr;
     const uint32_t* ent;
     const int* run_start;
@@ -37,17 +39,26 @@ struct AssembleArgs {
     float* ereg;
 };
 
-struct PcgArgs {
-    int nn;
-    const float* g;
+struct SolveStepArgs {
+    int nn, npx;
+    const int* row_ptr;
     const float* H;
+    const float* g;
     const int* frow_ptr;
     const uint32_t* fblk;
     const int* fcol;
-    const double* Minv;
+    double* Minv;
     float *x, *r, *z, *q, *p0, *p1;
-    double* sc;
-    double *part_rho, *part_rr, *part_pq;
+    double *sc, *part_rho, *part_rr, *part_pq;
+    int* flags;
+    const double* part_e;
+    const int* part_n;
+    int nparts;
+    const float* ereg;
+    void* stats;
+    const float4* pref;
+    float4 *rq, *tt, *dq, *cl;
+    unsigned long long* zbuf;
 };
 
 // setup
@@ -78,7 +89,8 @@ void launch_full_rows(int nn, int ntr, const int* row_ptr, const int* col_idx, c
                       hipStream_t st);
 
 // per frame
-void launch_depth_prep(const Cam& cam, const float* depth, float gate, float4* nmap, hipStream_t st);
+void launch_depth_prep(const Cam& cam, const float* depth, float gate, float4* nmap, unsigned long long* zbuf,
+                       int* flags, hipStream_t st);
 void launch_clear_z(unsigned long long* z, int n, hipStream_t st);
 void launch_warp_zbuf(int ns, const SurfelView& sv, const float4* dq, const Cam& cam, unsigned long long* z,
                       hipStream_t st);
@@ -86,20 +98,18 @@ int corr_blocks(int ns);
 void launch_corr_jac(int ns, const SurfelView& sv, const float4* dq, const float4* cl, const Cam& cam,
                      const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J, float* res,
                      int pitch, double* part_e, int* part_n, int* corr_map, float* live_pos, hipStream_t st);
+void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist, hipStream_t st);
 void launch_assemble(const AssembleArgs& a, hipStream_t st);
-void launch_jacobi(int nn, const int* row_ptr, const float* H, double* Minv, int* flags, const double* part_e,
-                   const int* part_n, int nparts, const float* ereg, void* stats, hipStream_t st);
-int pcg_update_blocks(int nn);
-int pcg_spmv_blocks(int nn);
-void launch_pcg(const PcgArgs& a, int iters, hipStream_t st);
-void launch_node_update(int nn, const float* x, const float4* pref, float4* rq, float4* tt, float4* dq, float4* cl,
-                        const double* part_rr, int nparts, void* stats, int* flags, hipStream_t st);
+int solve_partials_size(int nn);
+void launch_pcg_init(const SolveStepArgs& a, hipStream_t st);
+void launch_pcg_spmv(const SolveStepArgs& a, int it, hipStream_t st);
+void launch_pcg_update(const SolveStepArgs& a, int it, hipStream_t st);
+void launch_node_update(const SolveStepArgs& a, int pcg_iters, hipStream_t st);
 void launch_nodes_from_se3(int nn, const float* se3, const float4* pref, float4* rq, float4* tt, float4* dq,
                            float4* cl, hipStream_t st);
 void launch_node_se3_out(int nn, const float4* rq, const float4* tt, float* out, hipStream_t st);
 void launch_export_index_map(int npx, const unsigned long long* z, int* out, hipStream_t st);
 void launch_positions_to_f4(int n, const float* pos, float4* out, hipStream_t st);
-size_t iter_stats_size();
 
 }  // namespace swgn
 

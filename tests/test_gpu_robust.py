@@ -17,23 +17,23 @@ def test_call_order_and_arguments(swgn, scene_cache):
     st = swgn.Stream(swgn.config_for(s))
     with pytest.raises(swgn.SwError) as e:
         st.solve_frame(s.depth)
-    assert e.value.status == swgn.swgn.SW_ESTATE
+    assert e.value.status == swgn.SW_ESTATE
     with pytest.raises(swgn.SwError) as e:
         st.set_node_graph(s.node_pos)
-    assert e.value.status == swgn.swgn.SW_ESTATE
+    assert e.value.status == swgn.SW_ESTATE
     st.set_reference_surfels(s.surfel_pos, s.surfel_nrm)
     with pytest.raises(swgn.SwError) as e:
         st.set_node_graph(s.node_pos[:8])
-    assert e.value.status == swgn.swgn.SW_EINVAL
+    assert e.value.status == swgn.SW_EINVAL
     st.set_node_graph(s.node_pos)
     with pytest.raises(swgn.SwError) as e:
-        swgn.swgn.sw_set_node_se3(st.h, np.zeros((3, 12), np.float32))
-    assert e.value.status == swgn.swgn.SW_EINVAL
+        swgn.sw_set_node_se3(st.h, np.zeros((3, 12), np.float32))
+    assert e.value.status == swgn.SW_EINVAL
     # surfels set again invalidate the graph
     st.set_reference_surfels(s.surfel_pos, s.surfel_nrm)
     with pytest.raises(swgn.SwError) as e:
         st.solve_frame(s.depth)
-    assert e.value.status == swgn.swgn.SW_ESTATE
+    assert e.value.status == swgn.SW_ESTATE
     st.close()
 
 
