@@ -18,8 +18,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "assemble", "pcg_init", "pcg_spmv", "pcg_update",
-           "node_update"]
+KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "asm_segments", "pcg_init", "pcg_spmv", "pcg_update",
+           "node_update", "asm_fold"]
+SEG_LEN = 128     # surfels per segment at most (one node set)
+SEG_SLOTS = 400   # floats stored per segment
 
 
 def parse():
@@ -42,7 +44,7 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def kernel_bytes(ns, nn, nb, ne, npx, pcg_iters):
+def kernel_bytes(ns, nn, nb, nseg, npx, pcg_iters):
     """Algorithmic bytes per launch of each kernel (fp32 Jacobians): the data
     each kernel must move at minimum, node tables counted once."""
     return {
@@ -53,8 +55,10 @@ def kernel_bytes(ns, nn, nb, ne, npx, pcg_iters):
         # per surfel: position + normal 24, node ids 16, weights 16, index 4,
         # index map 8, normal map 16; Jacobian + residual out 100
         "corr_jac": 184.0 * ns + 48.0 * nn,
-        # Jacobians + residuals in once, run entries, blocks + gradient out
-        "assemble": 100.0 * ns + 4.0 * ne + 144.0 * nb + 24.0 * nn,
+        # Jacobians + residuals in once, per segment 10 Gram sub-blocks + J^T r out
+        "asm_segments": 100.0 * ns + 4.0 * SEG_SLOTS * nseg,
+        # per segment and block: entry, sub-block (and J^T r); blocks, gradient out
+        "asm_fold": 10.0 * nseg * (4.0 + 144.0) + 4 * 24.0 * nseg + 144.0 * nb + 28.0 * nn,
         # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
         "pcg_init": 144.0 * nn + 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
         # upper blocks once (each is used for a row and, transposed, a column),
@@ -147,7 +151,12 @@ def main():
     fps = args.steps / elapsed
     _, _, nb = st.sizes()
     idx4, _ = st.skinning()
-    nruns = int(np.unique(np.sort(idx4, axis=1), axis=0).shape[0])   # surfel runs sharing a node set
+    srt = np.sort(idx4, axis=1).astype(np.int64)
+    key = ((srt[:, 0] * nn + srt[:, 1]) * nn + srt[:, 2]) * nn + srt[:, 3]
+    ks = np.sort(key, kind="stable")
+    nruns = int(np.count_nonzero(np.r_[True, ks[1:] != ks[:-1]]))   # node sets
+    starts = np.r_[True, ks[1:] != ks[:-1]] | (np.arange(ks.size) % SEG_LEN == 0)
+    nseg = int(np.count_nonzero(starts))                              # assembly segments
     st.close()
     print(f"[bench] {args.steps} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
@@ -162,9 +171,9 @@ def main():
     tst.close()
     per_frame_us = tot / reps
     G, Pi = p.gn_iters, p.pcg_iters
-    launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G], dtype=float)
+    launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G, G], dtype=float)
     per_launch_us = per_frame_us / launches
-    kb = kernel_bytes(ns, nn, nb, 10 * nruns, scene.cam.width * scene.cam.height, p.pcg_iters)
+    kb = kernel_bytes(ns, nn, nb, nseg, scene.cam.width * scene.cam.height, p.pcg_iters)
     dom = int(np.argmax(per_frame_us))
     name = KERNELS[dom]
     achieved = kb[name] / (per_launch_us[dom] * 1e-6) / 1e9
@@ -186,7 +195,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "640x480 depth (f=570), 3 spheres + bumpy plane, plain single stream",
-                   "surfels": ns, "nodes": nn, "blocks": nb, "surfel_runs": nruns, "gn_iters": p.gn_iters,
+                   "surfels": ns, "nodes": nn, "blocks": nb, "node_sets": nruns, "segments": nseg, "gn_iters": p.gn_iters,
                    "pcg_iters": p.pcg_iters, "mode": "plain"},
         "latency_ms": {"p50": round(1000 * percentile(lat, 0.5), 4),
                        "p99": round(1000 * percentile(lat, 0.99), 4)},

@@ -67,9 +67,10 @@ typedef struct sw_frame_stats {
     float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
                                   over the frame: [0] depth preprocessing, [1] warp +
                                   index map, [2] correspondence + Jacobians,
-                                  [3] assembly, [4] block-Jacobi + PCG start,
-                                  [5] PCG products, [6] PCG updates, [7] node
-                                  update; measured with HIP events */
+                                  [3] assembly of chunk partials, [4] block-Jacobi +
+                                  PCG start, [5] PCG products, [6] PCG updates,
+                                  [7] node update, [8] assembly of the blocks;
+                                  measured with HIP events */
     double alg_bytes;          /* algorithmic bytes moved by the frame (model) */
 } sw_frame_stats;
 

@@ -1,17 +1,24 @@
 // Assembly of the Gauss-Newton system (Sec. 8: build J^T J, then solve):
 //   H = sum_i J_i^T J_i + lambda sum_edges J_e^T J_e + mu I   (6x6 node-pair blocks)
 //   g = sum_i J_i^T r_i + lambda sum_edges J_e^T r_e
-// over the upper block pattern. Data rows come from the per-surfel Jacobians
-// written by the correspondence kernel; regulariser rows (Sec. 7,
+// over the upper block pattern. Data rows are the per-surfel Jacobians written
+// by the correspondence kernel; regulariser rows (Sec. 7,
 // E_regulation = sum_j sum_{m in N_j} |T_j p_j - T_m p_j|^2) are formed here
 // from the node state.
 //
-// Work decomposition: a diagonal block (every surfel touching the node, a few
-// hundred) gets a whole wave; an off-diagonal block (the surfels shared by two
-// nodes, tens) gets a 16-lane row of a wave. Lanes walk the block's runs of
-// surfels (surfels sharing one node set are contiguous), accumulate in
-// registers with FMA, and finish with a DPP row reduction: no atomics, a fixed
-// summation order, one write per block.
+// Surfels are stored grouped by their set of 4 nodes, in segments of at most
+// 128 surfels with one node set. For a segment, every one of its 10 blocks is a
+// 6x6 sub-block of the Gram matrix G = [J | r]^T [J | r] over its surfels
+// (J the segment's n x 24 Jacobian), and g is G's column 24. So:
+//   1. one wave per segment accumulates G with the 32x32x2 FP32 MFMA, the sum
+//      over surfels being the MFMA's k dimension (2 surfels per instruction;
+//      the A and B operands are the same register: lane = Jacobian component,
+//      half-wave = surfel; a surfel's [J | r] is one 128-byte row), and stores
+//      the 10 upper sub-blocks and J^T r;
+//   2. a 16-lane group per block sums its segments' sub-blocks in a fixed
+//      order, adds the regulariser terms (edges spread over the lanes) and
+//      the damping, and finishes with a DPP row reduction.
+// Each Jacobian is read once; no atomics; results are reproducible.
 #include "swgn_impl.h"
 #include "swgn_launch.h"
 
@@ -19,33 +26,12 @@ namespace swgn {
 
 namespace {
 
-struct AsmIn {
-    int nb, nn, noff, pitch;
-    const int* blk_row;
-    const int* col_idx;
-    const int* row_ptr;
-    const int* offlist;
-    const int* ent_ptr;
-    const uint32_t* ent;
-    const int* run_start;
-    const float* J;
-    const float* res;
-    const int* nbr;
-    const float4* pref;
-    const float4* rq;
-    const float4* cl;
-    const int* frow_ptr;
-    const int* fcol;
-    float lambda, mu;
-    float* H;
-    float* g;
-    float* ereg;
-};
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float3 ld3(float4 a) { return make_float3(a.x, a.y, a.z); }
 
 // y = R_m (p_j - p_m), r_jm = c_j - c_m - y
-__device__ __forceinline__ void arap_edge(const AsmIn& in, int j, int m, float3& y, float3& r) {
+__device__ __forceinline__ void arap_edge(const AssembleArgs& in, int j, int m, float3& y, float3& r) {
     float3 pj = ld3(in.pref[j]), pm = ld3(in.pref[m]);
     float4 q = in.rq[m];
     y = qrot(q.x, make_float3(q.y, q.z, q.w), sub3(pj, pm));
@@ -59,166 +45,151 @@ __device__ __forceinline__ bool has_edge(const int* __restrict__ nbr, int j, int
     return e;
 }
 
-// Walk the surfels of block b's runs with `width` lanes (lane index g within
-// the group) and call f(surfel, pos_a, pos_b) for each.
-template <int WIDTH, class F>
-__device__ __forceinline__ void for_block_surfels(const AsmIn& in, int e0, int e1, int g, F&& f) {
-    for (int eb = e0; eb < e1; eb += WIDTH) {
-        int j = eb + g;
-        bool have = j < e1;
-        uint32_t e = have ? in.ent[j] : 0u;
-        int run = (int)(e >> 4);
-        int st = have ? in.run_start[run] : 0;
-        int len = have ? in.run_start[run + 1] - st : 0;
-        int pp = (int)(e & 15u);
-        int incl = len;
+// slot of the upper sub-block (pa <= pb) among the 10 of a segment
+__device__ __forceinline__ int sub_block(int pa, int pb) {
+    const int first[4] = {0, 4, 7, 9};
+    return first[pa] + (pb - pa);
+}
+
+// Level 1: one wave per segment.
+__global__ void __launch_bounds__(256) k_asm_segments(AssembleArgs in) {
+    __shared__ float stage[4][kSegSlots];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int seg = blockIdx.x * 4 + wave;
+    const bool active = seg < in.nseg;
+    const int s0 = active ? in.seg_start[seg] : 0;
+    const int s1 = active ? in.seg_start[seg + 1] : 0;
+    const int comp = lane & 31, half = lane >> 5;
+    // lane's column of [J | r | 0]: a surfel's row is one 128-byte line, so an
+    // MFMA step reads two full lines
+    const float* src = in.J + comp;
+    f32x16 acc;
 #pragma unroll
-        for (int o = 1; o < WIDTH; o <<= 1) {
-            int t = __shfl_up(incl, o, WIDTH);
-            if (g >= o) incl += t;
-        }
-        int total = __shfl(incl, WIDTH - 1, WIDTH);
-        for (int f0 = 0; f0 < total; f0 += WIDTH) {
-            int fl = f0 + g;
-            int lo = 0, hi = WIDTH - 1;
+    for (int t = 0; t < 16; ++t) acc[t] = 0.f;
+    const int n = s1 - s0;                 // wave-uniform
+    for (int m0 = 0; m0 < n; m0 += 16) {   // 8 MFMA steps, loads issued first
+        float v[8];
 #pragma unroll
-            for (int s = 1; s < WIDTH; s <<= 1) {
-                int mid = (lo + hi) >> 1;
-                int v = __shfl(incl, mid, WIDTH);
-                if (v > fl) hi = mid; else lo = mid + 1;
-            }
-            int inc_j = __shfl(incl, lo, WIDTH);
-            int len_j = __shfl(len, lo, WIDTH);
-            int st_j = __shfl(st, lo, WIDTH);
-            int pp_j = __shfl(pp, lo, WIDTH);
-            if (fl < total) f(st_j + (fl - (inc_j - len_j)), pp_j >> 2, pp_j & 3);
+        for (int q = 0; q < 8; ++q) {
+            const int s = s0 + m0 + 2 * q + half;   // surfel of this half-wave
+            v[q] = s < s1 ? src[(size_t)s * 32] : 0.f;
         }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
+    }
+    // accumulator element t of lane l is G[i][j], j = l % 32,
+    // i = (t / 4) * 8 + (l / 32) * 4 + t % 4
+    float* sg = stage[wave];
+    const int j = comp;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int i = (t >> 2) * 8 + half * 4 + (t & 3);
+        if (i < 24 && j < 24) {
+            const int pa = i / 6, pb = j / 6;
+            if (pa <= pb) sg[sub_block(pa, pb) * 36 + (i % 6) * 6 + (j % 6)] = acc[t];
+        } else if (j == 24 && i <= 24) {
+            sg[360 + i] = acc[t];            // J^T r (i < 24), r^T r (i = 24)
+        }
+    }
+    __syncthreads();
+    if (active) {
+        float4* dst = reinterpret_cast<float4*>(in.part + (size_t)seg * kSegSlots);
+        const float4* from = reinterpret_cast<const float4*>(sg);
+        for (int q = lane; q < kSegSlots / 4; q += kWave) dst[q] = from[q];
     }
 }
 
-__global__ void __launch_bounds__(256) k_assemble(AsmIn in, int n_diag_wg) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const size_t P = (size_t)in.pitch;
+// Level 2: one 16-lane group per block; diagonal blocks first (node order),
+// then the off-diagonal ones.
+__global__ void __launch_bounds__(256) k_asm_fold(AssembleArgs in) {
+    const int lane = threadIdx.x % kWave, g = lane & 15;
+    const int gi = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool active = gi < in.nn + in.noff;
+    const bool diag = gi < in.nn;
+    const int b = !active ? 0 : (diag ? in.row_ptr[gi] : in.offlist[gi - in.nn]);
+    const int k = in.blk_row[b], l = in.col_idx[b];
     const float lam = in.lambda;
-    if ((int)blockIdx.x < n_diag_wg) {
-        // ---------------- diagonal block of node k: one wave ----------------
-        const int k = blockIdx.x * 4 + wave;
-        if (k >= in.nn) return;
-        const int b = in.row_ptr[k];
-        float acc[21];   // upper triangle, row-major (a <= c)
-        float gacc[6];
-        float er = 0.f;
+    float acc[36];
+    float gacc[6];
+    float er = 0.f;
 #pragma unroll
-        for (int t = 0; t < 21; ++t) acc[t] = 0.f;
+    for (int t = 0; t < 36; ++t) acc[t] = 0.f;
 #pragma unroll
-        for (int t = 0; t < 6; ++t) gacc[t] = 0.f;
-        for_block_surfels<kWave>(in, in.ent_ptr[b], in.ent_ptr[b + 1], lane, [&](int s, int pa, int) {
-            const float* Ja = in.J + (size_t)(pa * 6) * P + s;
-            float x[6];
+    for (int t = 0; t < 6; ++t) gacc[t] = 0.f;
+    const int e0 = active ? in.ent_ptr[b] : 0, e1 = active ? in.ent_ptr[b + 1] : 0;
+    for (int e = e0 + g; e < e1; e += 16) {
+        const uint32_t v = in.ent[e];
+        const int seg = (int)(v >> 4), pa = (int)((v >> 2) & 3u), pb = (int)(v & 3u);
+        const float* base = in.part + (size_t)seg * kSegSlots;
+        const float4* blk = reinterpret_cast<const float4*>(base + sub_block(pa, pb) * 36);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) x[c] = Ja[c * P];
-            float rr = in.res[s];
-            int t = 0;
+        for (int q = 0; q < 9; ++q) {
+            const float4 t4 = blk[q];
+            acc[4 * q] += t4.x; acc[4 * q + 1] += t4.y; acc[4 * q + 2] += t4.z; acc[4 * q + 3] += t4.w;
+        }
+        if (diag) {
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-#pragma unroll
-                for (int c = a; c < 6; ++c, ++t) acc[t] = fmaf(x[a], x[c], acc[t]);
-                gacc[a] = fmaf(x[a], rr, gacc[a]);
-            }
-        });
-        // regulariser: out-edges k -> m (J_k = [0 | I]) on lanes 0..7
-        if (lane < 8) {
+            for (int c = 0; c < 6; ++c) gacc[c] += base[360 + 6 * pa + c];
+        }
+    }
+    if (active && diag) {
+        if (g < 8) {                          // out-edge k -> m: J_k = [0 | I]
             float3 y, r;
-            arap_edge(in, k, in.nbr[8 * k + lane], y, r);
-            acc[15] += lam; acc[18] += lam; acc[20] += lam;      // (3,3) (4,4) (5,5)
+            arap_edge(in, k, in.nbr[8 * k + g], y, r);
+            acc[21] += lam; acc[28] += lam; acc[35] += lam;
             gacc[3] += lam * r.x; gacc[4] += lam * r.y; gacc[5] += lam * r.z;
             er += dot3(r, r);
         }
-        // in-edges j -> k (J_k = [[y]x | -I]) over the node's neighbours
-        for (int f = in.frow_ptr[k] + lane; f < in.frow_ptr[k + 1]; f += kWave) {
-            int j = in.fcol[f];
-            if (j == k || !has_edge(in.nbr, j, k)) continue;
+        for (int f = in.in_ptr[k] + g; f < in.in_ptr[k + 1]; f += 16) {   // in-edge j -> k: J_k = [[y]x | -I]
             float3 y, r;
-            arap_edge(in, j, k, y, r);
-            float yy = dot3(y, y);
-            // [[|y|^2 I - y y^T, [y]x], [-[y]x, I]], upper triangle
-            acc[0] += lam * (yy - y.x * y.x); acc[1] += lam * (-y.x * y.y); acc[2] += lam * (-y.x * y.z);
-            acc[4] += lam * (-y.z); acc[5] += lam * (y.y);                          // (0,4) (0,5)
-            acc[6] += lam * (yy - y.y * y.y); acc[7] += lam * (-y.y * y.z);
-            acc[8] += lam * (y.z); acc[10] += lam * (-y.x);                         // (1,3) (1,5)
-            acc[11] += lam * (yy - y.z * y.z);
-            acc[12] += lam * (-y.y); acc[13] += lam * (y.x);                        // (2,3) (2,4)
-            acc[15] += lam; acc[18] += lam; acc[20] += lam;
-            float3 rxy = cross3(r, y);                                              // g += lambda [r x y; -r]
+            arap_edge(in, in.in_list[f], k, y, r);
+            const float yy = dot3(y, y);
+            // [[|y|^2 I - y y^T, [y]x], [-[y]x, I]]
+            const float a00 = lam * (yy - y.x * y.x), a01 = lam * (-y.x * y.y), a02 = lam * (-y.x * y.z);
+            const float a11 = lam * (yy - y.y * y.y), a12 = lam * (-y.y * y.z), a22 = lam * (yy - y.z * y.z);
+            acc[0] += a00; acc[1] += a01; acc[2] += a02;
+            acc[6] += a01; acc[7] += a11; acc[8] += a12;
+            acc[12] += a02; acc[13] += a12; acc[14] += a22;
+            const float sx = lam * y.x, sy = lam * y.y, sz = lam * y.z;
+            // top-right [y]x = [[0,-yz,yy],[yz,0,-yx],[-yy,yx,0]], bottom-left its transpose
+            acc[4] -= sz; acc[5] += sy; acc[9] += sz; acc[11] -= sx; acc[15] -= sy; acc[16] += sx;
+            acc[19] += sz; acc[20] -= sy; acc[24] -= sz; acc[26] += sx; acc[30] += sy; acc[31] -= sx;
+            acc[21] += lam; acc[28] += lam; acc[35] += lam;
+            const float3 rxy = cross3(r, y);  // g += lambda [r x y; -r]
             gacc[0] += lam * rxy.x; gacc[1] += lam * rxy.y; gacc[2] += lam * rxy.z;
             gacc[3] -= lam * r.x; gacc[4] -= lam * r.y; gacc[5] -= lam * r.z;
         }
+    } else if (active) {
+        if (g == 0 && has_edge(in.nbr, k, l)) {   // edge k -> l: J_k^T J_l = [0 0; [y]x -I]
+            float3 y, r;
+            arap_edge(in, k, l, y, r);
+            acc[19] += lam * (-y.z); acc[20] += lam * (y.y);
+            acc[24] += lam * (y.z);  acc[26] += lam * (-y.x);
+            acc[30] += lam * (-y.y); acc[31] += lam * (y.x);
+            acc[21] -= lam; acc[28] -= lam; acc[35] -= lam;
+        }
+        if (g == 1 && has_edge(in.nbr, l, k)) {   // edge l -> k: J_k^T J_l = [0 -[y]x; 0 -I]
+            float3 y, r;
+            arap_edge(in, l, k, y, r);
+            acc[4] += lam * (y.z);  acc[5] += lam * (-y.y);
+            acc[9] += lam * (-y.z); acc[11] += lam * (y.x);
+            acc[15] += lam * (y.y); acc[16] += lam * (-y.x);
+            acc[21] -= lam; acc[28] -= lam; acc[35] -= lam;
+        }
+    }
 #pragma unroll
-        for (int t = 0; t < 21; ++t) acc[t] = wave64_sum(acc[t]);
+    for (int t = 0; t < 36; ++t) acc[t] = row16_sum(acc[t]);
 #pragma unroll
-        for (int t = 0; t < 6; ++t) gacc[t] = wave64_sum(gacc[t]);
-        er = wave64_sum(er);
-        if (lane == 0) {
-            float Hb[36];
-            int t = 0;
+    for (int t = 0; t < 6; ++t) gacc[t] = row16_sum(gacc[t]);
+    er = row16_sum(er);
+    if (active && g == 0) {
+        if (diag) {
 #pragma unroll
-            for (int a = 0; a < 6; ++a)
-#pragma unroll
-                for (int c = a; c < 6; ++c, ++t) {
-                    Hb[a * 6 + c] = acc[t] + (a == c ? in.mu : 0.f);
-                    Hb[c * 6 + a] = Hb[a * 6 + c];
-                }
-            float4* out = reinterpret_cast<float4*>(in.H + (size_t)b * 36);
-#pragma unroll
-            for (int v = 0; v < 9; ++v) out[v] = make_float4(Hb[4 * v], Hb[4 * v + 1], Hb[4 * v + 2], Hb[4 * v + 3]);
+            for (int a = 0; a < 6; ++a) acc[7 * a] += in.mu;
 #pragma unroll
             for (int c = 0; c < 6; ++c) in.g[6 * k + c] = gacc[c];
             in.ereg[k] = er;
         }
-        return;
-    }
-    // ---------------- off-diagonal blocks: 16 lanes each ----------------
-    const int g = lane & 15;
-    const int oi = ((int)blockIdx.x - n_diag_wg) * 16 + wave * 4 + (lane >> 4);
-    const bool active = oi < in.noff;
-    const int b = active ? in.offlist[oi] : 0;
-    const int k = in.blk_row[b], l = in.col_idx[b];
-    float acc[36];
-#pragma unroll
-    for (int t = 0; t < 36; ++t) acc[t] = 0.f;
-    const int e0 = active ? in.ent_ptr[b] : 0, e1 = active ? in.ent_ptr[b + 1] : 0;
-    for_block_surfels<16>(in, e0, e1, g, [&](int s, int pa, int pb) {
-        const float* Ja = in.J + (size_t)(pa * 6) * P + s;
-        const float* Jb = in.J + (size_t)(pb * 6) * P + s;
-        float xa[6], xb[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) { xa[c] = Ja[c * P]; xb[c] = Jb[c * P]; }
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) acc[a * 6 + c] = fmaf(xa[a], xb[c], acc[a * 6 + c]);
-    });
-    if (active && g == 0 && has_edge(in.nbr, k, l)) {
-        // edge k -> l: J_k^T J_l = [0 0; [y]x -I]
-        float3 y, r;
-        arap_edge(in, k, l, y, r);
-        acc[19] += lam * (-y.z); acc[20] += lam * (y.y);
-        acc[24] += lam * (y.z);  acc[26] += lam * (-y.x);
-        acc[30] += lam * (-y.y); acc[31] += lam * (y.x);
-        acc[21] -= lam; acc[28] -= lam; acc[35] -= lam;
-    }
-    if (active && g == 1 && has_edge(in.nbr, l, k)) {
-        // edge l -> k: J_k^T J_l = [0 -[y]x; 0 -I]
-        float3 y, r;
-        arap_edge(in, l, k, y, r);
-        acc[4] += lam * (y.z);  acc[5] += lam * (-y.y);
-        acc[9] += lam * (-y.z); acc[11] += lam * (y.x);
-        acc[15] += lam * (y.y); acc[16] += lam * (-y.x);
-        acc[21] -= lam; acc[28] -= lam; acc[35] -= lam;
-    }
-#pragma unroll
-    for (int t = 0; t < 36; ++t) acc[t] = row16_sum(acc[t]);
-    if (active && g == 0) {
         float4* out = reinterpret_cast<float4*>(in.H + (size_t)b * 36);
 #pragma unroll
         for (int v = 0; v < 9; ++v) out[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
@@ -239,13 +210,13 @@ void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist
     hipLaunchKernelGGL(k_offlist, dim3((nb + 255) / 256), dim3(256), 0, st, nb, blk_row, col_idx, offlist);
 }
 
-void launch_assemble(const AssembleArgs& a, hipStream_t st) {
-    AsmIn in{a.nb, a.nn, a.nb - a.nn, a.pitch, a.blk_row, a.col_idx, a.row_ptr, a.offlist, a.ent_ptr, a.ent,
-             a.run_start, a.J, a.res, a.nbr, a.pref, a.rq, a.cl, a.frow_ptr, a.fcol, a.lambda, a.mu, a.H, a.g,
-             a.ereg};
-    int n_diag_wg = (a.nn + 3) / 4;
-    int n_off_wg = (a.nb - a.nn + 15) / 16;
-    hipLaunchKernelGGL(k_assemble, dim3(n_diag_wg + n_off_wg), dim3(256), 0, st, in, n_diag_wg);
+void launch_assemble_segments(const AssembleArgs& a, hipStream_t st) {
+    if (a.nseg > 0) hipLaunchKernelGGL(k_asm_segments, dim3((a.nseg + 3) / 4), dim3(256), 0, st, a);
+}
+
+void launch_assemble_fold(const AssembleArgs& a, hipStream_t st) {
+    const int groups = a.nn + a.noff;
+    hipLaunchKernelGGL(k_asm_fold, dim3((groups + 15) / 16), dim3(256), 0, st, a);
 }
 
 }  // namespace swgn

@@ -96,8 +96,7 @@ __global__ void __launch_bounds__(256) k_warp_zbuf(int ns, SurfelArrays s, const
 // Correspondence, residual and Jacobian
 // ---------------------------------------------------------------------------
 struct CorrOut {
-    float* J;              // [24][pitch]
-    float* res;            // [pitch]
+    float* J;              // [pitch][32]: 24 Jacobian entries (node position x 6), r, zero padding
     double* part_e;        // per block sum of r^2
     int* part_n;           // per block correspondence count
     int pitch;
@@ -175,22 +174,19 @@ __global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const 
         }
     }
     if (live) {
-        // store by node position within the surfel's ascending node set
+        // one 128-byte row per surfel, node blocks by position within the
+        // surfel's ascending node set, then the residual
         const int ids[4] = {id.x, id.y, id.z, id.w};
-        float* J = o.J;
-        int P = o.pitch;
+        float* row = o.J + (size_t)i * 32;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
-            float* Jp = J + (size_t)(pos * 6) * P + i;
-            Jp[0] = Jw[k][0];
-            Jp[(size_t)P] = Jw[k][1];
-            Jp[(size_t)2 * P] = Jw[k][2];
-            Jp[(size_t)3 * P] = Jt[k][0];
-            Jp[(size_t)4 * P] = Jt[k][1];
-            Jp[(size_t)5 * P] = Jt[k][2];
+            float2* Jp = reinterpret_cast<float2*>(row + pos * 6);
+            Jp[0] = make_float2(Jw[k][0], Jw[k][1]);
+            Jp[1] = make_float2(Jw[k][2], Jt[k][0]);
+            Jp[2] = make_float2(Jt[k][1], Jt[k][2]);
         }
-        o.res[i] = r;
+        row[24] = r;
         if (o.live_pos) {
             float nanv = __int_as_float(0x7fc00000);
             o.live_pos[3 * org + 0] = wp.ok ? wp.v.x : nanv;
@@ -303,10 +299,10 @@ int corr_blocks(int ns) { return (ns + 255) / 256; }
 
 void launch_corr_jac(int ns, const SurfelView& sv, const float4* dq, const float4* cl, const Cam& cam,
                      const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J,
-                     float* res, int pitch, double* part_e, int* part_n, int* corr_map, float* live_pos,
+                     int pitch, double* part_e, int* part_n, int* corr_map, float* live_pos,
                      hipStream_t st) {
     SurfelArrays s{sv.px, sv.py, sv.pz, sv.nx, sv.ny, sv.nz, sv.idx, sv.w, sv.orig};
-    CorrOut o{J, res, part_e, part_n, pitch, corr_map, live_pos};
+    CorrOut o{J, part_e, part_n, pitch, corr_map, live_pos};
     hipLaunchKernelGGL(k_corr_jac, dim3(corr_blocks(ns)), dim3(256), 0, st, ns, s, dq, cl, cam, z, nmap, dist2,
                        cosn, o);
 }

@@ -100,12 +100,20 @@ struct sw_stream_s {
     int4* sidx;
     float4* sw;
     int* sorig;
-    int* run_start;
     float4 *pref, *rq, *tt, *dq, *cl, *rq_bak, *tt_bak;
     int* nbr;
-    int *row_ptr, *col_idx, *blk_row, *ent_ptr, *frow_ptr, *fcol;
-    uint32_t *ent, *fblk;
-    float *J, *res, *H, *g, *ereg;
+    int *row_ptr, *col_idx, *blk_row;
+    int ell_w = 0;
+    uint32_t* ell_blk;
+    int* ell_col;
+    // assembly work lists: segments of surfels with one node set, per-block
+    // (segment, positions) entries, node in-edges
+    int* seg_start;
+    int* ent_ptr;
+    uint32_t* ent;
+    int *in_ptr, *in_list;
+    float* part;
+    float *J, *H, *g, *ereg;
     double* Minv;
     double* part_e;
     int* part_n;
@@ -113,7 +121,7 @@ struct sw_stream_s {
     double *sc, *part_rho, *part_rr, *part_pq;
     int* offlist;
     // captured iteration
-    float *dbg_live, *dbg_H, *dbg_g, *dbg_x, *dbg_J, *dbg_res;
+    float *dbg_live, *dbg_H, *dbg_g, *dbg_x, *dbg_J;
     bool captured = false;
 
     std::vector<hipEvent_t> events;
@@ -239,19 +247,20 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     s->sorig = G.alloc<int>(s->pitch);
     int* flag = tmp.alloc<int>(ns + 1);
     int* fpos = tmp.alloc<int>(ns + 1);
-    int* scan_tmp = tmp.alloc<int>(scan_tmp_size(std::max(ns, 16 * nn) + 16));
-    launch_permute_surfels(ns, key, val, s->in_pos, s->in_nrm, idx_in, w_in, s->spx, s->spy, s->spz, s->snx,
+    int* scan_tmp = tmp.alloc<int>(scan_tmp_size(std::max(10 * ns, 64 * nn) + 16));
+    launch_permute_surfels(ns, kSegLen, key, val, s->in_pos, s->in_nrm, idx_in, w_in, s->spx, s->spy, s->spz, s->snx,
                            s->sny, s->snz, s->sidx, s->sw, s->sorig, flag, st);
     exclusive_scan(flag, fpos, ns, scan_tmp, st);
     s->nruns = read_scalar(fpos + ns, st);
-    s->run_start = G.alloc<int>(s->nruns + 1);
-    launch_run_starts(ns, flag, fpos, s->run_start, st);
+    s->seg_start = G.alloc<int>(s->nruns + 1);
+    int* run_start = s->seg_start;    // segments: ranges of one node set, at most kSegLen long
+    launch_run_starts(ns, flag, fpos, run_start, st);
 
     // upper block pattern
     int words = (nn + 31) / 32;
     uint32_t* bm = tmp.alloc<uint32_t>((size_t)nn * words);
     launch_fill_i32(reinterpret_cast<int*>(bm), nn * words, 0, st);
-    launch_pattern(s->nruns, key, s->run_start, nn, s->nbr, bm, words, st);
+    launch_pattern(s->nruns, key, run_start, nn, s->nbr, bm, words, st);
     int* rcnt = tmp.alloc<int>(nn);
     launch_row_counts(nn, bm, words, rcnt, st);
     s->row_ptr = G.alloc<int>(nn + 1);
@@ -268,13 +277,30 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     uint32_t* eval = tmp.alloc<uint32_t>(npad_e);
     int* ecount = tmp.alloc<int>(s->nb);
     launch_fill_i32(ecount, s->nb, 0, st);
-    launch_run_entries(s->nruns, npad_e, key, s->run_start, s->row_ptr, s->col_idx, ekey, eval, ecount, st);
+    launch_run_entries(s->nruns, npad_e, key, run_start, s->row_ptr, s->col_idx, ekey, eval, ecount, st);
     sort_pairs(ekey, eval, npad_e, st);
     s->ent_ptr = G.alloc<int>(s->nb + 1);
-    int* scan_tmp_b = tmp.alloc<int>(scan_tmp_size(s->nb) + 16);
+    int* scan_tmp_b = tmp.alloc<int>(scan_tmp_size(std::max(s->nb, s->ne) + 16) + 16);
     exclusive_scan(ecount, s->ent_ptr, s->nb, scan_tmp_b, st);
     s->ent = G.alloc<uint32_t>(s->ne);
     launch_entries_store(s->ne, ekey, s->ent, st);
+    const int noff = s->nb - nn;
+    s->offlist = G.alloc<int>(std::max(1, noff));
+    launch_offlist(s->nb, s->blk_row, s->col_idx, s->offlist, st);
+    s->part = G.alloc<float>((size_t)kSegSlots * std::max(1, s->nruns));
+
+    // in-edges of every node (j with the node in N_j), ascending j
+    int npad_i = pow2_at_least(8 * (int64_t)nn, 1024);
+    uint64_t* ikey = tmp.alloc<uint64_t>(npad_i);
+    uint32_t* ival = tmp.alloc<uint32_t>(npad_i);
+    int* icount = tmp.alloc<int>(nn);
+    launch_fill_i32(icount, nn, 0, st);
+    launch_in_edge_keys(nn, npad_i, s->nbr, ikey, ival, icount, st);
+    sort_pairs(ikey, ival, npad_i, st);
+    s->in_ptr = G.alloc<int>(nn + 1);
+    exclusive_scan(icount, s->in_ptr, nn, scan_tmp, st);
+    s->in_list = G.alloc<int>(8 * (size_t)nn);
+    launch_in_edge_store(8 * nn, ival, s->in_list, st);
 
     // full symmetric rows for the matrix product
     int npad_t = pow2_at_least(s->nb, 1024);
@@ -288,17 +314,27 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     exclusive_scan(tcount, tstart, nn, scan_tmp, st);
     int* fcount = tmp.alloc<int>(nn);
     launch_full_counts(nn, s->row_ptr, tcount, fcount, st);
-    s->frow_ptr = G.alloc<int>(nn + 1);
-    exclusive_scan(fcount, s->frow_ptr, nn, scan_tmp, st);
+    int* frow_ptr = tmp.alloc<int>(nn + 1);
+    exclusive_scan(fcount, frow_ptr, nn, scan_tmp, st);
     s->nf = 2 * s->nb - nn;
-    s->fblk = G.alloc<uint32_t>(s->nf);
-    s->fcol = G.alloc<int>(s->nf);
-    launch_full_rows(nn, s->nb - nn, s->row_ptr, s->col_idx, tcount, tstart, s->frow_ptr, tkey, tval, s->fblk,
-                     s->fcol, st);
+    uint32_t* fblk = tmp.alloc<uint32_t>(s->nf);
+    int* fcol = tmp.alloc<int>(s->nf);
+    launch_full_rows(nn, s->nb - nn, s->row_ptr, s->col_idx, tcount, tstart, frow_ptr, tkey, tval, fblk, fcol, st);
+    {
+        std::vector<int> hrow(nn + 1);
+        SWGN_HIP(hipMemcpyAsync(hrow.data(), frow_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        int wmax = 1;
+        for (int k = 0; k < nn; ++k) wmax = std::max(wmax, hrow[k + 1] - hrow[k]);
+        s->ell_w = (wmax + 7) & ~7;
+    }
+    s->ell_blk = G.alloc<uint32_t>((size_t)nn * s->ell_w);
+    s->ell_col = G.alloc<int>((size_t)nn * s->ell_w);
+    launch_ell(nn, s->ell_w, frow_ptr, fblk, fcol, s->ell_blk, s->ell_col, st);
 
     // per-iteration buffers
-    s->J = G.alloc<float>(24 * (size_t)s->pitch);
-    s->res = G.alloc<float>(s->pitch);
+    s->J = G.alloc<float>(32 * (size_t)s->pitch);
+    launch_fill_i32(reinterpret_cast<int*>(s->J), 32 * s->pitch, 0, st);   // padding columns stay zero
     s->H = G.alloc<float>(36 * (size_t)s->nb);
     s->g = G.alloc<float>(6 * (size_t)nn);
     s->ereg = G.alloc<float>(nn);
@@ -314,14 +350,11 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     s->part_rho = G.alloc<double>(nparts);
     s->part_rr = G.alloc<double>(nparts);
     s->part_pq = G.alloc<double>(nparts);
-    s->offlist = G.alloc<int>(std::max(1, s->nb - nn));
-    launch_offlist(s->nb, s->blk_row, s->col_idx, s->offlist, st);
     s->dbg_live = G.alloc<float>(3 * (size_t)ns);
     s->dbg_H = G.alloc<float>(36 * (size_t)s->nb);
     s->dbg_g = G.alloc<float>(n6);
     s->dbg_x = G.alloc<float>(n6);
-    s->dbg_J = G.alloc<float>(24 * (size_t)s->pitch);
-    s->dbg_res = G.alloc<float>(s->pitch);
+    s->dbg_J = G.alloc<float>(32 * (size_t)s->pitch);
 
     SWGN_HIP(hipGetLastError());
     SWGN_HIP(hipStreamSynchronize(st));
@@ -338,13 +371,13 @@ hipEvent_t event_at(sw_stream s, size_t i) {
 }
 
 double model_bytes(const sw_stream_s* s, int64_t n_corr_total) {
-    // algorithmic bytes of one frame (see the kernel notes in the design document)
+    // algorithmic bytes of one frame: data each kernel must read or write at least
     double ns = (double)s->ns, nn = (double)s->nn, nb = (double)s->nb;
     double npx = (double)s->cam.W * s->cam.H;
     double per_iter = 0.0;
     per_iter += 48.0 * ns + 8.0 * ns + 8.0 * npx;                 // warp + z-buffer (+ clear)
     per_iter += 60.0 * ns + 8.0 * ns + 16.0 * ns + 100.0 * ns;    // correspondence + J
-    per_iter += 144.0 * nb + 24.0 * nn + 4.0 * s->ne;             // assembly writes + entries
+    per_iter += 2.0 * kSegSlots * 4.0 * s->nruns + 144.0 * nb + 24.0 * nn;  // segment Grams + blocks
     per_iter += 144.0 * nn + 288.0 * nn;                          // block-Jacobi
     per_iter += s->cfg.pcg_iters * (144.0 * nb + 7.0 * 24.0 * nn); // PCG
     double frame = s->cfg.gn_iters * per_iter + 20.0 * npx;
@@ -518,10 +551,10 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
         const float dist2 = c.corr_dist * c.corr_dist;
         char* stats_d = static_cast<char*>(s->stats_d);
         const size_t iss = sizeof(IterStats);
-        AssembleArgs aa{s->nb, nn, s->pitch, s->blk_row, s->col_idx, s->row_ptr, s->offlist, s->ent_ptr, s->ent,
-                        s->run_start, s->J, s->res, s->nbr, s->pref, s->rq, s->cl, s->frow_ptr, s->fcol,
-                        c.lambda_reg, c.damping, s->H, s->g, s->ereg};
-        SolveStepArgs sa{nn, npx, s->row_ptr, s->H, s->g, s->frow_ptr, s->fblk, s->fcol, s->Minv,
+        AssembleArgs aa{s->nb, nn, s->nb - nn, s->pitch, s->nruns, s->blk_row, s->col_idx, s->row_ptr,
+                        s->offlist, s->seg_start, s->ent_ptr, s->ent, s->in_ptr, s->in_list, s->J, s->nbr,
+                        s->pref, s->rq, s->cl, c.lambda_reg, c.damping, s->part, s->H, s->g, s->ereg};
+        SolveStepArgs sa{nn, npx, s->row_ptr, s->H, s->g, s->ell_w, s->ell_blk, s->ell_col, s->Minv,
                          s->x, s->r, s->z, s->q, s->p0, s->p1, s->sc, s->part_rho, s->part_rr, s->part_pq, s->flags,
                          s->part_e, s->part_n, corr_blocks(ns), s->ereg, nullptr, s->pref, s->rq, s->tt, s->dq,
                          s->cl, s->zbuf};
@@ -536,17 +569,19 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
                 launch_fill_i32(s->dbg_corr, npx, -1, st);
             }
             mark(2);
-            launch_corr_jac(ns, sv, s->dq, s->cl, s->cam, s->zbuf, s->nmap, dist2, c.corr_normal, s->J, s->res,
+            launch_corr_jac(ns, sv, s->dq, s->cl, s->cam, s->zbuf, s->nmap, dist2, c.corr_normal, s->J,
                             s->pitch, s->part_e, s->part_n, cap ? s->dbg_corr : nullptr,
                             cap ? s->dbg_live : nullptr, st);
             mark(-1);
             mark(3);
-            launch_assemble(aa, st);
+            launch_assemble_segments(aa, st);
+            mark(-1);
+            mark(8);
+            launch_assemble_fold(aa, st);
             mark(-1);
             if (cap) {
                 // the solve step updates the node state: keep this iteration's system first
-                SWGN_HIP(hipMemcpyAsync(s->dbg_J, s->J, sizeof(float) * 24 * s->pitch, hipMemcpyDeviceToDevice, st));
-                SWGN_HIP(hipMemcpyAsync(s->dbg_res, s->res, sizeof(float) * s->pitch, hipMemcpyDeviceToDevice, st));
+                SWGN_HIP(hipMemcpyAsync(s->dbg_J, s->J, sizeof(float) * 32 * s->pitch, hipMemcpyDeviceToDevice, st));
                 SWGN_HIP(hipMemcpyAsync(s->dbg_H, s->H, sizeof(float) * 36 * s->nb, hipMemcpyDeviceToDevice, st));
                 SWGN_HIP(hipMemcpyAsync(s->dbg_g, s->g, sizeof(float) * 6 * nn, hipMemcpyDeviceToDevice, st));
             }
@@ -724,22 +759,22 @@ sw_status sw_get_last_jacobian(sw_stream s, float* r, float* J) {
     if (!s->graph_set || !s->captured) return fail(s, SW_ESTATE, "no captured iteration");
     return guarded(s, [&]() -> sw_status {
         const size_t ns = (size_t)s->ns, P = (size_t)s->pitch;
-        std::vector<float> hJ(24 * P), hr(P);
+        std::vector<float> hJ(32 * P);
         std::vector<int4> idx(ns);
         std::vector<int> orig(ns);
-        SWGN_HIP(hipMemcpyAsync(hJ.data(), s->dbg_J, sizeof(float) * 24 * P, hipMemcpyDeviceToHost, s->st));
-        SWGN_HIP(hipMemcpyAsync(hr.data(), s->dbg_res, sizeof(float) * P, hipMemcpyDeviceToHost, s->st));
+        SWGN_HIP(hipMemcpyAsync(hJ.data(), s->dbg_J, sizeof(float) * 32 * P, hipMemcpyDeviceToHost, s->st));
         SWGN_HIP(hipMemcpyAsync(idx.data(), s->sidx, sizeof(int4) * ns, hipMemcpyDeviceToHost, s->st));
         SWGN_HIP(hipMemcpyAsync(orig.data(), s->sorig, sizeof(int) * ns, hipMemcpyDeviceToHost, s->st));
         SWGN_HIP(hipStreamSynchronize(s->st));
         for (size_t i = 0; i < ns; ++i) {
-            size_t o = (size_t)orig[i];
-            if (r) r[o] = hr[i];
+            const size_t o = (size_t)orig[i];
+            const float* row = hJ.data() + 32 * i;
+            if (r) r[o] = row[24];
             if (J) {
                 const int ids[4] = {idx[i].x, idx[i].y, idx[i].z, idx[i].w};
                 for (int k = 0; k < 4; ++k) {
                     int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
-                    for (int c = 0; c < 6; ++c) J[24 * o + 6 * k + c] = hJ[(size_t)(pos * 6 + c) * P + i];
+                    for (int c = 0; c < 6; ++c) J[24 * o + 6 * k + c] = row[pos * 6 + c];
                 }
             }
         }

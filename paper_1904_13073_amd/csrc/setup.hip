@@ -257,7 +257,7 @@ __global__ void k_tuple_keys(int ns, int npad, const int4* __restrict__ idx, uin
 }
 
 // Gather surfel arrays into sorted order; flag run starts.
-__global__ void k_permute_surfels(int ns, const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
+__global__ void k_permute_surfels(int ns, int seg_len, const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
         const float* __restrict__ ipos, const float* __restrict__ inrm, const int4* __restrict__ iidx,
         const float4* __restrict__ iw, float* __restrict__ px, float* __restrict__ py, float* __restrict__ pz,
         float* __restrict__ nx, float* __restrict__ ny, float* __restrict__ nz, int4* __restrict__ oidx,
@@ -270,7 +270,8 @@ __global__ void k_permute_surfels(int ns, const uint64_t* __restrict__ key, cons
     oidx[i] = iidx[o];
     ow[i] = iw[o];
     orig[i] = o;
-    flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+    // segment starts: a new node set, or every seg_len-th surfel
+    flag[i] = (i == 0 || key[i] != key[i - 1] || (i % seg_len) == 0) ? 1 : 0;
 }
 
 __global__ void k_run_starts(int ns, const int* __restrict__ flag, const int* __restrict__ pos,
@@ -428,6 +429,42 @@ __global__ void k_full_fill_u(int nn, const int* __restrict__ row_ptr, const int
 }
 
 // ---------------------------------------------------------------------------
+// Node-graph in-edges and ELL rows
+// ---------------------------------------------------------------------------
+// in-edges of every node: (m << 32 | j) keys for every edge j -> m
+__global__ void k_in_edge_keys(int nn, int npad, const int* __restrict__ nbr, uint64_t* __restrict__ key,
+                               uint32_t* __restrict__ val, int* __restrict__ icount) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npad) return;
+    if (e >= 8 * nn) {
+        key[e] = ~0ull;
+        val[e] = 0xffffffffu;
+        return;
+    }
+    int j = e / 8, m = nbr[e];
+    key[e] = ((uint64_t)m << 32) | (uint64_t)j;
+    val[e] = (uint32_t)j;
+    atomicAdd(&icount[m], 1);
+}
+
+__global__ void k_in_edge_store(int n, const uint32_t* __restrict__ val, int* __restrict__ in_list) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) in_list[e] = (int)val[e];
+}
+
+// Full rows in ELL layout (width ell_w, left-aligned, ~0 padding).
+__global__ void k_ell(int nn, int ell_w, const int* __restrict__ frow_ptr, const uint32_t* __restrict__ fblk,
+                      const int* __restrict__ fcol, uint32_t* __restrict__ ell_blk, int* __restrict__ ell_col) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * ell_w) return;
+    int k = t / ell_w, i = t % ell_w;
+    int f = frow_ptr[k] + i;
+    bool in = f < frow_ptr[k + 1];
+    ell_blk[t] = in ? fblk[f] : 0xffffffffu;
+    ell_col[t] = in ? fcol[f] : 0;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, float inv_two_sigma2, int4* idx,
@@ -445,11 +482,11 @@ void launch_tuple_keys(int ns, int npad, const int4* idx, uint64_t* key, uint32_
     hipLaunchKernelGGL(k_tuple_keys, dim3((npad + 255) / 256), dim3(256), 0, st, ns, npad, idx, key, val);
 }
 
-void launch_permute_surfels(int ns, const uint64_t* key, const uint32_t* val, const float* ipos,
+void launch_permute_surfels(int ns, int seg_len, const uint64_t* key, const uint32_t* val, const float* ipos,
                             const float* inrm, const int4* iidx, const float4* iw, float* px, float* py,
                             float* pz, float* nx, float* ny, float* nz, int4* oidx, float4* ow, int* orig,
                             int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_permute_surfels, dim3((ns + 255) / 256), dim3(256), 0, st, ns, key, val, ipos, inrm,
+    hipLaunchKernelGGL(k_permute_surfels, dim3((ns + 255) / 256), dim3(256), 0, st, ns, seg_len, key, val, ipos, inrm,
                        iidx, iw, px, py, pz, nx, ny, nz, oidx, ow, orig, flag);
 }
 
@@ -511,6 +548,21 @@ void launch_full_rows(int nn, int ntr, const int* row_ptr, const int* col_idx, c
 
 void launch_full_counts(int nn, const int* row_ptr, const int* tcount, int* fcount, hipStream_t st) {
     hipLaunchKernelGGL(k_full_counts, dim3((nn + 255) / 256), dim3(256), 0, st, nn, row_ptr, tcount, fcount);
+}
+
+void launch_in_edge_keys(int nn, int npad, const int* nbr, uint64_t* key, uint32_t* val, int* icount, hipStream_t st) {
+    hipLaunchKernelGGL(k_in_edge_keys, dim3((npad + 255) / 256), dim3(256), 0, st, nn, npad, nbr, key, val, icount);
+}
+
+void launch_ell(int nn, int ell_w, const int* frow_ptr, const uint32_t* fblk, const int* fcol, uint32_t* ell_blk,
+                int* ell_col, hipStream_t st) {
+    int n = nn * ell_w;
+    hipLaunchKernelGGL(k_ell, dim3((n + 255) / 256), dim3(256), 0, st, nn, ell_w, frow_ptr, fblk, fcol, ell_blk,
+                       ell_col);
+}
+
+void launch_in_edge_store(int n, const uint32_t* val, int* in_list, hipStream_t st) {
+    hipLaunchKernelGGL(k_in_edge_store, dim3((n + 255) / 256), dim3(256), 0, st, n, val, in_list);
 }
 
 }  // namespace swgn

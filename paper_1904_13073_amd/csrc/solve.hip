@@ -4,10 +4,11 @@
 //                the start of preconditioned conjugate gradients on
 //                (J^T J + mu I) delta = -g: r = -g, z = M r, p = z, x = 0
 //   pcg_spmv     q = A p with p = z + beta p_old formed on the fly (one wave per
-//                block row)
+//                block row, rows in ELL layout)
 //   pcg_update   x += alpha p, r -= alpha q, z = M r (8 lanes per node)
 //   node_update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
-//                and the reset of the index map for the next iteration
+//                the reset of the index map for the next iteration and the
+//                iteration's energy statistics
 //
 // PCG runs a fixed number of iterations and stops early only if rho = r^T z is
 // exactly 0. Its scalars never leave the device: every workgroup sums the same
@@ -27,9 +28,9 @@ struct SolveArgs {
     const int* row_ptr;
     const float* H;
     const float* g;
-    const int* frow_ptr;
-    const uint32_t* fblk;
-    const int* fcol;
+    int ell_w;                 // ELL row width (multiple of 8)
+    const uint32_t* ell_blk;   // [nn][ell_w] block id (bit 31 = transposed), ~0 = padding
+    const int* ell_col;        // [nn][ell_w] column node
     double* Minv;
     float *x, *r, *z, *q, *p0, *p1;
     double* sc;          // sc[2 it] = rho_it
@@ -47,81 +48,13 @@ struct SolveArgs {
     unsigned long long* zbuf;
 };
 
-constexpr int kInitBlock = 64;
+constexpr int kInitBlock = 256;     // 32 nodes x 8 lanes
 constexpr int kUpdBlock = 256;      // 32 nodes x 8 lanes
 constexpr int kRowsPerSpmvBlock = 4;
 
-int init_blocks(int nn) { return (nn + kInitBlock - 1) / kInitBlock; }
+int init_blocks(int nn) { return (8 * nn + kInitBlock - 1) / kInitBlock; }
 int upd_blocks(int nn) { return (8 * nn + kUpdBlock - 1) / kUpdBlock; }
 int spmv_blocks(int nn) { return (nn + kRowsPerSpmvBlock - 1) / kRowsPerSpmvBlock; }
-
-// FP64 inverse of a symmetric positive-definite 6x6 block (Cholesky, then
-// L^-T L^-1). Returns false (and the identity) if a pivot is not positive.
-__device__ bool spd_inverse6(const float* __restrict__ A, double* __restrict__ M) {
-    double L[6][6];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L[a][c] = 0.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double d = (double)A[c * 6 + c];
-#pragma unroll
-        for (int t = 0; t < c; ++t) d -= L[c][t] * L[c][t];
-        ok = ok && (d > 0.0);
-        double lc = sqrt(ok ? d : 1.0);
-        L[c][c] = lc;
-#pragma unroll
-        for (int a = c + 1; a < 6; ++a) {
-            double v = (double)A[c * 6 + a];
-#pragma unroll
-            for (int t = 0; t < c; ++t) v -= L[a][t] * L[c][t];
-            L[a][c] = v / lc;
-        }
-    }
-    if (!ok) {
-#pragma unroll
-        for (int t = 0; t < 36; ++t) M[t] = (t % 7 == 0) ? 1.0 : 0.0;
-        return false;
-    }
-    double Li[6][6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) Li[a][c] = 0.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        Li[c][c] = 1.0 / L[c][c];
-#pragma unroll
-        for (int a = c + 1; a < 6; ++a) {
-            double v = 0.0;
-#pragma unroll
-            for (int t = c; t < a; ++t) v -= L[a][t] * Li[t][c];
-            Li[a][c] = v / L[a][a];
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double v = 0.0;
-#pragma unroll
-            for (int t = (a > c ? a : c); t < 6; ++t) v += Li[t][a] * Li[t][c];
-            M[a * 6 + c] = v;
-        }
-    return true;
-}
-
-__device__ __forceinline__ void apply_minv(const double* __restrict__ M, const float* r, float* z) {
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v += M[a * 6 + c] * (double)r[c];
-        z[a] = (float)v;
-    }
-}
 
 __device__ void update_node(const SolveArgs& a, int k) {
     const float* x = a.x + 6 * k;
@@ -157,26 +90,55 @@ __device__ void update_node(const SolveArgs& a, int k) {
 }
 
 
+// 8 lanes per node: lane a < 6 holds row a of [H_kk + mu I | I]; FP64
+// Gauss-Jordan elimination leaves row a of the inverse. Without pivoting the
+// pivots of a symmetric matrix are all positive exactly when it is positive
+// definite, which is checked.
 __global__ void __launch_bounds__(kInitBlock) k_pcg_init(SolveArgs a) {
     __shared__ double sh[40];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = gid >> 3, row = gid & 7, base = threadIdx.x & ~7;
+    const bool on = (k < a.nn) && (row < 6);
+    double m[12];
+    const float* A = a.H + (size_t)(k < a.nn ? a.row_ptr[k] : 0) * 36;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        m[c] = on ? (double)A[row * 6 + c] : 0.0;
+        m[6 + c] = (on && c == row) ? 1.0 : 0.0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double pr[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) pr[j] = __shfl(m[j], base + c, kWave);
+        const double piv = pr[c];
+        ok = ok && (piv > 0.0);
+        const double inv = 1.0 / (piv > 0.0 ? piv : 1.0);
+        const double f = (row == c) ? 0.0 : m[c] * inv;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) m[j] = (row == c) ? m[j] * inv : m[j] - f * pr[j];
+    }
+    if (k < a.nn && row == 0 && !ok) atomicOr(a.flags, 1);
+    float rc = on ? -a.g[6 * k + row] : 0.f;
+    double zc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float rj = __shfl(rc, base + j, kWave);
+        const double mj = ok ? m[6 + j] : (j == row ? 1.0 : 0.0);
+        zc += mj * (double)rj;
+        if (on) a.Minv[(size_t)k * 36 + row * 6 + j] = mj;
+    }
     double rho = 0.0, rr = 0.0;
-    if (k < a.nn) {
-        double* M = a.Minv + (size_t)k * 36;
-        if (!spd_inverse6(a.H + (size_t)a.row_ptr[k] * 36, M)) atomicOr(a.flags, 1);
-        float r[6], z[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) r[c] = -a.g[6 * k + c];
-        apply_minv(M, r, z);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            a.r[6 * k + c] = r[c];
-            a.z[6 * k + c] = z[c];
-            a.p0[6 * k + c] = z[c];
-            a.x[6 * k + c] = 0.f;
-            rho += (double)r[c] * (double)z[c];
-            rr += (double)r[c] * (double)r[c];
-        }
+    if (on) {
+        const float zf = (float)zc;
+        const int t = 6 * k + row;
+        a.r[t] = rc;
+        a.z[t] = zf;
+        a.p0[t] = zf;
+        a.x[t] = 0.f;
+        rho = (double)rc * (double)zf;
+        rr = (double)rc * (double)rc;
     }
     rho = block_sum(rho, sh);
     rr = block_sum(rr, sh);
@@ -184,64 +146,56 @@ __global__ void __launch_bounds__(kInitBlock) k_pcg_init(SolveArgs a) {
         a.part_rho[blockIdx.x] = rho;
         a.part_rr[blockIdx.x] = rr;
     }
-    if (blockIdx.x == 0) {
-        // energies at this linearisation point
-        double e = 0.0, n = 0.0, er = 0.0;
-        for (int t = threadIdx.x; t < a.nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
-        for (int t = threadIdx.x; t < a.nn; t += blockDim.x) er += (double)a.ereg[t];
-        e = block_sum(e, sh);
-        n = block_sum(n, sh);
-        er = block_sum(er, sh);
-        if (threadIdx.x == 0) {
-            a.stats->e_data = e;
-            a.stats->e_reg = er;
-            a.stats->n_corr = (int)n;
-            if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
-        }
-    }
 }
 
+// q = A p_it with p_it = z + beta p_{it-1} (beta = 0 and p_0 = z at it = 0).
+// The row's products with z and with p_{it-1} are accumulated separately, so
+// the matrix loads run before beta (a grid-wide sum) is known.
 __global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a, int it, int n_rho_parts) {
     __shared__ double sh[40];
+    float* const pbuf[2] = {a.p0, a.p1};
+    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];
+    float* pcur = pbuf[it & 1];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int k = blockIdx.x * kRowsPerSpmvBlock + wave;
+    const int sub = lane & 7, fl = lane >> 3;
+    float az = 0.f, ap = 0.f;
+    if (k < a.nn && sub < 6) {
+        const uint32_t* eb = a.ell_blk + (size_t)k * a.ell_w;
+        const int* ec = a.ell_col + (size_t)k * a.ell_w;
+#pragma unroll 2
+        for (int f = fl; f < a.ell_w; f += 8) {
+            const uint32_t bb = eb[f];
+            if (bb == 0xffffffffu) break;
+            const int col = ec[f];
+            const float* B = a.H + (size_t)(bb & ~kTransposed) * 36;
+            const bool tr = (bb & kTransposed) != 0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const float h = tr ? B[c * 6 + sub] : B[sub * 6 + c];
+                az = fmaf(h, a.z[6 * col + c], az);
+                ap = fmaf(h, pold[6 * col + c], ap);
+            }
+        }
+    }
+    az += __shfl_xor(az, 8, kWave);
+    az += __shfl_xor(az, 16, kWave);
+    az += __shfl_xor(az, 32, kWave);
+    ap += __shfl_xor(ap, 8, kWave);
+    ap += __shfl_xor(ap, 16, kWave);
+    ap += __shfl_xor(ap, 32, kWave);
     const double rho = reduce_partials(a.part_rho, n_rho_parts, sh);
     const bool stop = (rho == 0.0);
     const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[2 * (it - 1)]) : 0.f;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.sc[2 * it] = rho;
-    // p_it lives in p[it & 1]; p_0 was written by the init kernel
-    float* const pbuf[2] = {a.p0, a.p1};
-    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];   // p_{it-1} (p_0 at it = 0)
-    float* pcur = pbuf[it & 1];
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int k = blockIdx.x * kRowsPerSpmvBlock + wave;
     double pq = 0.0;
-    if (!stop && k < a.nn) {
-        const int sub = lane & 7, fl = lane >> 3;
-        float acc = 0.f;
-        if (sub < 6) {
-            const int f1 = a.frow_ptr[k + 1];
-            for (int f = a.frow_ptr[k] + fl; f < f1; f += 8) {
-                const uint32_t bb = a.fblk[f];
-                const int col = a.fcol[f];
-                const float* B = a.H + (size_t)(bb & ~kTransposed) * 36;
-                const bool tr = (bb & kTransposed) != 0;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    float pc = it > 0 ? a.z[6 * col + c] + beta * pold[6 * col + c] : pold[6 * col + c];
-                    float h = tr ? B[c * 6 + sub] : B[sub * 6 + c];
-                    acc = fmaf(h, pc, acc);
-                }
-            }
-        }
-        acc += __shfl_xor(acc, 8, kWave);
-        acc += __shfl_xor(acc, 16, kWave);
-        acc += __shfl_xor(acc, 32, kWave);
-        if (lane < 6) {
-            const int t = 6 * k + lane;
-            const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
-            if (it > 0) pcur[t] = pk;
-            a.q[t] = acc;
-            pq = (double)pk * (double)acc;
-        }
+    if (!stop && k < a.nn && lane < 6) {
+        const int t = 6 * k + lane;
+        const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
+        const float qv = az + beta * ap;
+        if (it > 0) pcur[t] = pk;
+        a.q[t] = qv;
+        pq = (double)pk * (double)qv;
     }
     pq = block_sum(pq, sh);
     if (threadIdx.x == 0) a.part_pq[blockIdx.x] = pq;
@@ -249,33 +203,41 @@ __global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a
 
 __global__ void __launch_bounds__(kUpdBlock) k_pcg_update(SolveArgs a, int it, int n_pq_parts) {
     __shared__ double sh[40];
-    const double rho = a.sc[2 * it];
-    const bool stop = (rho == 0.0);
-    const double pq = reduce_partials(a.part_pq, n_pq_parts, sh);
     const float* p = (it & 1) ? a.p1 : a.p0;
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = gid >> 3, c = gid & 7;
     const bool on = (k < a.nn) && (c < 6);
-    float rc = on ? a.r[6 * k + c] : 0.f;
+    const int t = 6 * k + c;
+    float rc = 0.f, xc = 0.f, pc = 0.f, qc = 0.f;
+    double mrow[6];
+    if (on) {
+        rc = a.r[t]; xc = a.x[t]; pc = p[t]; qc = a.q[t];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) mrow[j] = a.Minv[(size_t)k * 36 + c * 6 + j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) mrow[j] = 0.0;
+    }
+    const double rho = a.sc[2 * it];
+    const bool stop = (rho == 0.0);
+    const double pq = reduce_partials(a.part_pq, n_pq_parts, sh);
     double rz = 0.0, rr = 0.0;
     if (!stop) {
         const float alpha = (float)(rho / pq);
+        xc = xc + alpha * pc;
+        rc = rc - alpha * qc;
         if (on) {
-            a.x[6 * k + c] = a.x[6 * k + c] + alpha * p[6 * k + c];
-            rc = rc - alpha * a.q[6 * k + c];
-            a.r[6 * k + c] = rc;
+            a.x[t] = xc;
+            a.r[t] = rc;
         }
         // z_c = sum_j M[c][j] r_j: the node's 6 residual entries from its lanes
         const int base = (threadIdx.x & ~7);
         double zc = 0.0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            float rj = __shfl(rc, base + j, kWave);
-            if (on) zc += a.Minv[(size_t)k * 36 + c * 6 + j] * (double)rj;
-        }
+        for (int j = 0; j < 6; ++j) zc += mrow[j] * (double)__shfl(rc, base + j, kWave);
         if (on) {
             const float zf = (float)zc;
-            a.z[6 * k + c] = zf;
+            a.z[t] = zf;
             rz = (double)rc * (double)zf;
         }
     }
@@ -294,8 +256,21 @@ __global__ void __launch_bounds__(256) k_node_update(SolveArgs a, int n_rr_parts
     if (gid < a.nn) update_node(a, gid);
     if (gid < a.npx) a.zbuf[gid] = ~0ull;     // index map of the next iteration
     if (blockIdx.x == 0) {
-        double rr = reduce_partials(a.part_rr, n_rr_parts, sh);
-        if (threadIdx.x == 0) a.stats->pcg_resid = sqrt(rr);
+        const double rr = reduce_partials(a.part_rr, n_rr_parts, sh);
+        // energies at this iteration's linearisation point
+        double e = 0.0, n = 0.0, er = 0.0;
+        for (int t = threadIdx.x; t < a.nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
+        for (int t = threadIdx.x; t < a.nn; t += blockDim.x) er += (double)a.ereg[t];
+        e = block_sum(e, sh);
+        n = block_sum(n, sh);
+        er = block_sum(er, sh);
+        if (threadIdx.x == 0) {
+            a.stats->pcg_resid = sqrt(rr);
+            a.stats->e_data = e;
+            a.stats->e_reg = er;
+            a.stats->n_corr = (int)n;
+            if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
+        }
     }
 }
 
@@ -304,7 +279,7 @@ __global__ void __launch_bounds__(256) k_node_update(SolveArgs a, int n_rr_parts
 int solve_partials_size(int nn) { return std::max(std::max(init_blocks(nn), upd_blocks(nn)), spmv_blocks(nn)); }
 
 static SolveArgs solve_args(const SolveStepArgs& s) {
-    return SolveArgs{s.nn, s.npx, s.row_ptr, s.H, s.g, s.frow_ptr, s.fblk, s.fcol, s.Minv, s.x, s.r, s.z, s.q, s.p0,
+    return SolveArgs{s.nn, s.npx, s.row_ptr, s.H, s.g, s.ell_w, s.ell_blk, s.ell_col, s.Minv, s.x, s.r, s.z, s.q, s.p0,
                      s.p1, s.sc, s.part_rho, s.part_rr, s.part_pq, s.flags, s.part_e, s.part_n, s.nparts, s.ereg,
                      static_cast<IterStats*>(s.stats), s.pref, s.rq, s.tt, s.dq, s.cl, s.zbuf};
 }

@@ -16,24 +16,27 @@ struct SurfelView {
     const int* orig;
 };
 
+constexpr int kSegLen = 128;      // surfels per segment at most (one node set)
+constexpr int kSegSlots = 400;    // per segment: 10 upper 6x6 blocks, J^T r (24), r^T r
+
 struct AssembleArgs {
-    int nb, nn, pitch;
+    int nb, nn, noff, pitch, nseg;
     const int* blk_row;
     const int* col_idx;
     const int* row_ptr;
     const int* offlist;
-    const int* ent_ptr;
-    const uint32_t* ent;
-    const int* run_start;
-    const float* J;
-    const float* res;
+    const int* seg_start;    // [nseg + 1] surfel ranges sharing one node set
+    const int* ent_ptr;      // [nb + 1] per block: its (segment, pos_a, pos_b) entries
+    const uint32_t* ent;     // (segment << 4 | pos_a << 2 | pos_b)
+    const int* in_ptr;       // node -> in-edges (j with the node in N_j)
+    const int* in_list;
+    const float* J;          // [pitch][32]: J (24), r, zero padding
     const int* nbr;
     const float4* pref;
     const float4* rq;
     const float4* cl;
-    const int* frow_ptr;
-    const int* fcol;
     float lambda, mu;
+    float* part;             // [nseg][kSegSlots] segment Gram sub-blocks
     float* H;
     float* g;
     float* ereg;
@@ -44,9 +47,9 @@ struct SolveStepArgs {
     const int* row_ptr;
     const float* H;
     const float* g;
-    const int* frow_ptr;
-    const uint32_t* fblk;
-    const int* fcol;
+    int ell_w;
+    const uint32_t* ell_blk;
+    const int* ell_col;
     double* Minv;
     float *x, *r, *z, *q, *p0, *p1;
     double *sc, *part_rho, *part_rr, *part_pq;
@@ -69,7 +72,7 @@ void sort_pairs(uint64_t* key, uint32_t* val, int n_pow2, hipStream_t st);
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t st);
 size_t scan_tmp_size(int n);
 void launch_tuple_keys(int ns, int npad, const int4* idx, uint64_t* key, uint32_t* val, hipStream_t st);
-void launch_permute_surfels(int ns, const uint64_t* key, const uint32_t* val, const float* ipos, const float* inrm,
+void launch_permute_surfels(int ns, int seg_len, const uint64_t* key, const uint32_t* val, const float* ipos, const float* inrm,
                             const int4* iidx, const float4* iw, float* px, float* py, float* pz, float* nx,
                             float* ny, float* nz, int4* oidx, float4* ow, int* orig, int* flag, hipStream_t st);
 void launch_run_starts(int ns, const int* flag, const int* pos, int* run_start, hipStream_t st);
@@ -88,6 +91,11 @@ void launch_full_rows(int nn, int ntr, const int* row_ptr, const int* col_idx, c
                       const int* frow_ptr, const uint64_t* tkey, const uint32_t* tval, uint32_t* fblk, int* fcol,
                       hipStream_t st);
 
+void launch_in_edge_keys(int nn, int npad, const int* nbr, uint64_t* key, uint32_t* val, int* icount, hipStream_t st);
+void launch_in_edge_store(int n, const uint32_t* val, int* in_list, hipStream_t st);
+void launch_ell(int nn, int ell_w, const int* frow_ptr, const uint32_t* fblk, const int* fcol, uint32_t* ell_blk,
+                int* ell_col, hipStream_t st);
+
 // per frame
 void launch_depth_prep(const Cam& cam, const float* depth, float gate, float4* nmap, unsigned long long* zbuf,
                        int* flags, hipStream_t st);
@@ -96,10 +104,11 @@ void launch_warp_zbuf(int ns, const SurfelView& sv, const float4* dq, const Cam&
                       hipStream_t st);
 int corr_blocks(int ns);
 void launch_corr_jac(int ns, const SurfelView& sv, const float4* dq, const float4* cl, const Cam& cam,
-                     const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J, float* res,
-                     int pitch, double* part_e, int* part_n, int* corr_map, float* live_pos, hipStream_t st);
+                     const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J, int pitch,
+                     double* part_e, int* part_n, int* corr_map, float* live_pos, hipStream_t st);
 void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist, hipStream_t st);
-void launch_assemble(const AssembleArgs& a, hipStream_t st);
+void launch_assemble_segments(const AssembleArgs& a, hipStream_t st);
+void launch_assemble_fold(const AssembleArgs& a, hipStream_t st);
 int solve_partials_size(int nn);
 void launch_pcg_init(const SolveStepArgs& a, hipStream_t st);
 void launch_pcg_spmv(const SolveStepArgs& a, int it, hipStream_t st);

@@ -38,7 +38,7 @@ class SwFrameStats(C.Structure):
         n = self.iters
         return dict(iters=n, e_data=list(self.e_data[:n]), e_reg=list(self.e_reg[:n]),
                     n_corr=list(self.n_corr[:n]), pcg_resid=list(self.pcg_resid[:n]),
-                    stage_us=list(self.stage_us[:8]), alg_bytes=self.alg_bytes)
+                    stage_us=list(self.stage_us[:9]), alg_bytes=self.alg_bytes)
 
 
 class SwError(RuntimeError):
