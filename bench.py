@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="streams of the 640x480 workload solved together in the batched leg (0 = skip)")
     ap.add_argument("--cpu-gn-iters", type=int, default=2,
                     help="oracle Gauss-Newton iterations timed for the CPU baseline")
     return ap.parse_args()
@@ -69,6 +71,34 @@ def kernel_bytes(ns, nn, nb, nseg, npx, pcg_iters):
         # twist in; node state and tables out; index map reset
         "node_update": 24.0 * nn + 32.0 * nn + 96.0 * nn + 8.0 * npx,
     }
+
+
+def replay_us(bx, streams, pcg_iters, reps=200):
+    """Mean time per launch of every replayable stage, each launched `reps`
+    times back to back between two HIP events on the solve's stream."""
+    out = {}
+    for i, k in enumerate(KERNELS):
+        if k in ("depth_prep", "node_update"):
+            continue
+        pit = min(1, max(0, pcg_iters - 1)) if k in ("pcg_spmv", "pcg_update") else 0
+        out[k] = bx.profile_stage(streams, i, reps=reps, pcg_it=pit)
+    return out
+
+
+def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0):
+    """Achieved GB/s of every replayed kernel (algorithmic bytes x scale / mean
+    time per launch) and the roofline entry of the kernel with the largest
+    share of the frame."""
+    import numpy as np
+    rates = {k: scale * kb[k] / (us * 1e-6) / 1e9 for k, us in replay.items() if us > 0}
+    share = {k: per_frame_us[i] for i, k in enumerate(KERNELS) if k in replay}
+    name = max(share, key=share.get)
+    achieved = rates[name]
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_launch": scale * kb[name], "avg_launch_us": round(float(replay[name]), 3),
+            "launches_per_frame": int(launches[KERNELS.index(name)])}
+    return roof, {k: round(v, 1) for k, v in rates.items()}
 
 
 def cpu_baseline(scene, gn_iters):
@@ -168,18 +198,58 @@ def main():
     for _ in range(reps):
         stats = tst.solve_frame(depth)
         tot += np.array(stats["stage_us"])
-    tst.close()
     per_frame_us = tot / reps
     G, Pi = p.gn_iters, p.pcg_iters
     launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G, G], dtype=float)
-    per_launch_us = per_frame_us / launches
     kb = kernel_bytes(ns, nn, nb, nseg, scene.cam.width * scene.cam.height, p.pcg_iters)
-    dom = int(np.argmax(per_frame_us))
-    name = KERNELS[dom]
-    achieved = kb[name] / (per_launch_us[dom] * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "alg_bytes_per_launch": kb[name], "avg_launch_us": round(float(per_launch_us[dom]), 3)}
+    px = swgn.Batch(hip_stream=hip_stream)
+    replay = replay_us(px, [tst], Pi)
+    px.close()
+    tst.close()
+    roofline, rates = stage_roofline(per_frame_us, launches, kb, replay)
+
+    batched = None
+    if args.batch > 0:
+        B = min(args.batch, 64)
+        sts = [make_stream() for _ in range(B)]
+        bx = swgn.Batch(hip_stream=hip_stream)
+        depths = [depth] * B
+        torch.cuda.synchronize()
+        for _ in range(max(2, args.warmup // 2)):
+            bx.solve(sts, depths, with_stats=False)
+        torch.cuda.synchronize()
+        nbs = max(5, args.steps // B)
+        blat = []
+        t0 = time.perf_counter()
+        for _ in range(nbs):
+            a = time.perf_counter()
+            bx.solve(sts, depths, with_stats=False)
+            blat.append(time.perf_counter() - a)
+        torch.cuda.synchronize()
+        bel = time.perf_counter() - t0
+        same = all(np.array_equal(sts[0].node_se3(), t.node_se3()) for t in sts[1:3])
+        bx.close()
+        for t in sts:
+            t.set_node_se3(np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (nn, 1)))
+        tb = swgn.Batch(hip_stream=hip_stream, timing=True)
+        btot = np.zeros(len(KERNELS))
+        breps = 3
+        for _ in range(breps):
+            res, _ = tb.solve(sts, depths)
+            btot += np.array(res[0]["stage_us"])
+        b_replay = replay_us(tb, sts, Pi, reps=50)
+        tb.close()
+        for t in sts:
+            t.close()
+        b_roof, b_rates = stage_roofline(btot / breps, launches, kb, b_replay, scale=B)
+        batched = {"streams": B, "value": round(B * nbs / bel, 2), "unit": "frames/s",
+                   "ms_per_batch": round(1000.0 * bel / nbs, 3),
+                   "latency_ms": {"p50": round(1000 * percentile(blat, 0.5), 4),
+                                  "p99": round(1000 * percentile(blat, 0.99), 4)},
+                   "kernel_us_per_batch_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, btot / breps)},
+                   "kernel_us_per_launch": {k: round(v, 3) for k, v in b_replay.items()},
+                   "kernel_gbs": b_rates, "roofline": b_roof, "identical_results": bool(same)}
+        print(f"[bench] batched x{B}: {batched['value']} frames/s", file=sys.stderr, flush=True)
 
     out = {
         "metric": "GN frame solves/s at 640x480 ~2k nodes; p50/p99 solve latency, served vs plain",
@@ -200,9 +270,13 @@ def main():
         "latency_ms": {"p50": round(1000 * percentile(lat, 0.5), 4),
                        "p99": round(1000 * percentile(lat, 0.99), 4)},
         "kernel_us_per_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, per_frame_us)},
+        "kernel_us_per_launch": {k: round(v, 3) for k, v in replay.items()},
         "roofline": roofline,
+        "kernel_gbs": rates,
         "n_corr": stats["n_corr"][-1],
     }
+    if batched is not None:
+        out["batched"] = batched
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_gn_iters)

@@ -541,7 +541,7 @@ def scene_random(seed: int, size: Optional[Tuple[int, int]] = None,
                  ref_depth, pix, info)
 
 
-SCENES = {"tiny": scene_tiny, "c1": scene_c1, "c2": scene_c2}
+SCENES = {"tiny": scene_tiny, "c1": scene_c1, "c2": scene_c2, "random": scene_random}
 
 
 def make_scene(name: str, seed: Optional[int] = None) -> Scene:

@@ -36,8 +36,10 @@ typedef int32_t sw_status;
 #define SW_ENOMEM   -3   /* device or host allocation failed */
 #define SW_EHIP     -4   /* HIP runtime error */
 #define SW_ENUMERIC -5   /* non-finite energy or a non-positive-definite 6x6 block */
+#define SW_EPENDING  1   /* sw_server_poll: the frame is not done yet (not an error) */
 
 typedef struct sw_stream_s* sw_stream;
+typedef struct sw_server_s* sw_server;
 
 /* Solver configuration. sw_config_default() fills the defaults given below. */
 typedef struct sw_config {
@@ -67,7 +69,7 @@ typedef struct sw_frame_stats {
     float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
                                   over the frame: [0] depth preprocessing, [1] warp +
                                   index map, [2] correspondence + Jacobians,
-                                  [3] assembly of chunk partials, [4] block-Jacobi +
+                                  [3] segment Gram matrices, [4] block-Jacobi +
                                   PCG start, [5] PCG products, [6] PCG updates,
                                   [7] node update, [8] assembly of the blocks;
                                   measured with HIP events */
@@ -89,7 +91,8 @@ const char* sw_last_error(sw_stream s);
  * iteration counts out of range, non-positive sigma, negative weights. */
 sw_status sw_create_stream(const sw_config* cfg, void* hip_stream, sw_stream* out);
 
-/* Destroy a stream and free its device memory. NULL is a no-op. */
+/* Destroy a stream and free its device memory (if it is attached to a
+ * server, after its submitted frames are done). NULL is a no-op. */
 sw_status sw_destroy_stream(sw_stream s);
 
 /* Reference surfels S_ref (Sec. 4): n positions and unit normals, each n x 3
@@ -122,6 +125,127 @@ sw_status sw_set_node_se3(sw_stream s, const float* node_se3, int32_t n, int32_t
  * SW_ENUMERIC the transforms keep their values from before the call. */
 sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
                          sw_frame_stats* stats);
+
+/* ---- batches: frames of several streams solved together ----
+ *
+ * A batch executor launches each Gauss-Newton stage once for all the streams
+ * of a call: the grid is the concatenation of every stream's tiles and each
+ * workgroup reads its stream's descriptor, so a stream's result does not
+ * depend on what it is batched with. Streams may differ in image size,
+ * surfel and node counts and iteration counts. An executor owns a HIP stream
+ * (or uses the caller's), a small statistics buffer and timing events; it is
+ * not thread-safe, and a stream must not be solved by two calls at once. */
+typedef struct sw_batch_s* sw_batch;
+
+#define SW_BATCH_TIMING 1   /* time every launch with HIP events into stage_us */
+
+/* Create an executor. hip_stream as in sw_create_stream; flags: 0 or
+ * SW_BATCH_TIMING (then every stream's stage_us holds the times of the
+ * batch's launches, summed over the frame). */
+sw_status sw_create_batch(void* hip_stream, int32_t flags, sw_batch* out);
+
+/* Destroy an executor (NULL is a no-op). Streams are not affected. */
+sw_status sw_destroy_batch(sw_batch b);
+
+/* Message of the last failed call on b (never NULL). */
+const char* sw_batch_last_error(sw_batch b);
+
+/* Solve one frame for each of n distinct streams (1 <= n <= 64): depths[i]
+ * is stream i's H_i x W_i image, all host (on_device = 0) or all device
+ * memory readable on the executor's HIP stream. Synchronous. Each stream
+ * ends exactly as sw_solve_frame would leave it. stats (n entries) and
+ * status (n entries, per-stream result) may be NULL. Returns SW_OK, or
+ * SW_ENUMERIC when one or more streams failed numerically (those keep their
+ * transforms from before the call, the others are updated), or an argument /
+ * state / runtime error before or during the launches. */
+sw_status sw_solve_batch(sw_batch b, const sw_stream* streams, int32_t n,
+                         const float* const* depths, int32_t on_device,
+                         sw_frame_stats* stats, sw_status* status);
+
+/* Measurement: launch one per-frame stage of the batch reps times back to
+ * back (after one untimed launch) between two HIP events and return the mean
+ * time per launch in microseconds. The streams' frame workspaces are
+ * overwritten (their warp fields are not); use after a solve, so that the
+ * stage's inputs hold a real frame. stage numbers as in stage_us: 1 warp +
+ * index map, 2 correspondence + Jacobians, 3 segment Gram matrices,
+ * 4 block-Jacobi + PCG start, 5 PCG product, 6 PCG update, 8 block fold;
+ * others give SW_EINVAL. pcg_it selects the PCG iteration for 5 and 6. */
+sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int32_t stage,
+                           int32_t pcg_it, int32_t reps, float* us_per_launch);
+
+/* ---- serving: frames of many streams arriving at any time ----
+ *
+ * A server owns a HIP stream (or uses the caller's), one device slab for the
+ * workspaces of frames in flight and a worker thread. Streams are attached
+ * to it; frames are submitted with sw_server_submit and collected with
+ * sw_server_poll. A frame is admitted when its stream has no frame in flight,
+ * a batch slot is free and the stream's workspace (its footprint) fits in a
+ * free range of the slab; frames are admitted in arrival order as slots and
+ * memory free up. Every step runs one Gauss-Newton iteration of all frames in
+ * flight in the same launches, so a frame that arrives while others are on
+ * the GPU joins them at the next iteration. A frame's result is the same as
+ * sw_solve_frame's alone. The server's functions are thread-safe. */
+typedef struct sw_server_config {
+    int32_t max_batch;          /* frames in flight at most, 1..64 (default 32) */
+    int32_t reserved;
+    int64_t workspace_bytes;    /* device slab for frame workspaces (default 4 GiB) */
+} sw_server_config;
+
+typedef struct sw_ticket_info {
+    sw_status status;           /* the frame's result (as sw_solve_frame's) */
+    int32_t reserved;
+    double t_submit, t_admit, t_done;   /* seconds since the server was created
+                                           (monotonic clock) */
+} sw_ticket_info;
+
+typedef struct sw_server_info {
+    int64_t steps;              /* Gauss-Newton steps run */
+    int64_t frames_done;
+    int32_t max_in_flight;      /* most frames in flight at once so far */
+    int32_t pending;            /* frames waiting for admission now */
+    int32_t in_flight;          /* frames in flight now */
+    int32_t reserved;
+    int64_t workspace_bytes;    /* slab size */
+    int64_t workspace_peak;     /* most slab bytes in use at once so far */
+} sw_server_info;
+
+void sw_server_config_default(sw_server_config* cfg);
+
+/* Create a server on the current device. SW_EINVAL for max_batch outside
+ * 1..64 or a slab under 4 KiB; SW_ENOMEM if the slab cannot be allocated. */
+sw_status sw_create_server(const sw_server_config* cfg, void* hip_stream, sw_server* out);
+
+/* Wait for every submitted frame, stop the worker, give attached streams
+ * their own workspace back and free the slab. NULL is a no-op. */
+sw_status sw_destroy_server(sw_server sv);
+
+const char* sw_server_last_error(sw_server sv);
+
+/* Attach a stream (surfels and node graph set): its own frame workspace is
+ * freed and its frames run in the slab from now on. While attached the
+ * stream's sw_set_* and sw_solve_frame calls return SW_ESTATE, and its
+ * readers wait until its submitted frames are done. SW_EINVAL if its
+ * workspace exceeds the slab. */
+sw_status sw_server_attach(sw_server sv, sw_stream s);
+
+/* Wait for the stream's frames, then give it its own workspace back. */
+sw_status sw_server_detach(sw_server sv, sw_stream s);
+
+/* Queue one frame of an attached stream. A host image is copied before the
+ * call returns; a device image must stay readable and unchanged until the
+ * frame is done. *ticket identifies the frame for sw_server_poll. */
+sw_status sw_server_submit(sw_server sv, sw_stream s, const float* depth, int32_t on_device,
+                           uint64_t* ticket);
+
+/* Result of a frame: waits up to wait_ms (0 = do not wait, -1 = until done).
+ * SW_OK when done (stats and info filled, either may be NULL; the ticket is
+ * then released), SW_EPENDING while not done, SW_EINVAL for an unknown
+ * ticket. */
+sw_status sw_server_poll(sw_server sv, uint64_t ticket, int32_t wait_ms, sw_frame_stats* stats,
+                         sw_ticket_info* info);
+
+/* Counters of the server so far. */
+sw_status sw_server_counters(sw_server sv, sw_server_info* out);
 
 /* Copy the node transforms to host memory out (n_nodes x 12 fp32 [R | t]).
  * SW_EINVAL if capacity (in nodes) < n_nodes. */

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libswgn.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["setup.hip", "frame.hip", "assemble.hip", "solve.hip", "runtime.cpp"]
+SOURCES = ["setup.hip", "frame.hip", "assemble.hip", "solve.hip", "runtime.cpp", "batch.cpp", "server.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(" ".join(cmd) + "\n")
         objs.append(obj)
     tmp = OUT + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

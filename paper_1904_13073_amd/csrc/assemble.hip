@@ -19,6 +19,7 @@
 //      order, adds the regulariser terms (edges spread over the lanes) and
 //      the damping, and finishes with a DPP row reduction.
 // Each Jacobian is read once; no atomics; results are reproducible.
+#include "swgn_frame.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
 
@@ -31,7 +32,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ float3 ld3(float4 a) { return make_float3(a.x, a.y, a.z); }
 
 // y = R_m (p_j - p_m), r_jm = c_j - c_m - y
-__device__ __forceinline__ void arap_edge(const AssembleArgs& in, int j, int m, float3& y, float3& r) {
+__device__ __forceinline__ void arap_edge(const FrameDesc& in, int j, int m, float3& y, float3& r) {
     float3 pj = ld3(in.pref[j]), pm = ld3(in.pref[m]);
     float4 q = in.rq[m];
     y = qrot(q.x, make_float3(q.y, q.z, q.w), sub3(pj, pm));
@@ -52,10 +53,12 @@ __device__ __forceinline__ int sub_block(int pa, int pb) {
 }
 
 // Level 1: one wave per segment.
-__global__ void __launch_bounds__(256) k_asm_segments(AssembleArgs in) {
-    __shared__ float stage[4][kSegSlots];
+__global__ void __launch_bounds__(64 * kSegWaves) k_asm_segments(Batch wl) {
+    __shared__ float stage[kSegWaves][kSegSlots];
+    const Where at = locate(wl);
+    const FrameDesc in = *wl.d[at.s];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int seg = blockIdx.x * 4 + wave;
+    const int seg = at.tile * kSegWaves + wave;
     const bool active = seg < in.nseg;
     const int s0 = active ? in.seg_start[seg] : 0;
     const int s1 = active ? in.seg_start[seg + 1] : 0;
@@ -101,9 +104,11 @@ __global__ void __launch_bounds__(256) k_asm_segments(AssembleArgs in) {
 
 // Level 2: one 16-lane group per block; diagonal blocks first (node order),
 // then the off-diagonal ones.
-__global__ void __launch_bounds__(256) k_asm_fold(AssembleArgs in) {
+__global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
+    const Where at = locate(wl);
+    const FrameDesc in = *wl.d[at.s];
     const int lane = threadIdx.x % kWave, g = lane & 15;
-    const int gi = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int gi = at.tile * kFoldGroups + (threadIdx.x >> 4);
     const bool active = gi < in.nn + in.noff;
     const bool diag = gi < in.nn;
     const int b = !active ? 0 : (diag ? in.row_ptr[gi] : in.offlist[gi - in.nn]);
@@ -210,13 +215,11 @@ void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist
     hipLaunchKernelGGL(k_offlist, dim3((nb + 255) / 256), dim3(256), 0, st, nb, blk_row, col_idx, offlist);
 }
 
-void launch_assemble_segments(const AssembleArgs& a, hipStream_t st) {
-    if (a.nseg > 0) hipLaunchKernelGGL(k_asm_segments, dim3((a.nseg + 3) / 4), dim3(256), 0, st, a);
-}
-
-void launch_assemble_fold(const AssembleArgs& a, hipStream_t st) {
-    const int groups = a.nn + a.noff;
-    hipLaunchKernelGGL(k_asm_fold, dim3((groups + 15) / 16), dim3(256), 0, st, a);
+void launch_asm_stage(int stage, const Batch& b, hipStream_t st) {
+    const int grid = b.off[b.n];
+    if (grid <= 0) return;
+    if (stage == kStAsmSeg) hipLaunchKernelGGL(k_asm_segments, dim3(grid), dim3(64 * kSegWaves), 0, st, b);
+    if (stage == kStAsmFold) hipLaunchKernelGGL(k_asm_fold, dim3(grid), dim3(16 * kFoldGroups), 0, st, b);
 }
 
 }  // namespace swgn

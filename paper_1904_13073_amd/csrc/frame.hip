@@ -1,16 +1,17 @@
 // Per-frame kernels of the Gauss-Newton warp-field solve (Sec. 7), part 1:
 //
 //   depth_prep   normal map of the depth image (Sec. 5); resets the index map
-//   clear_z      index-map reset
 //   warp_zbuf    dual-quaternion warp of every surfel (Sec. 3, Eq. 1-2) and
 //                a 64-bit atomic-min z-buffer of (z bits, surfel index) (Sec. 7)
 //   corr_jac     projective correspondence, point-to-plane residual and its
 //                exact Jacobian with respect to the 4 node twists
 // plus node-state conversions and capture helpers. Assembly is in
-// assemble.hip, the linear solve and node update in solve.hip.
+// assemble.hip, the linear solve and node update in solve.hip. The per-frame
+// kernels take a batch of streams (one work list, see swgn_frame.h).
 //
 // Sums are taken in a fixed order everywhere, so a frame solve is
 // bit-reproducible run to run.
+#include "swgn_frame.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
 
@@ -18,22 +19,34 @@ namespace swgn {
 
 // ---------------------------------------------------------------------------
 // Depth preprocessing: normal map by central differences (Sec. 5).
-// nmap = (n, d) where the normal is defined, (0, 0, 0, 0) elsewhere.
+// nmap = (n, d) where the normal is defined, (0, 0, 0, 0) elsewhere. Also
+// resets the index map and the failure flags and keeps the node state the
+// frame starts from.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_depth_prep(Cam cam, const float* __restrict__ depth, float gate,
-                                                    float4* __restrict__ nmap, unsigned long long* __restrict__ zbuf,
-                                                    int* __restrict__ flags) {
-    int x = blockIdx.x * 16 + (threadIdx.x & 15);
-    int y = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4) flags[threadIdx.x] = 0;
+__global__ void __launch_bounds__(256) k_depth_prep(Batch b, DepthIn in) {
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const float* __restrict__ depth = in.p[at.s];
+    const int gid = at.tile * 256 + threadIdx.x;
+    if (at.tile == 0 && threadIdx.x < 4) d.flags[threadIdx.x] = 0;
+    if (gid < d.nn) {
+        d.rq_bak[gid] = d.rq[gid];
+        d.tt_bak[gid] = d.tt[gid];
+    }
+    const Cam cam = d.cam;
+    const int gx = cdiv(cam.W, kDepthTile);
+    if (at.tile >= gx * cdiv(cam.H, kDepthTile)) return;
+    const int x = (at.tile % gx) * kDepthTile + (threadIdx.x & 15);
+    const int y = (at.tile / gx) * kDepthTile + (threadIdx.x >> 4);
     if (x >= cam.W || y >= cam.H) return;
-    int W = cam.W;
-    zbuf[y * W + x] = ~0ull;   // index map of the first iteration
+    const int W = cam.W;
+    d.zbuf[y * W + x] = ~0ull;   // index map of the first iteration
     float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
     if (x > 0 && y > 0 && x < cam.W - 1 && y < cam.H - 1) {
         float dc = depth[y * W + x];
         float dU = depth[(y - 1) * W + x], dD = depth[(y + 1) * W + x];
         float dL = depth[y * W + x - 1], dR = depth[y * W + x + 1];
+        const float gate = d.edge_gate;
         bool ok = depth_ok(dc) && depth_ok(dU) && depth_ok(dD) && depth_ok(dL) && depth_ok(dR);
         if (ok) {
             ok = fabsf(dU - dc) <= gate && fabsf(dD - dc) <= gate && fabsf(dL - dc) <= gate &&
@@ -43,10 +56,10 @@ __global__ void __launch_bounds__(256) k_depth_prep(Cam cam, const float* __rest
             float3 vU = backproject(cam, x, y - 1, dU), vD = backproject(cam, x, y + 1, dD);
             float3 vL = backproject(cam, x - 1, y, dL), vR = backproject(cam, x + 1, y, dR);
             float3 a = sub3(vD, vU);   // V(x, y+1) - V(x, y-1)
-            float3 b = sub3(vR, vL);   // V(x+1, y) - V(x-1, y)
-            float c0 = a.y * b.z - a.z * b.y;
-            float c1 = a.z * b.x - a.x * b.z;
-            float c2 = a.x * b.y - a.y * b.x;
+            float3 bb = sub3(vR, vL);  // V(x+1, y) - V(x-1, y)
+            float c0 = a.y * bb.z - a.z * bb.y;
+            float c1 = a.z * bb.x - a.x * bb.z;
+            float c2 = a.x * bb.y - a.y * bb.x;
             float nn = (c0 * c0 + c1 * c1) + c2 * c2;
             if (nn > 0.f && nn < INFINITY) {
                 float ln = sqrtf(nn);
@@ -58,20 +71,8 @@ __global__ void __launch_bounds__(256) k_depth_prep(Cam cam, const float* __rest
             }
         }
     }
-    nmap[y * W + x] = out;
+    d.nmap[y * W + x] = out;
 }
-
-__global__ void k_clear_z(unsigned long long* __restrict__ z, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) z[i] = ~0ull;
-}
-
-struct SurfelArrays {
-    const float *px, *py, *pz, *nx, *ny, *nz;
-    const int4* idx;
-    const float4* w;
-    const int* orig;
-};
 
 __device__ __forceinline__ unsigned long long zkey(float z, int orig) {
     return ((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)(unsigned)orig;
@@ -80,38 +81,36 @@ __device__ __forceinline__ unsigned long long zkey(float z, int orig) {
 // ---------------------------------------------------------------------------
 // Warp + index map
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_warp_zbuf(int ns, SurfelArrays s, const float4* __restrict__ dq,
-                                                   Cam cam, unsigned long long* __restrict__ zbuf) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns) return;
-    float3 v = make_float3(s.px[i], s.py[i], s.pz[i]);
-    Warp wp = warp_surfel(s.idx[i], s.w[i], v, make_float3(0.f, 0.f, 0.f), dq);
+__global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const int i = at.tile * kWarpBlock + threadIdx.x;
+    if (i >= d.ns) return;
+    float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
+    Warp wp = warp_surfel(d.idx[i], d.w[i], v, make_float3(0.f, 0.f, 0.f), d.dq);
     if (!wp.ok) return;
     int ux, uy;
-    if (!project(cam, wp.v, ux, uy)) return;
-    atomicMin(&zbuf[uy * cam.W + ux], zkey(wp.v.z, s.orig[i]));
+    if (!project(d.cam, wp.v, ux, uy)) return;
+    atomicMin(&d.zbuf[uy * d.cam.W + ux], zkey(wp.v.z, d.orig[i]));
 }
 
 // ---------------------------------------------------------------------------
-// Correspondence, residual and Jacobian
+// Correspondence, residual and Jacobian. Each surfel's row [J | r | 0] (node
+// blocks by position within the surfel's ascending node set) is staged in
+// LDS and written out as whole 128-byte lines.
 // ---------------------------------------------------------------------------
-struct CorrOut {
-    float* J;              // [pitch][32]: 24 Jacobian entries (node position x 6), r, zero padding
-    double* part_e;        // per block sum of r^2
-    int* part_n;           // per block correspondence count
-    int pitch;
-    // capture (null unless this iteration is captured)
-    int* corr_map;
-    float* live_pos;
-};
+constexpr int kRowPad = 33;   // LDS row stride in floats (odd: no bank conflicts)
 
-__global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const float4* __restrict__ dq,
-        const float4* __restrict__ cl, Cam cam, const unsigned long long* __restrict__ zbuf,
-        const float4* __restrict__ nmap, float dist2, float cosn, CorrOut o) {
+__global__ void __launch_bounds__(kCorrBlock) k_corr_jac(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool live = i < ns;
+    __shared__ float rows[kCorrBlock / kWave][kWave * kRowPad];
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
+    const int i = at.tile * kCorrBlock + threadIdx.x;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const bool live = i < d.ns;
     float r = 0.f;
     float Jw[4][3], Jt[4][3];
 #pragma unroll
@@ -119,27 +118,28 @@ __global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const 
 #pragma unroll
         for (int c = 0; c < 3; ++c) { Jw[k][c] = 0.f; Jt[k][c] = 0.f; }
     bool matched = false;
-    int4 id = make_int4(0, 0, 0, 0);
+    int4 id = make_int4(0, 1, 2, 3);
     int pix = 0, org = 0;
     Warp wp;
     wp.ok = false;
     if (live) {
-        id = s.idx[i];
-        org = s.orig[i];
-        float3 v = make_float3(s.px[i], s.py[i], s.pz[i]);
-        float3 n = make_float3(s.nx[i], s.ny[i], s.nz[i]);
-        wp = warp_surfel(id, s.w[i], v, n, dq);
+        id = d.idx[i];
+        org = d.orig[i];
+        const float4 w4 = d.w[i];
+        float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
+        float3 n = make_float3(d.nx[i], d.ny[i], d.nz[i]);
+        wp = warp_surfel(id, w4, v, n, d.dq);
         int ux, uy;
-        if (wp.ok && project(cam, wp.v, ux, uy)) {
-            pix = uy * cam.W + ux;
-            if (zbuf[pix] == zkey(wp.v.z, org)) {
-                float4 nm = nmap[pix];
+        if (wp.ok && project(d.cam, wp.v, ux, uy)) {
+            pix = uy * d.cam.W + ux;
+            if (d.zbuf[pix] == zkey(wp.v.z, org)) {
+                float4 nm = d.nmap[pix];
                 if (nm.w > 0.f) {
-                    float3 V = backproject(cam, ux, uy, nm.w);
+                    float3 V = backproject(d.cam, ux, uy, nm.w);
                     float3 dv = sub3(wp.v, V);
                     float d2 = (dv.x * dv.x + dv.y * dv.y) + dv.z * dv.z;
                     float3 N = make_float3(nm.x, nm.y, nm.z);
-                    if (d2 < dist2 && dot3(wp.n, N) > cosn) {
+                    if (d2 < d.dist2 && dot3(wp.n, N) > d.cosn) {
                         matched = true;
                         r = dot3(N, dv);
                         // d r / d xi_k, closed form of N^T dF/db(b; v) w_k s_k M(q_k, c_k)
@@ -149,13 +149,12 @@ __global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const 
                         Q4 PV = qmul(P, Q4{0.f, v.x, v.y, v.z});
                         float ndv = dot3(N, wp.v);
                         const int ids[4] = {id.x, id.y, id.z, id.w};
-                        const float4 w4 = s.w[i];
                         const float wk[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            Q4 rk = q4(dq[2 * ids[k]]);
-                            Q4 dk = q4(dq[2 * ids[k] + 1]);
-                            float4 c4 = cl[ids[k]];
+                            Q4 rk = q4(d.dq[2 * ids[k]]);
+                            Q4 dk = q4(d.dq[2 * ids[k] + 1]);
+                            float4 c4 = d.cl[ids[k]];
                             float3 ck = make_float3(c4.x, c4.y, c4.z);
                             float a = (wk[k] * wp.sgn[k]) * wp.inv_beta;
                             float3 h = vec_mul_conj(P, rk);
@@ -173,27 +172,40 @@ __global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const 
             }
         }
     }
-    if (live) {
-        // one 128-byte row per surfel, node blocks by position within the
-        // surfel's ascending node set, then the residual
+    {
+        // stage the row: node block k goes to position = rank of its id in the set
+        float* row = &rows[wave][lane * kRowPad];
         const int ids[4] = {id.x, id.y, id.z, id.w};
-        float* row = o.J + (size_t)i * 32;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
-            float2* Jp = reinterpret_cast<float2*>(row + pos * 6);
-            Jp[0] = make_float2(Jw[k][0], Jw[k][1]);
-            Jp[1] = make_float2(Jw[k][2], Jt[k][0]);
-            Jp[2] = make_float2(Jt[k][1], Jt[k][2]);
+            const int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
+            float* o = row + pos * 6;
+            o[0] = Jw[k][0]; o[1] = Jw[k][1]; o[2] = Jw[k][2];
+            o[3] = Jt[k][0]; o[4] = Jt[k][1]; o[5] = Jt[k][2];
         }
         row[24] = r;
-        if (o.live_pos) {
-            float nanv = __int_as_float(0x7fc00000);
-            o.live_pos[3 * org + 0] = wp.ok ? wp.v.x : nanv;
-            o.live_pos[3 * org + 1] = wp.ok ? wp.v.y : nanv;
-            o.live_pos[3 * org + 2] = wp.ok ? wp.v.z : nanv;
-            if (matched) o.corr_map[pix] = org;
+#pragma unroll
+        for (int c = 25; c < 32; ++c) row[c] = 0.f;
+    }
+    __syncthreads();
+    {
+        // the wave's rows [base, base + 64) of the stream, two rows per store
+        const int base = at.tile * kCorrBlock + wave * kWave;
+        const float* src = rows[wave];
+        float* dst = d.J + (size_t)base * 32;
+        const int nrow = min(kWave, d.ns - base);
+#pragma unroll 4
+        for (int q = 0; q < kWave / 2; ++q) {
+            const int rr = 2 * q + (lane >> 5), c = lane & 31;
+            if (rr < nrow) dst[rr * 32 + c] = src[rr * kRowPad + c];
         }
+    }
+    if (live && capture) {
+        float nanv = __int_as_float(0x7fc00000);
+        d.dbg_live[3 * org + 0] = wp.ok ? wp.v.x : nanv;
+        d.dbg_live[3 * org + 1] = wp.ok ? wp.v.y : nanv;
+        d.dbg_live[3 * org + 2] = wp.ok ? wp.v.z : nanv;
+        if (matched) d.dbg_corr[pix] = org;
     }
     double e = block_sum((double)r * (double)r, sh);
     int cnt = wave_sumi(matched ? 1 : 0);
@@ -202,8 +214,8 @@ __global__ void __launch_bounds__(256) k_corr_jac(int ns, SurfelArrays s, const 
     if (threadIdx.x == 0) {
         int c = 0;
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
-        o.part_e[blockIdx.x] = e;
-        o.part_n[blockIdx.x] = c;
+        d.part_e[at.tile] = e;
+        d.part_n[at.tile] = c;
     }
 }
 
@@ -279,32 +291,15 @@ __global__ void k_pointer_positions(int n, const float* __restrict__ pos, float4
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-void launch_depth_prep(const Cam& cam, const float* depth, float gate, float4* nmap, unsigned long long* zbuf,
-                       int* flags, hipStream_t st) {
-    dim3 grid((cam.W + 15) / 16, (cam.H + 15) / 16);
-    hipLaunchKernelGGL(k_depth_prep, grid, dim3(256), 0, st, cam, depth, gate, nmap, zbuf, flags);
-}
-
-void launch_clear_z(unsigned long long* z, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_clear_z, dim3((n + 255) / 256), dim3(256), 0, st, z, n);
-}
-
-void launch_warp_zbuf(int ns, const SurfelView& sv, const float4* dq, const Cam& cam, unsigned long long* z,
-                      hipStream_t st) {
-    SurfelArrays s{sv.px, sv.py, sv.pz, sv.nx, sv.ny, sv.nz, sv.idx, sv.w, sv.orig};
-    hipLaunchKernelGGL(k_warp_zbuf, dim3((ns + 255) / 256), dim3(256), 0, st, ns, s, dq, cam, z);
-}
-
-int corr_blocks(int ns) { return (ns + 255) / 256; }
-
-void launch_corr_jac(int ns, const SurfelView& sv, const float4* dq, const float4* cl, const Cam& cam,
-                     const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J,
-                     int pitch, double* part_e, int* part_n, int* corr_map, float* live_pos,
-                     hipStream_t st) {
-    SurfelArrays s{sv.px, sv.py, sv.pz, sv.nx, sv.ny, sv.nz, sv.idx, sv.w, sv.orig};
-    CorrOut o{J, part_e, part_n, pitch, corr_map, live_pos};
-    hipLaunchKernelGGL(k_corr_jac, dim3(corr_blocks(ns)), dim3(256), 0, st, ns, s, dq, cl, cam, z, nmap, dist2,
-                       cosn, o);
+void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStream_t st) {
+    const int grid = b.off[b.n];
+    if (grid <= 0) return;
+    switch (stage) {
+        case kStDepth: hipLaunchKernelGGL(k_depth_prep, dim3(grid), dim3(256), 0, st, b, *depth); break;
+        case kStWarp: hipLaunchKernelGGL(k_warp_zbuf, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
+        case kStCorr: hipLaunchKernelGGL(k_corr_jac, dim3(grid), dim3(kCorrBlock), 0, st, b); break;
+        default: break;
+    }
 }
 
 void launch_nodes_from_se3(int nn, const float* se3, const float4* pref, float4* rq, float4* tt, float4* dq,

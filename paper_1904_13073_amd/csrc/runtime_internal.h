@@ -1,0 +1,130 @@
+// Host-side objects shared by the C ABI files: device arenas, executors (a
+// HIP stream with its statistics buffers and timing events) and the stream
+// object itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "swgn.h"
+#include "swgn_frame.h"
+
+namespace swgn {
+namespace rt {
+
+constexpr int kMaxNodes = 32768;
+constexpr int64_t kMaxSurfels = (int64_t)1 << 28;
+
+struct HipFail {
+    hipError_t e;
+    std::string what;
+};
+
+#define SWGN_HIP(x)                                                         \
+    do {                                                                    \
+        hipError_t _e = (x);                                                \
+        if (_e != hipSuccess) throw ::swgn::rt::HipFail{_e, std::string(#x)}; \
+    } while (0)
+
+// Device allocations released together.
+class Arena {
+public:
+    ~Arena() { release(); }
+    void* raw(size_t bytes);
+    template <class T>
+    T* alloc(size_t n) {
+        return static_cast<T*>(raw(n * sizeof(T)));
+    }
+    void release();
+
+private:
+    std::vector<void*> ptrs_;
+};
+
+// A HIP stream plus what a solve needs besides the streams' own memory: the
+// device and pinned host slots of the statistics copy (kMaxBatch streams)
+// and timing events.
+struct Executor {
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    char* stats_dev = nullptr;
+    void* stats_host = nullptr;
+    std::vector<hipEvent_t> events;
+    ~Executor();
+    void init(void* hip_stream);
+    hipEvent_t event(size_t i);
+};
+
+inline sw_status fail(std::string& err, sw_status code, const std::string& msg) {
+    err = msg;
+    return code;
+}
+
+template <class F>
+sw_status guarded(std::string& err, F&& f) {
+    try {
+        return f();
+    } catch (const HipFail& h) {
+        const sw_status code =
+            (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) ? SW_ENOMEM : SW_EHIP;
+        return fail(err, code, h.what + ": " + hipGetErrorString(h.e));
+    } catch (const std::bad_alloc&) {
+        return fail(err, SW_ENOMEM, "host allocation failed");
+    }
+}
+
+size_t carve_workspace(FrameDesc& h, char* base);
+
+}  // namespace rt
+}  // namespace swgn
+
+struct sw_stream_s {
+    sw_config cfg{};
+    swgn::Cam cam{};
+    std::string err;
+    swgn::rt::Executor exec;              // the stream's own HIP stream
+    swgn::rt::Arena frame_mem, surf_mem, graph_mem, ws_mem;
+    uint64_t generation = 0;              // bumped whenever device buffers are replaced
+
+    // surfels as given
+    int64_t ns = 0;
+    float* in_pos = nullptr;
+    float* in_nrm = nullptr;
+    bool surfels_set = false;
+    bool graph_set = false;
+    sw_server server = nullptr;           // set while attached to a serving loop
+
+    // descriptor: host copy, pinned staging copy and the device copy kernels read
+    swgn::FrameDesc h{};
+    swgn::FrameDesc* h_pinned = nullptr;
+    swgn::FrameDesc* d_desc = nullptr;
+    size_t ws_bytes = 0;
+
+    // captured iteration (allocated only when the config asks for a capture)
+    int* dbg_index = nullptr;
+    float *dbg_H = nullptr, *dbg_g = nullptr, *dbg_x = nullptr, *dbg_J = nullptr;
+    bool captured = false;
+
+    ~sw_stream_s() {
+        if (h_pinned) (void)hipHostFree(h_pinned);
+    }
+};
+
+namespace swgn {
+namespace rt {
+void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const std::vector<int>& its, int pcg_it,
+               const DepthIn* depth, bool timing, std::vector<int>& ev_stage);
+void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths, int32_t on_device,
+                   bool timing, std::vector<int>& ev);
+void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std::vector<int>& its, bool timing,
+                       std::vector<int>& ev, std::vector<char>& captured);
+sw_status collect_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
+                         sw_frame_stats* stats, sw_status* status);
+void server_quiesce(sw_server sv, sw_stream s);
+void server_forget(sw_server sv, sw_stream s);
+sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths,
+                       int32_t on_device, bool timing, sw_frame_stats* stats, sw_status* status);
+}  // namespace rt
+}  // namespace swgn

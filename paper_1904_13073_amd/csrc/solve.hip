@@ -16,6 +16,7 @@
 // identical decisions and a solve is bit-reproducible.
 #include <algorithm>
 
+#include "swgn_frame.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
 
@@ -23,40 +24,7 @@ namespace swgn {
 
 namespace {
 
-struct SolveArgs {
-    int nn, npx;
-    const int* row_ptr;
-    const float* H;
-    const float* g;
-    int ell_w;                 // ELL row width (multiple of 8)
-    const uint32_t* ell_blk;   // [nn][ell_w] block id (bit 31 = transposed), ~0 = padding
-    const int* ell_col;        // [nn][ell_w] column node
-    double* Minv;
-    float *x, *r, *z, *q, *p0, *p1;
-    double* sc;          // sc[2 it] = rho_it
-    double* part_rho;    // per-workgroup partials of r.z (init or update)
-    double* part_rr;     // ... of r.r
-    double* part_pq;     // per-workgroup partials of p.q (spmv)
-    int* flags;
-    const double* part_e;
-    const int* part_n;
-    int nparts;
-    const float* ereg;
-    IterStats* stats;
-    const float4* pref;
-    float4 *rq, *tt, *dq, *cl;
-    unsigned long long* zbuf;
-};
-
-constexpr int kInitBlock = 256;     // 32 nodes x 8 lanes
-constexpr int kUpdBlock = 256;      // 32 nodes x 8 lanes
-constexpr int kRowsPerSpmvBlock = 4;
-
-int init_blocks(int nn) { return (8 * nn + kInitBlock - 1) / kInitBlock; }
-int upd_blocks(int nn) { return (8 * nn + kUpdBlock - 1) / kUpdBlock; }
-int spmv_blocks(int nn) { return (nn + kRowsPerSpmvBlock - 1) / kRowsPerSpmvBlock; }
-
-__device__ void update_node(const SolveArgs& a, int k) {
+__device__ void update_node(const FrameDesc& a, int k) {
     const float* x = a.x + 6 * k;
     float3 w = make_float3(x[0], x[1], x[2]);
     float3 tau = make_float3(x[3], x[4], x[5]);
@@ -94,9 +62,11 @@ __device__ void update_node(const SolveArgs& a, int k) {
 // Gauss-Jordan elimination leaves row a of the inverse. Without pivoting the
 // pivots of a symmetric matrix are all positive exactly when it is positive
 // definite, which is checked.
-__global__ void __launch_bounds__(kInitBlock) k_pcg_init(SolveArgs a) {
+__global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     __shared__ double sh[40];
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    const int gid = at.tile * kSolveBlock + threadIdx.x;
     const int k = gid >> 3, row = gid & 7, base = threadIdx.x & ~7;
     const bool on = (k < a.nn) && (row < 6);
     double m[12];
@@ -143,21 +113,24 @@ __global__ void __launch_bounds__(kInitBlock) k_pcg_init(SolveArgs a) {
     rho = block_sum(rho, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        a.part_rho[blockIdx.x] = rho;
-        a.part_rr[blockIdx.x] = rr;
+        a.part_rho[at.tile] = rho;
+        a.part_rr[at.tile] = rr;
     }
 }
 
 // q = A p_it with p_it = z + beta p_{it-1} (beta = 0 and p_0 = z at it = 0).
 // The row's products with z and with p_{it-1} are accumulated separately, so
 // the matrix loads run before beta (a grid-wide sum) is known.
-__global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a, int it, int n_rho_parts) {
+__global__ void __launch_bounds__(64 * kSpmvRows) k_pcg_spmv(Batch b) {
     __shared__ double sh[40];
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    const int it = b.pcg_it;
     float* const pbuf[2] = {a.p0, a.p1};
     const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];
     float* pcur = pbuf[it & 1];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int k = blockIdx.x * kRowsPerSpmvBlock + wave;
+    const int k = at.tile * kSpmvRows + wave;
     const int sub = lane & 7, fl = lane >> 3;
     float az = 0.f, ap = 0.f;
     if (k < a.nn && sub < 6) {
@@ -184,10 +157,10 @@ __global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a
     ap += __shfl_xor(ap, 8, kWave);
     ap += __shfl_xor(ap, 16, kWave);
     ap += __shfl_xor(ap, 32, kWave);
-    const double rho = reduce_partials(a.part_rho, n_rho_parts, sh);
+    const double rho = reduce_partials(a.part_rho, solve_tiles(a), sh);
     const bool stop = (rho == 0.0);
-    const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[2 * (it - 1)]) : 0.f;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.sc[2 * it] = rho;
+    const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[(it - 1) & 1]) : 0.f;
+    if (at.tile == 0 && threadIdx.x == 0) a.sc[it & 1] = rho;   // read by this iteration's update
     double pq = 0.0;
     if (!stop && k < a.nn && lane < 6) {
         const int t = 6 * k + lane;
@@ -198,13 +171,16 @@ __global__ void __launch_bounds__(64 * kRowsPerSpmvBlock) k_pcg_spmv(SolveArgs a
         pq = (double)pk * (double)qv;
     }
     pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = pq;
+    if (threadIdx.x == 0) a.part_pq[at.tile] = pq;
 }
 
-__global__ void __launch_bounds__(kUpdBlock) k_pcg_update(SolveArgs a, int it, int n_pq_parts) {
+__global__ void __launch_bounds__(kSolveBlock) k_pcg_update(Batch b) {
     __shared__ double sh[40];
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    const int it = b.pcg_it;
     const float* p = (it & 1) ? a.p1 : a.p0;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = at.tile * kSolveBlock + threadIdx.x;
     const int k = gid >> 3, c = gid & 7;
     const bool on = (k < a.nn) && (c < 6);
     const int t = 6 * k + c;
@@ -218,9 +194,9 @@ __global__ void __launch_bounds__(kUpdBlock) k_pcg_update(SolveArgs a, int it, i
 #pragma unroll
         for (int j = 0; j < 6; ++j) mrow[j] = 0.0;
     }
-    const double rho = a.sc[2 * it];
+    const double rho = a.sc[it & 1];
     const bool stop = (rho == 0.0);
-    const double pq = reduce_partials(a.part_pq, n_pq_parts, sh);
+    const double pq = reduce_partials(a.part_pq, spmv_tiles(a), sh);
     double rz = 0.0, rr = 0.0;
     if (!stop) {
         const float alpha = (float)(rho / pq);
@@ -245,64 +221,66 @@ __global__ void __launch_bounds__(kUpdBlock) k_pcg_update(SolveArgs a, int it, i
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        a.part_rho[blockIdx.x] = rz;
-        a.part_rr[blockIdx.x] = rr;
+        a.part_rho[at.tile] = rz;
+        a.part_rr[at.tile] = rr;
     }
 }
 
-__global__ void __launch_bounds__(256) k_node_update(SolveArgs a, int n_rr_parts) {
+__global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
     __shared__ double sh[40];
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    const int gid = at.tile * kNodeBlock + threadIdx.x;
     if (gid < a.nn) update_node(a, gid);
     if (gid < a.npx) a.zbuf[gid] = ~0ull;     // index map of the next iteration
-    if (blockIdx.x == 0) {
-        const double rr = reduce_partials(a.part_rr, n_rr_parts, sh);
+    if (at.tile == 0) {
+        const int nparts = corr_tiles(a);
+        IterStats* stats = a.stats + b.it[at.s];
+        const double rr = reduce_partials(a.part_rr, solve_tiles(a), sh);
         // energies at this iteration's linearisation point
         double e = 0.0, n = 0.0, er = 0.0;
-        for (int t = threadIdx.x; t < a.nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
+        for (int t = threadIdx.x; t < nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
         for (int t = threadIdx.x; t < a.nn; t += blockDim.x) er += (double)a.ereg[t];
         e = block_sum(e, sh);
         n = block_sum(n, sh);
         er = block_sum(er, sh);
         if (threadIdx.x == 0) {
-            a.stats->pcg_resid = sqrt(rr);
-            a.stats->e_data = e;
-            a.stats->e_reg = er;
-            a.stats->n_corr = (int)n;
+            stats->pcg_resid = sqrt(rr);
+            stats->e_data = e;
+            stats->e_reg = er;
+            stats->n_corr = (int)n;
             if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
         }
     }
 }
 
+// Copies each stream's iteration statistics and failure flags to slot s of
+// `out` (kStatsOutBytes per stream), so one copy brings a whole batch's back.
+__global__ void __launch_bounds__(64) k_stats_out(Batch b, char* __restrict__ out) {
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    int* dst = reinterpret_cast<int*>(out + (size_t)at.s * kStatsOutBytes);
+    const int* src = reinterpret_cast<const int*>(a.stats);
+    constexpr int nw = (int)(sizeof(IterStats) * kMaxIters / 4);
+    for (int t = threadIdx.x; t < nw; t += 64) dst[t] = src[t];
+    if (threadIdx.x < 4) dst[nw + threadIdx.x] = a.flags[threadIdx.x];
+}
+
 }  // namespace
 
-int solve_partials_size(int nn) { return std::max(std::max(init_blocks(nn), upd_blocks(nn)), spmv_blocks(nn)); }
-
-static SolveArgs solve_args(const SolveStepArgs& s) {
-    return SolveArgs{s.nn, s.npx, s.row_ptr, s.H, s.g, s.ell_w, s.ell_blk, s.ell_col, s.Minv, s.x, s.r, s.z, s.q, s.p0,
-                     s.p1, s.sc, s.part_rho, s.part_rr, s.part_pq, s.flags, s.part_e, s.part_n, s.nparts, s.ereg,
-                     static_cast<IterStats*>(s.stats), s.pref, s.rq, s.tt, s.dq, s.cl, s.zbuf};
-}
-
-void launch_pcg_init(const SolveStepArgs& s, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(init_blocks(s.nn)), dim3(kInitBlock), 0, st, solve_args(s));
-}
-
-void launch_pcg_spmv(const SolveStepArgs& s, int it, hipStream_t st) {
-    const int n_rho = it == 0 ? init_blocks(s.nn) : upd_blocks(s.nn);
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(spmv_blocks(s.nn)), dim3(64 * kRowsPerSpmvBlock), 0, st, solve_args(s), it,
-                       n_rho);
-}
-
-void launch_pcg_update(const SolveStepArgs& s, int it, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(upd_blocks(s.nn)), dim3(kUpdBlock), 0, st, solve_args(s), it,
-                       spmv_blocks(s.nn));
-}
-
-void launch_node_update(const SolveStepArgs& s, int pcg_iters, hipStream_t st) {
-    const int n_rr = pcg_iters == 0 ? init_blocks(s.nn) : upd_blocks(s.nn);
-    const int grid = (std::max(s.nn, s.npx) + 255) / 256;
-    hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(256), 0, st, solve_args(s), n_rr);
+void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t st) {
+    const int grid = b.off[b.n];
+    if (grid <= 0) return;
+    switch (stage) {
+        case kStPcgInit: hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kSolveBlock), 0, st, b); break;
+        case kStSpmv: hipLaunchKernelGGL(k_pcg_spmv, dim3(grid), dim3(64 * kSpmvRows), 0, st, b); break;
+        case kStUpdate: hipLaunchKernelGGL(k_pcg_update, dim3(grid), dim3(kSolveBlock), 0, st, b); break;
+        case kStNodeUpdate: hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
+        case kStStatsOut:
+            hipLaunchKernelGGL(k_stats_out, dim3(grid), dim3(64), 0, st, b, static_cast<char*>(stats_out));
+            break;
+        default: break;
+    }
 }
 
 }  // namespace swgn

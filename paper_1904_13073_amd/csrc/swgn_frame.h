@@ -1,0 +1,147 @@
+// Per-stream frame descriptor and the batch work list of the per-frame kernels.
+//
+// Every per-frame kernel runs over a batch of streams in one launch: the grid
+// is the concatenation of each stream's tiles, `Batch::off` is the prefix of
+// tile counts, and a workgroup finds its stream by binary search over it. A
+// stream's descriptor (device memory, written by the host when the stream's
+// buffers change) holds its shapes, gates and every device pointer the kernels
+// use. A workgroup computes from its own stream's data and its tile index in
+// that stream only, so a stream's results do not depend on what else is in
+// the batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swgn_impl.h"
+
+namespace swgn {
+
+constexpr int kMaxBatch = 64;
+constexpr int kMaxIters = 16;
+constexpr int kMaxPcg = 4096;
+
+// Launch geometry of the per-frame kernels.
+constexpr int kDepthTile = 16;        // 16 x 16 pixels per workgroup
+constexpr int kWarpBlock = 256;       // surfels per workgroup
+constexpr int kCorrBlock = 256;
+constexpr int kSegWaves = 4;          // segments per workgroup (one wave each)
+constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
+constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes
+constexpr int kSpmvRows = 4;          // block rows per workgroup (one wave each)
+constexpr int kNodeBlock = 256;
+
+constexpr int kSegLen = 128;          // surfels per segment at most (one node set)
+constexpr int kSegSlots = 400;        // per segment: 10 upper 6x6 blocks, J^T r (24), r^T r, pad
+
+struct FrameDesc {
+    // shapes
+    int ns, nn, nb, noff, nseg, pitch, npx, ell_w;
+    int pcg_iters, debug_iter, pad0, pad1;
+    Cam cam;
+    float edge_gate, dist2, cosn, lambda, mu, pad2;
+    // resident: surfels sorted by node set; orig = caller's index
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    const int4* idx;
+    const float4* w;
+    const int* orig;
+    // resident: nodes
+    const float4* pref;
+    float4 *rq, *tt, *dq, *cl;
+    const int* nbr;
+    // resident: upper block pattern and the assembly / product work lists
+    const int *row_ptr, *col_idx, *blk_row, *offlist, *seg_start, *ent_ptr;
+    const uint32_t* ent;
+    const int *in_ptr, *in_list;
+    const uint32_t* ell_blk;
+    const int* ell_col;
+    // resident: capture of one iteration (null unless requested)
+    int* dbg_corr;
+    float* dbg_live;
+    // workspace of a frame in flight
+    float* depth;                 // copy of a host depth image
+    float4* nmap;                 // (normal, depth) per pixel
+    unsigned long long* zbuf;     // index map: (z bits << 32 | surfel) per pixel
+    int* flags;                   // [4] failure bits of the frame
+    IterStats* stats;             // [kMaxIters]
+    float4 *rq_bak, *tt_bak;      // node state at the start of the frame
+    float* J;                     // [pitch][32]: 24 Jacobian entries, r, zero padding
+    float* part;                  // [nseg][kSegSlots] segment Gram sub-blocks
+    float *H, *g, *ereg;
+    double* Minv;                 // [nn][36] block-Jacobi inverses
+    double* part_e;               // correspondence pass partials
+    int* part_n;
+    float *x, *r, *z, *q, *p0, *p1;
+    double *sc, *part_rho, *part_rr, *part_pq;
+};
+
+// Tiles (workgroups) of each per-frame stage for one stream.
+enum Stage {
+    kStDepth = 0, kStWarp, kStCorr, kStAsmSeg, kStPcgInit, kStSpmv, kStUpdate, kStNodeUpdate, kStAsmFold,
+    kStStatsOut, kNumStages
+};
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int corr_tiles(const FrameDesc& d) { return cdiv(d.ns, kCorrBlock); }
+__host__ __device__ inline int solve_tiles(const FrameDesc& d) { return cdiv(8 * d.nn, kSolveBlock); }
+__host__ __device__ inline int spmv_tiles(const FrameDesc& d) { return cdiv(d.nn, kSpmvRows); }
+
+inline int stage_tiles(int stage, const FrameDesc& d) {
+    switch (stage) {
+        case kStDepth: {
+            const int px = cdiv(d.cam.W, kDepthTile) * cdiv(d.cam.H, kDepthTile);
+            const int nt = cdiv(d.nn, kDepthTile * kDepthTile);
+            return px > nt ? px : nt;
+        }
+        case kStWarp: return cdiv(d.ns, kWarpBlock);
+        case kStCorr: return corr_tiles(d);
+        case kStAsmSeg: return cdiv(d.nseg, kSegWaves);
+        case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
+        case kStPcgInit: return solve_tiles(d);
+        case kStSpmv: return spmv_tiles(d);
+        case kStUpdate: return solve_tiles(d);
+        case kStNodeUpdate: return cdiv(d.nn > d.npx ? d.nn : d.npx, kNodeBlock);
+        case kStStatsOut: return 1;
+        default: return 0;
+    }
+}
+
+// Work list of one launch, passed by value as a kernel argument.
+struct Batch {
+    int n;                        // streams
+    int pcg_it;                   // PCG iteration of this launch
+    int off[kMaxBatch + 1];       // stream s owns tiles [off[s], off[s+1])
+    const FrameDesc* d[kMaxBatch];
+    int8_t it[kMaxBatch];         // Gauss-Newton iteration of each stream
+};
+
+struct DepthIn {
+    const float* p[kMaxBatch];    // depth image of each stream (device)
+};
+
+struct Where {
+    int s;       // stream index in the batch
+    int tile;    // tile index within the stream
+};
+
+// Largest s with off[s] <= tile (streams with no tiles are skipped).
+__device__ __forceinline__ Where locate(const Batch& b) {
+    const int t = blockIdx.x;
+    int lo = 0, hi = b.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return Where{lo, t - b.off[lo]};
+}
+
+// Launchers (one per kernel file); grid = b.off[b.n] workgroups.
+void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStream_t st);
+void launch_asm_stage(int stage, const Batch& b, hipStream_t st);
+void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t st);
+
+// Bytes per stream written by the statistics copy: kMaxIters IterStats, then
+// the failure flags.
+constexpr int kStatsOutBytes = (int)(sizeof(IterStats) * kMaxIters) + 16;
+
+}  // namespace swgn

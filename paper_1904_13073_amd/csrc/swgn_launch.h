@@ -1,4 +1,5 @@
-// Host-side launchers of the setup and per-frame kernels.
+// Host-side launchers of the setup kernels and the node-state helpers; the
+// per-frame stages are launched through swgn_frame.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,63 +7,6 @@
 #include <stdint.h>
 
 namespace swgn {
-
-struct Cam;
-
-struct SurfelView {
-    const float *px, *py, *pz, *nx, *ny, *nz;
-    const int4* idx;
-    const float4* w;
-    const int* orig;
-};
-
-constexpr int kSegLen = 128;      // surfels per segment at most (one node set)
-constexpr int kSegSlots = 400;    // per segment: 10 upper 6x6 blocks, J^T r (24), r^T r
-
-struct AssembleArgs {
-    int nb, nn, noff, pitch, nseg;
-    const int* blk_row;
-    const int* col_idx;
-    const int* row_ptr;
-    const int* offlist;
-    const int* seg_start;    // [nseg + 1] surfel ranges sharing one node set
-    const int* ent_ptr;      // [nb + 1] per block: its (segment, pos_a, pos_b) entries
-    const uint32_t* ent;     // (segment << 4 | pos_a << 2 | pos_b)
-    const int* in_ptr;       // node -> in-edges (j with the node in N_j)
-    const int* in_list;
-    const float* J;          // [pitch][32]: J (24), r, zero padding
-    const int* nbr;
-    const float4* pref;
-    const float4* rq;
-    const float4* cl;
-    float lambda, mu;
-    float* part;             // [nseg][kSegSlots] segment Gram sub-blocks
-    float* H;
-    float* g;
-    float* ereg;
-};
-
-struct SolveStepArgs {
-    int nn, npx;
-    const int* row_ptr;
-    const float* H;
-    const float* g;
-    int ell_w;
-    const uint32_t* ell_blk;
-    const int* ell_col;
-    double* Minv;
-    float *x, *r, *z, *q, *p0, *p1;
-    double *sc, *part_rho, *part_rr, *part_pq;
-    int* flags;
-    const double* part_e;
-    const int* part_n;
-    int nparts;
-    const float* ereg;
-    void* stats;
-    const float4* pref;
-    float4 *rq, *tt, *dq, *cl;
-    unsigned long long* zbuf;
-};
 
 // setup
 void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, float inv_two_sigma2, int4* idx,
@@ -96,24 +40,8 @@ void launch_in_edge_store(int n, const uint32_t* val, int* in_list, hipStream_t 
 void launch_ell(int nn, int ell_w, const int* frow_ptr, const uint32_t* fblk, const int* fcol, uint32_t* ell_blk,
                 int* ell_col, hipStream_t st);
 
-// per frame
-void launch_depth_prep(const Cam& cam, const float* depth, float gate, float4* nmap, unsigned long long* zbuf,
-                       int* flags, hipStream_t st);
-void launch_clear_z(unsigned long long* z, int n, hipStream_t st);
-void launch_warp_zbuf(int ns, const SurfelView& sv, const float4* dq, const Cam& cam, unsigned long long* z,
-                      hipStream_t st);
-int corr_blocks(int ns);
-void launch_corr_jac(int ns, const SurfelView& sv, const float4* dq, const float4* cl, const Cam& cam,
-                     const unsigned long long* z, const float4* nmap, float dist2, float cosn, float* J, int pitch,
-                     double* part_e, int* part_n, int* corr_map, float* live_pos, hipStream_t st);
+// node state and capture helpers
 void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist, hipStream_t st);
-void launch_assemble_segments(const AssembleArgs& a, hipStream_t st);
-void launch_assemble_fold(const AssembleArgs& a, hipStream_t st);
-int solve_partials_size(int nn);
-void launch_pcg_init(const SolveStepArgs& a, hipStream_t st);
-void launch_pcg_spmv(const SolveStepArgs& a, int it, hipStream_t st);
-void launch_pcg_update(const SolveStepArgs& a, int it, hipStream_t st);
-void launch_node_update(const SolveStepArgs& a, int pcg_iters, hipStream_t st);
 void launch_nodes_from_se3(int nn, const float* se3, const float4* pref, float4* rq, float4* tt, float4* dq,
                            float4* cl, hipStream_t st);
 void launch_node_se3_out(int nn, const float4* rq, const float4* tt, float* out, hipStream_t st);

@@ -41,6 +41,24 @@ class SwFrameStats(C.Structure):
                     stage_us=list(self.stage_us[:9]), alg_bytes=self.alg_bytes)
 
 
+class SwServerConfig(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("reserved", C.c_int32), ("workspace_bytes", C.c_int64)]
+
+
+class SwTicketInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class SwServerInfo(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("frames_done", C.c_int64), ("max_in_flight", C.c_int32),
+                ("pending", C.c_int32), ("in_flight", C.c_int32), ("reserved", C.c_int32),
+                ("workspace_bytes", C.c_int64), ("workspace_peak", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class SwError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -53,7 +71,14 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_destroy_stream", "sw_set_reference_surfels", "sw_set_node_graph", "sw_set_node_se3",
            "sw_solve_frame", "sw_get_node_se3", "sw_get_sizes", "sw_get_skinning",
            "sw_get_node_graph", "sw_get_pattern", "sw_get_last_maps", "sw_get_last_system",
-           "sw_get_last_jacobian"]
+           "sw_get_last_jacobian", "sw_create_batch", "sw_destroy_batch", "sw_batch_last_error",
+           "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
+           "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
+           "sw_server_submit", "sw_server_poll", "sw_server_counters"]
+
+SW_EPENDING = 1
+
+SW_BATCH_TIMING = 1
 
 
 def lib() -> C.CDLL:
@@ -83,6 +108,21 @@ def lib() -> C.CDLL:
         "sw_get_last_maps": (i32, [vp, ip, ip, fp, fp]),
         "sw_get_last_system": (i32, [vp, fp, fp, fp]),
         "sw_get_last_jacobian": (i32, [vp, fp, fp]),
+        "sw_create_batch": (i32, [vp, i32, C.POINTER(vp)]),
+        "sw_destroy_batch": (i32, [vp]),
+        "sw_batch_last_error": (C.c_char_p, [vp]),
+        "sw_solve_batch": (i32, [vp, C.POINTER(vp), i32, C.POINTER(vp), i32, C.POINTER(SwFrameStats),
+                                 C.POINTER(i32)]),
+        "sw_profile_stage": (i32, [vp, C.POINTER(vp), i32, i32, i32, i32, C.POINTER(C.c_float)]),
+        "sw_server_config_default": (None, [C.POINTER(SwServerConfig)]),
+        "sw_create_server": (i32, [C.POINTER(SwServerConfig), vp, C.POINTER(vp)]),
+        "sw_destroy_server": (i32, [vp]),
+        "sw_server_last_error": (C.c_char_p, [vp]),
+        "sw_server_attach": (i32, [vp, vp]),
+        "sw_server_detach": (i32, [vp, vp]),
+        "sw_server_submit": (i32, [vp, vp, fp, i32, C.POINTER(C.c_uint64)]),
+        "sw_server_poll": (i32, [vp, C.c_uint64, i32, C.POINTER(SwFrameStats), C.POINTER(SwTicketInfo)]),
+        "sw_server_counters": (i32, [vp, C.POINTER(SwServerInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -162,6 +202,135 @@ def sw_solve_frame(h, depth, with_stats: bool = True):
     stats = SwFrameStats()
     _check(h, lib().sw_solve_frame(h, p, dev, C.byref(stats) if with_stats else None))
     return stats.as_dict() if with_stats else None
+
+
+def sw_create_batch(hip_stream: Optional[int] = None, flags: int = 0):
+    h = C.c_void_p()
+    st = lib().sw_create_batch(C.c_void_p(hip_stream) if hip_stream else None, int(flags), C.byref(h))
+    if st != SW_OK:
+        raise SwError(st, lib().sw_status_string(st).decode())
+    return h
+
+
+def sw_destroy_batch(b):
+    lib().sw_destroy_batch(b)
+
+
+def sw_solve_batch(b, handles, depths, with_stats: bool = True, raise_numeric: bool = True):
+    """Solve one frame per stream handle; returns (stats dicts or None, per-stream statuses)."""
+    n = len(handles)
+    if len(depths) != n:
+        raise ValueError("one depth image per stream")
+    ptrs, devs, keep = [], [], []
+    for d in depths:
+        p, dev, ka = _ptr(d, np.float32)
+        ptrs.append(p)
+        devs.append(dev)
+        keep.append(ka)
+    if len(set(devs)) > 1:
+        raise ValueError("depths must be all host arrays or all device tensors")
+    hs = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    ds = (C.c_void_p * n)(*[p.value for p in ptrs])
+    stats = (SwFrameStats * n)()
+    status = (C.c_int32 * n)()
+    st = lib().sw_solve_batch(b, hs, n, ds, devs[0], stats if with_stats else None, status)
+    if st != SW_OK and not (st == SW_ENUMERIC and not raise_numeric):
+        msg = lib().sw_batch_last_error(b).decode()
+        raise SwError(st, f"{lib().sw_status_string(st).decode()}: {msg}")
+    return ([stats[i].as_dict() for i in range(n)] if with_stats else None), list(status)
+
+
+class Batch:
+    """A batch executor: solves one frame for each of several Streams per call."""
+
+    def __init__(self, hip_stream: Optional[int] = None, timing: bool = False):
+        self.h = sw_create_batch(hip_stream, SW_BATCH_TIMING if timing else 0)
+
+    def close(self):
+        if self.h:
+            sw_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, streams, depths, with_stats: bool = True, raise_numeric: bool = True):
+        return sw_solve_batch(self.h, [s.h for s in streams], depths, with_stats, raise_numeric)
+
+    def profile_stage(self, streams, stage: int, reps: int = 100, pcg_it: int = 0) -> float:
+        """Mean microseconds per launch of one stage over these streams."""
+        n = len(streams)
+        hs = (C.c_void_p * n)(*[s.h.value for s in streams])
+        us = C.c_float()
+        st = lib().sw_profile_stage(self.h, hs, n, int(stage), int(pcg_it), int(reps), C.byref(us))
+        if st != SW_OK:
+            raise SwError(st, f"{lib().sw_status_string(st).decode()}: {lib().sw_batch_last_error(self.h).decode()}")
+        return us.value
+
+
+class Server:
+    """Serving loop: attach Streams, submit frames as they arrive, poll tickets."""
+
+    def __init__(self, max_batch: int = 32, workspace_bytes: int = 4 << 30, hip_stream: Optional[int] = None):
+        cfg = SwServerConfig()
+        lib().sw_server_config_default(C.byref(cfg))
+        cfg.max_batch = int(max_batch)
+        cfg.workspace_bytes = int(workspace_bytes)
+        h = C.c_void_p()
+        st = lib().sw_create_server(C.byref(cfg), C.c_void_p(hip_stream) if hip_stream else None, C.byref(h))
+        if st != SW_OK:
+            raise SwError(st, lib().sw_status_string(st).decode())
+        self.h = h
+        self._keep = {}
+
+    def _check(self, st: int):
+        if st != SW_OK:
+            raise SwError(st, f"{lib().sw_status_string(st).decode()}: {lib().sw_server_last_error(self.h).decode()}")
+
+    def close(self):
+        if self.h:
+            lib().sw_destroy_server(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def attach(self, stream):
+        self._check(lib().sw_server_attach(self.h, stream.h))
+
+    def detach(self, stream):
+        self._check(lib().sw_server_detach(self.h, stream.h))
+
+    def submit(self, stream, depth) -> int:
+        p, dev, ka = _ptr(depth, np.float32)
+        t = C.c_uint64()
+        self._check(lib().sw_server_submit(self.h, stream.h, p, dev, C.byref(t)))
+        if dev:
+            self._keep[t.value] = ka       # a device image must outlive its frame
+        return t.value
+
+    def poll(self, ticket: int, wait_ms: int = -1):
+        """(stats dict, info dict) when the frame is done, None while it is pending."""
+        stats, info = SwFrameStats(), SwTicketInfo()
+        st = lib().sw_server_poll(self.h, C.c_uint64(ticket), int(wait_ms), C.byref(stats), C.byref(info))
+        if st == SW_EPENDING:
+            return None
+        self._check(st)
+        self._keep.pop(ticket, None)
+        return stats.as_dict(), {"status": info.status, "t_submit": info.t_submit, "t_admit": info.t_admit,
+                                 "t_done": info.t_done}
+
+    def counters(self) -> dict:
+        out = SwServerInfo()
+        self._check(lib().sw_server_counters(self.h, C.byref(out)))
+        return out.as_dict()
 
 
 def sw_get_sizes(h):

@@ -63,3 +63,34 @@ def test_create_rejects_bad_config(field, value):
     h = C.c_void_p()
     st = swgn.lib().sw_create_stream(C.byref(c), None, C.byref(h))
     assert st == swgn.SW_EINVAL and not h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_batch_entry_points_validate_on_the_host():
+    from paper_1904_13073_amd import swgn
+    L = swgn.lib()
+    h = C.c_void_p()
+    assert L.sw_create_batch(None, 2, C.byref(h)) == swgn.SW_EINVAL and not h.value
+    assert L.sw_create_batch(None, 0, None) == swgn.SW_EINVAL
+    assert L.sw_destroy_batch(None) == 0
+    assert L.sw_batch_last_error(None) == b"null batch"
+    assert L.sw_solve_batch(None, None, 1, None, 0, None, None) == swgn.SW_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_server_entry_points_validate_on_the_host():
+    from paper_1904_13073_amd import swgn
+    L = swgn.lib()
+    cfg = swgn.SwServerConfig()
+    L.sw_server_config_default(C.byref(cfg))
+    assert cfg.max_batch == 32 and cfg.workspace_bytes == 4 << 30
+    h = C.c_void_p()
+    for mb, ws in ((0, 1 << 20), (65, 1 << 20), (4, 100)):
+        bad = swgn.SwServerConfig(max_batch=mb, workspace_bytes=ws)
+        assert L.sw_create_server(C.byref(bad), None, C.byref(h)) == swgn.SW_EINVAL and not h.value
+    assert L.sw_destroy_server(None) == 0
+    assert L.sw_server_last_error(None) == b"null server"
+    t = C.c_uint64()
+    assert L.sw_server_submit(None, None, None, 0, C.byref(t)) == swgn.SW_EINVAL
+    assert L.sw_server_poll(None, 1, 0, None, None) == swgn.SW_EINVAL
+    assert L.sw_server_attach(None, None) == swgn.SW_EINVAL

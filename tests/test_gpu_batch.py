@@ -1,0 +1,139 @@
+"""Batched solves: streams of uneven shapes solved together in one launch
+per Gauss-Newton stage must end exactly where each ends when solved alone
+(same kernels, same per-stream arithmetic and summation order), over several
+frames, with uneven iteration counts, captures and a failing member."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_lib, stream_for
+
+pytestmark = pytest.mark.gpu
+
+MIX = [("tiny", None), ("c1", None), ("random", 400), ("random", 402), ("random", 401)]
+
+
+@pytest.fixture(scope="module")
+def swgn():
+    return gpu_lib()
+
+
+def _scenes(scene_cache, names=MIX):
+    return [scene_cache(n, s) for n, s in names]
+
+
+def _solo(swgn, scenes, depths_per_frame, cfgs):
+    out, stats = [], []
+    for i, sc in enumerate(scenes):
+        st = stream_for(swgn, sc, **cfgs[i])
+        fr = []
+        for depths in depths_per_frame:
+            fr.append(st.solve_frame(depths[i]))
+        out.append(st.node_se3())
+        stats.append(fr)
+        st.close()
+    return out, stats
+
+
+def _batched(swgn, scenes, depths_per_frame, cfgs, order=None):
+    order = list(range(len(scenes))) if order is None else order
+    sts = [stream_for(swgn, sc, **cfgs[i]) for i, sc in enumerate(scenes)]
+    b = swgn.Batch()
+    stats = [[] for _ in scenes]
+    for depths in depths_per_frame:
+        res, status = b.solve([sts[i] for i in order], [depths[i] for i in order])
+        assert status == [swgn.SW_OK] * len(order)
+        for k, i in enumerate(order):
+            stats[i].append(res[k])
+    out = [st.node_se3() for st in sts]
+    for st in sts:
+        st.close()
+    b.close()
+    return out, stats
+
+
+def _assert_same(a_se3, a_stats, b_se3, b_stats):
+    for i, (x, y) in enumerate(zip(a_se3, b_se3)):
+        assert np.array_equal(x, y), f"stream {i}: node transforms differ"
+    for i, (fa, fb) in enumerate(zip(a_stats, b_stats)):
+        for sa, sb in zip(fa, fb):
+            assert sa["n_corr"] == sb["n_corr"], f"stream {i}"
+            assert sa["e_data"] == sb["e_data"] and sa["e_reg"] == sb["e_reg"], f"stream {i}"
+            assert sa["pcg_resid"] == sb["pcg_resid"], f"stream {i}"
+
+
+def test_batch_of_uneven_streams_equals_solo_runs(swgn, scene_cache):
+    scenes = _scenes(scene_cache)
+    shapes = {(s.cam.width, s.node_pos.shape[0]) for s in scenes}
+    assert len(shapes) == len(scenes)          # image sizes and node counts differ
+    frames = [[s.depth for s in scenes]]
+    cfgs = [{} for _ in scenes]
+    solo = _solo(swgn, scenes, frames, cfgs)
+    bat = _batched(swgn, scenes, frames, cfgs, order=[3, 0, 4, 2, 1])
+    _assert_same(*solo, *bat)
+    assert all(st[0]["n_corr"][-1] > 0 for st in solo[1])
+
+
+def test_batch_with_uneven_iteration_counts_and_two_frames(swgn, scene_cache):
+    scenes = _scenes(scene_cache, MIX[:4])
+    cfgs = [dict(gn_iters=3, pcg_iters=5), dict(gn_iters=10, pcg_iters=10), dict(gn_iters=0),
+            dict(gn_iters=6, pcg_iters=0)]
+    rng = np.random.default_rng(5)
+    second = []
+    for s in scenes:       # a second frame: the same depth with some pixels dropped
+        d = s.depth.copy()
+        d[rng.random(d.shape) < 0.1] = 0.0
+        second.append(d)
+    frames = [[s.depth for s in scenes], second]
+    solo = _solo(swgn, scenes, frames, cfgs)
+    bat = _batched(swgn, scenes, frames, cfgs)
+    _assert_same(*solo, *bat)
+    assert [len(f[0]["e_data"]) for f in bat[1]] == [3, 10, 0, 6]
+
+
+def test_batch_from_device_depths_and_capture(swgn, scene_cache):
+    import torch
+    scenes = _scenes(scene_cache, MIX[:3])
+    dev = torch.device("cuda:0")
+    depths = [torch.from_numpy(s.depth).to(dev) for s in scenes]
+    torch.cuda.synchronize()
+    cfgs = [{}, dict(debug_iter=2), {}]
+    solo_st = stream_for(swgn, scenes[1], debug_iter=2)
+    solo_st.solve_frame(scenes[1].depth)
+    want = solo_st.last_maps(), solo_st.last_system()
+    solo_st.close()
+    sts = [stream_for(swgn, sc, **cfgs[i]) for i, sc in enumerate(scenes)]
+    b = swgn.Batch()
+    b.solve(sts, depths)
+    got = sts[1].last_maps(), sts[1].last_system()
+    for w, g in zip(want[0] + want[1], got[0] + got[1]):
+        assert np.array_equal(w, g, equal_nan=True)
+    for st in sts:
+        st.close()
+    b.close()
+
+
+def test_batch_arguments_and_a_failing_member(swgn, scene_cache):
+    scenes = _scenes(scene_cache, MIX[:3])
+    sts = [stream_for(swgn, sc) for sc in scenes]
+    b = swgn.Batch()
+    with pytest.raises(swgn.SwError) as e:
+        b.solve([sts[0], sts[0]], [scenes[0].depth, scenes[0].depth])
+    assert e.value.status == swgn.SW_EINVAL
+    bare = swgn.Stream(swgn.config_for(scenes[0]))
+    with pytest.raises(swgn.SwError) as e:
+        b.solve([sts[0], bare], [scenes[0].depth, scenes[0].depth])
+    assert e.value.status == swgn.SW_ESTATE
+    bare.close()
+    # one member with a non-finite node transform fails; the others are solved
+    nn = scenes[1].node_pos.shape[0]
+    bad = np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (nn, 1))
+    bad[5, 3] = np.nan
+    sts[1].set_node_se3(bad)
+    res, status = b.solve(sts, [s.depth for s in scenes], raise_numeric=False)
+    assert status == [swgn.SW_OK, swgn.SW_ENUMERIC, swgn.SW_OK]
+    assert np.array_equal(sts[1].node_se3(), bad, equal_nan=True)
+    want, _ = _solo(swgn, [scenes[0], scenes[2]], [[scenes[0].depth, scenes[2].depth]], [{}, {}])
+    assert np.array_equal(sts[0].node_se3(), want[0]) and np.array_equal(sts[2].node_se3(), want[1])
+    for st in sts:
+        st.close()
+    b.close()
