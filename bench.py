@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=16,
                     help="streams of the 640x480 workload solved together in the batched leg (0 = skip)")
+    ap.add_argument("--serve-streams", type=int, default=16,
+                    help="streams of the 640x480 workload in the served leg (0 = skip)")
+    ap.add_argument("--serve-hz", type=float, default=30.0, help="Poisson frame rate of each served stream")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the arrival trace")
     ap.add_argument("--cpu-gn-iters", type=int, default=2,
                     help="oracle Gauss-Newton iterations timed for the CPU baseline")
     return ap.parse_args()
@@ -55,10 +59,10 @@ def kernel_bytes(ns, nn, nb, nseg, npx, pcg_iters):
         # per surfel: position 12, node ids 16, weights 16, index 4; atomic 8
         "warp_zbuf": 56.0 * ns + 32.0 * nn,
         # per surfel: position + normal 24, node ids 16, weights 16, index 4,
-        # index map 8, normal map 16; Jacobian + residual out 100
-        "corr_jac": 184.0 * ns + 48.0 * nn,
-        # Jacobians + residuals in once, per segment 10 Gram sub-blocks + J^T r out
-        "asm_segments": 100.0 * ns + 4.0 * SEG_SLOTS * nseg,
+        # index map 8, normal map 16; per segment 10 Gram sub-blocks, J^T r and
+        # r^T r out (385 floats); Jacobian rows stay on chip
+        "corr_jac": 84.0 * ns + 48.0 * nn + 1540.0 * nseg,
+        "asm_segments": 0.0,
         # per segment and block: entry, sub-block (and J^T r); blocks, gradient out
         "asm_fold": 10.0 * nseg * (4.0 + 144.0) + 4 * 24.0 * nseg + 144.0 * nb + 28.0 * nn,
         # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
@@ -78,7 +82,7 @@ def replay_us(bx, streams, pcg_iters, reps=200):
     times back to back between two HIP events on the solve's stream."""
     out = {}
     for i, k in enumerate(KERNELS):
-        if k in ("depth_prep", "node_update"):
+        if k in ("depth_prep", "node_update", "asm_segments"):
             continue
         pit = min(1, max(0, pcg_iters - 1)) if k in ("pcg_spmv", "pcg_update") else 0
         out[k] = bx.profile_stage(streams, i, reps=reps, pcg_it=pit)
@@ -99,6 +103,105 @@ def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0):
             "alg_bytes_per_launch": scale * kb[name], "avg_launch_us": round(float(replay[name]), 3),
             "launches_per_frame": int(launches[KERNELS.index(name)])}
     return roof, {k: round(v, 1) for k, v in rates.items()}
+
+
+def arrival_trace(n_streams, hz, seconds, seed=0):
+    """Poisson arrivals: (time, stream) pairs, exponential gaps of mean 1/hz per stream."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ev = []
+    for i in range(n_streams):
+        t = rng.exponential(1.0 / hz)
+        while t < seconds:
+            ev.append((t, i))
+            t += rng.exponential(1.0 / hz)
+    ev.sort()
+    return ev
+
+
+def run_served(swgn, sts, depth, trace, max_batch, closed_seconds=0.0):
+    """Open loop: frames submitted at their arrival times; latency = done - submit.
+    Closed loop (closed_seconds > 0): every stream resubmits as soon as its frame
+    is done, for that long; gives the saturated throughput."""
+    import threading
+    sv = swgn.Server(max_batch=max_batch)
+    for st in sts:
+        sv.attach(st)
+    tickets = []
+    lock = threading.Lock()
+    t0 = time.perf_counter()
+
+    def submit_all():
+        for t, i in trace:
+            d = t - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tk = sv.submit(sts[i], depth)
+            with lock:
+                tickets.append(tk)
+
+    th = threading.Thread(target=submit_all)
+    th.start()
+    infos = []
+    k = 0
+    while True:
+        with lock:
+            tk = tickets[k] if k < len(tickets) else None
+        if tk is None:
+            if not th.is_alive() and k >= len(tickets):
+                break
+            time.sleep(0.0002)
+            continue
+        infos.append(sv.poll(tk, wait_ms=-1)[1])
+        k += 1
+    th.join()
+    lat = [1000.0 * (i["t_done"] - i["t_submit"]) for i in infos]
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    ok = all(i["status"] == swgn.SW_OK for i in infos)
+    out = {"frames": len(infos), "frames_per_s": round(len(infos) / span, 2),
+           "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
+           "max_in_flight": sv.counters()["max_in_flight"], "all_ok": ok}
+    if closed_seconds > 0:
+        live = {sv.submit(st, depth): i for i, st in enumerate(sts)}
+        done, lat2 = 0, []
+        c0 = time.perf_counter()
+        first = None
+        last = None
+        while live:
+            for tk in list(live):
+                r = sv.poll(tk, wait_ms=0)
+                if r is None:
+                    continue
+                i = live.pop(tk)
+                info = r[1]
+                first = info["t_submit"] if first is None else min(first, info["t_submit"])
+                last = info["t_done"] if last is None else max(last, info["t_done"])
+                done += 1
+                lat2.append(1000.0 * (info["t_done"] - info["t_submit"]))
+                if time.perf_counter() - c0 < closed_seconds:
+                    live[sv.submit(sts[i], depth)] = i
+            time.sleep(0.0001)
+        out["saturated"] = {"frames": done, "frames_per_s": round(done / (last - first), 2),
+                            "latency_ms": {"p50": round(percentile(lat2, 0.5), 3),
+                                           "p99": round(percentile(lat2, 0.99), 3)}}
+    sv.close()
+    return out
+
+
+def run_plain_fifo(sts, depth, trace):
+    """The same arrivals served one frame at a time in arrival order by plain
+    single-stream solves; latency = completion - arrival."""
+    lat = []
+    t0 = time.perf_counter()
+    for t, i in trace:
+        d = t - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        sts[i].solve_frame(depth, with_stats=False)
+        lat.append(1000.0 * ((time.perf_counter() - t0) - t))
+    span = time.perf_counter() - t0 - trace[0][0]
+    return {"frames": len(lat), "frames_per_s": round(len(lat) / span, 2),
+            "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)}}
 
 
 def cpu_baseline(scene, gn_iters):
@@ -251,6 +354,22 @@ def main():
                    "kernel_gbs": b_rates, "roofline": b_roof, "identical_results": bool(same)}
         print(f"[bench] batched x{B}: {batched['value']} frames/s", file=sys.stderr, flush=True)
 
+    served = None
+    if args.serve_streams > 0:
+        S = min(args.serve_streams, 64)
+        trace = arrival_trace(S, args.serve_hz, args.serve_seconds)
+        sts = [make_stream() for _ in range(S)]
+        torch.cuda.synchronize()
+        plain = run_plain_fifo(sts, depth, trace)
+        print(f"[bench] plain FIFO: {plain}", file=sys.stderr, flush=True)
+        srv = run_served(swgn, sts, depth, trace, max_batch=S, closed_seconds=2.0)
+        print(f"[bench] served: {srv}", file=sys.stderr, flush=True)
+        for t in sts:
+            t.close()
+        served = {"streams": S, "hz_per_stream": args.serve_hz, "trace_seconds": args.serve_seconds,
+                  "offered_frames_per_s": round(len(trace) / args.serve_seconds, 1),
+                  "served": srv, "plain_fifo": plain}
+
     out = {
         "metric": "GN frame solves/s at 640x480 ~2k nodes; p50/p99 solve latency, served vs plain",
         "value": round(fps, 2),
@@ -277,6 +396,8 @@ def main():
     }
     if batched is not None:
         out["batched"] = batched
+    if served is not None:
+        out["served"] = served
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_gn_iters)

@@ -53,7 +53,9 @@ typedef struct sw_config {
     float corr_normal;         /* correspondence normal gate (cosine), 0.5 */
     float edge_gate;           /* normal-map depth-discontinuity gate, 0.03 m */
     float damping;             /* mu added to every diagonal entry of J^T J, 1e-4 */
-    int32_t jac_dtype;         /* Jacobian storage: 0 = fp32 */
+    int32_t jac_dtype;         /* Jacobian entries kept as 0 = fp32, 1 = bf16, 2 = fp16
+                                  (rounded to nearest even; r, J^T J, J^T r, PCG stay
+                                  fp32, block inverses and PCG dots fp64) */
     int32_t dot_fp64;          /* 1 = accumulate PCG dot products in fp64 (default 1) */
     int32_t debug_iter;        /* -1 = capture nothing; k = capture GN iteration k */
     int32_t stage_timing;      /* 1 = time every kernel with HIP events into stage_us */
@@ -68,8 +70,8 @@ typedef struct sw_frame_stats {
     float pcg_resid[16];       /* |r| of the linear system when PCG stops */
     float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
                                   over the frame: [0] depth preprocessing, [1] warp +
-                                  index map, [2] correspondence + Jacobians,
-                                  [3] segment Gram matrices, [4] block-Jacobi +
+                                  index map, [2] correspondence + Jacobians +
+                                  segment Gram matrices, [3] unused, [4] block-Jacobi +
                                   PCG start, [5] PCG products, [6] PCG updates,
                                   [7] node update, [8] assembly of the blocks;
                                   measured with HIP events */
@@ -138,10 +140,18 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
 typedef struct sw_batch_s* sw_batch;
 
 #define SW_BATCH_TIMING 1   /* time every launch with HIP events into stage_us */
+#define SW_BATCH_GRAPH  2   /* replay a batch's Gauss-Newton iterations as one HIP graph */
 
-/* Create an executor. hip_stream as in sw_create_stream; flags: 0 or
+/* Create an executor. hip_stream as in sw_create_stream; flags: 0,
  * SW_BATCH_TIMING (then every stream's stage_us holds the times of the
- * batch's launches, summed over the frame). */
+ * batch's launches, summed over the frame) or SW_BATCH_GRAPH: the launches
+ * of all Gauss-Newton iterations and the statistics copy are captured as one
+ * HIP graph the first time a batch (the same streams in the same order) is
+ * solved, and the graph is replayed while the batch and its streams'
+ * buffers are unchanged (a new batch, or sw_set_reference_surfels /
+ * sw_set_node_graph on a member, captures anew). Results are identical to
+ * the launch-by-launch path. Not combinable with SW_BATCH_TIMING (EINVAL);
+ * streams that capture an iteration (debug_iter) run launch by launch. */
 sw_status sw_create_batch(void* hip_stream, int32_t flags, sw_batch* out);
 
 /* Destroy an executor (NULL is a no-op). Streams are not affected. */
@@ -167,7 +177,7 @@ sw_status sw_solve_batch(sw_batch b, const sw_stream* streams, int32_t n,
  * time per launch in microseconds. The streams' frame workspaces are
  * overwritten (their warp fields are not); use after a solve, so that the
  * stage's inputs hold a real frame. stage numbers as in stage_us: 1 warp +
- * index map, 2 correspondence + Jacobians, 3 segment Gram matrices,
+ * index map, 2 correspondence + Jacobians + segment Gram matrices,
  * 4 block-Jacobi + PCG start, 5 PCG product, 6 PCG update, 8 block fold;
  * others give SW_EINVAL. pcg_it selects the PCG iteration for 5 and 6. */
 sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int32_t stage,
@@ -253,6 +263,12 @@ sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity);
 
 /* Sizes of the current problem (any pointer may be NULL). */
 sw_status sw_get_sizes(sw_stream s, int64_t* n_surfels, int32_t* n_nodes, int32_t* n_blocks);
+
+/* Device memory of the stream: resident state (surfels, skinning, node state,
+ * graph, block pattern, work lists, capture buffers) and the workspace one
+ * frame in flight needs (the admission footprint of sw_server_attach).
+ * SW_ESTATE before sw_set_node_graph. */
+sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes);
 
 /* ---- parity and debug exports (host pointers, caller's surfel order) ---- */
 

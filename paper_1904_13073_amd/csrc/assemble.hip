@@ -1,24 +1,16 @@
 // Assembly of the Gauss-Newton system (Sec. 8: build J^T J, then solve):
 //   H = sum_i J_i^T J_i + lambda sum_edges J_e^T J_e + mu I   (6x6 node-pair blocks)
 //   g = sum_i J_i^T r_i + lambda sum_edges J_e^T r_e
-// over the upper block pattern. Data rows are the per-surfel Jacobians written
-// by the correspondence kernel; regulariser rows (Sec. 7,
-// E_regulation = sum_j sum_{m in N_j} |T_j p_j - T_m p_j|^2) are formed here
-// from the node state.
+// over the upper block pattern. The data term arrives as per-segment Gram
+// matrices (a segment = surfels sharing one node set; its 10 upper 6x6
+// sub-blocks and J^T r, written by the correspondence kernel); regulariser
+// rows (Sec. 7, E_regulation = sum_j sum_{m in N_j} |T_j p_j - T_m p_j|^2) are
+// formed here from the node state.
 //
-// Surfels are stored grouped by their set of 4 nodes, in segments of at most
-// 128 surfels with one node set. For a segment, every one of its 10 blocks is a
-// 6x6 sub-block of the Gram matrix G = [J | r]^T [J | r] over its surfels
-// (J the segment's n x 24 Jacobian), and g is G's column 24. So:
-//   1. one wave per segment accumulates G with the 32x32x2 FP32 MFMA, the sum
-//      over surfels being the MFMA's k dimension (2 surfels per instruction;
-//      the A and B operands are the same register: lane = Jacobian component,
-//      half-wave = surfel; a surfel's [J | r] is one 128-byte row), and stores
-//      the 10 upper sub-blocks and J^T r;
-//   2. a 16-lane group per block sums its segments' sub-blocks in a fixed
-//      order, adds the regulariser terms (edges spread over the lanes) and
-//      the damping, and finishes with a DPP row reduction.
-// Each Jacobian is read once; no atomics; results are reproducible.
+// A 16-lane group per block sums its segments' sub-blocks in a fixed order,
+// adds the regulariser terms (edges spread over the lanes) and the damping,
+// and finishes with a DPP row reduction. No atomics; results are
+// reproducible.
 #include "swgn_frame.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
@@ -26,8 +18,6 @@
 namespace swgn {
 
 namespace {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float3 ld3(float4 a) { return make_float3(a.x, a.y, a.z); }
 
@@ -52,61 +42,12 @@ __device__ __forceinline__ int sub_block(int pa, int pb) {
     return first[pa] + (pb - pa);
 }
 
-// Level 1: one wave per segment.
-__global__ void __launch_bounds__(64 * kSegWaves) k_asm_segments(Batch wl) {
-    __shared__ float stage[kSegWaves][kSegSlots];
-    const Where at = locate(wl);
-    const FrameDesc in = *wl.d[at.s];
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int seg = at.tile * kSegWaves + wave;
-    const bool active = seg < in.nseg;
-    const int s0 = active ? in.seg_start[seg] : 0;
-    const int s1 = active ? in.seg_start[seg + 1] : 0;
-    const int comp = lane & 31, half = lane >> 5;
-    // lane's column of [J | r | 0]: a surfel's row is one 128-byte line, so an
-    // MFMA step reads two full lines
-    const float* src = in.J + comp;
-    f32x16 acc;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.f;
-    const int n = s1 - s0;                 // wave-uniform
-    for (int m0 = 0; m0 < n; m0 += 16) {   // 8 MFMA steps, loads issued first
-        float v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int s = s0 + m0 + 2 * q + half;   // surfel of this half-wave
-            v[q] = s < s1 ? src[(size_t)s * 32] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
-    }
-    // accumulator element t of lane l is G[i][j], j = l % 32,
-    // i = (t / 4) * 8 + (l / 32) * 4 + t % 4
-    float* sg = stage[wave];
-    const int j = comp;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int i = (t >> 2) * 8 + half * 4 + (t & 3);
-        if (i < 24 && j < 24) {
-            const int pa = i / 6, pb = j / 6;
-            if (pa <= pb) sg[sub_block(pa, pb) * 36 + (i % 6) * 6 + (j % 6)] = acc[t];
-        } else if (j == 24 && i <= 24) {
-            sg[360 + i] = acc[t];            // J^T r (i < 24), r^T r (i = 24)
-        }
-    }
-    __syncthreads();
-    if (active) {
-        float4* dst = reinterpret_cast<float4*>(in.part + (size_t)seg * kSegSlots);
-        const float4* from = reinterpret_cast<const float4*>(sg);
-        for (int q = lane; q < kSegSlots / 4; q += kWave) dst[q] = from[q];
-    }
-}
-
-// Level 2: one 16-lane group per block; diagonal blocks first (node order),
+// One 16-lane group per block; diagonal blocks first (node order),
 // then the off-diagonal ones.
 __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
     const Where at = locate(wl);
     const FrameDesc in = *wl.d[at.s];
+    const bool capture = wl.it[at.s] == in.debug_iter;
     const int lane = threadIdx.x % kWave, g = lane & 15;
     const int gi = at.tile * kFoldGroups + (threadIdx.x >> 4);
     const bool active = gi < in.nn + in.noff;
@@ -195,9 +136,26 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
             for (int c = 0; c < 6; ++c) in.g[6 * k + c] = gacc[c];
             in.ereg[k] = er;
         }
-        float4* out = reinterpret_cast<float4*>(in.H + (size_t)b * 36);
+        // the product's explicit rows: the block in its row, its transpose in the column's row
+        float4* fu = reinterpret_cast<float4*>(in.Hf + (size_t)in.slot_u[b] * 36);
 #pragma unroll
-        for (int v = 0; v < 9; ++v) out[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+        for (int v = 0; v < 9; ++v) fu[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+        if (!diag) {
+            float tr[36];
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = 0; j < 6; ++j) tr[6 * i + j] = acc[6 * j + i];
+            float4* ft = reinterpret_cast<float4*>(in.Hf + (size_t)in.slot_t[b] * 36);
+#pragma unroll
+            for (int v = 0; v < 9; ++v) ft[v] = make_float4(tr[4 * v], tr[4 * v + 1], tr[4 * v + 2], tr[4 * v + 3]);
+        }
+        if (diag || capture) {
+            float4* out = reinterpret_cast<float4*>(in.H + (size_t)b * 36);
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                out[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+        }
     }
 }
 
@@ -218,7 +176,6 @@ void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist
 void launch_asm_stage(int stage, const Batch& b, hipStream_t st) {
     const int grid = b.off[b.n];
     if (grid <= 0) return;
-    if (stage == kStAsmSeg) hipLaunchKernelGGL(k_asm_segments, dim3(grid), dim3(64 * kSegWaves), 0, st, b);
     if (stage == kStAsmFold) hipLaunchKernelGGL(k_asm_fold, dim3(grid), dim3(16 * kFoldGroups), 0, st, b);
 }
 

@@ -26,12 +26,14 @@ extern "C" {
 sw_status sw_create_batch(void* hip_stream, int32_t flags, sw_batch* out) {
     if (!out) return SW_EINVAL;
     *out = nullptr;
-    if (flags & ~SW_BATCH_TIMING) return SW_EINVAL;
+    if (flags & ~(SW_BATCH_TIMING | SW_BATCH_GRAPH)) return SW_EINVAL;
+    if ((flags & SW_BATCH_TIMING) && (flags & SW_BATCH_GRAPH)) return SW_EINVAL;
     sw_batch_s* b = new (std::nothrow) sw_batch_s();
     if (!b) return SW_ENOMEM;
     const sw_status rc = guarded(b->err, [&]() -> sw_status {
         b->flags = flags;
         b->exec.init(hip_stream);
+        b->exec.graphs = (flags & SW_BATCH_GRAPH) != 0;
         return SW_OK;
     });
     if (rc != SW_OK) {
@@ -82,7 +84,7 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
     if (!streams || !us_per_launch) return fail(b->err, SW_EINVAL, "streams and output must not be NULL");
     if (n < 1 || n > kMaxBatch) return fail(b->err, SW_EINVAL, "batch size must be in [1, 64]");
     if (reps < 1 || reps > 100000) return fail(b->err, SW_EINVAL, "reps must be in [1, 100000]");
-    const bool replayable = stage == kStWarp || stage == kStCorr || stage == kStAsmSeg || stage == kStAsmFold ||
+    const bool replayable = stage == kStWarp || stage == kStCorr || stage == kStAsmFold ||
                             stage == kStPcgInit || stage == kStSpmv || stage == kStUpdate;
     if (!replayable) return fail(b->err, SW_EINVAL, "stage cannot be replayed (it reads input or moves nodes)");
     std::vector<sw_stream> ss(streams, streams + n);

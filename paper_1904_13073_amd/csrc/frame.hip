@@ -3,8 +3,9 @@
 //   depth_prep   normal map of the depth image (Sec. 5); resets the index map
 //   warp_zbuf    dual-quaternion warp of every surfel (Sec. 3, Eq. 1-2) and
 //                a 64-bit atomic-min z-buffer of (z bits, surfel index) (Sec. 7)
-//   corr_jac     projective correspondence, point-to-plane residual and its
-//                exact Jacobian with respect to the 4 node twists
+//   corr_gram    projective correspondence, point-to-plane residual, its exact
+//                Jacobian with respect to the 4 node twists, and per segment
+//                of surfels sharing a node set the Gram matrix of [J | r]
 // plus node-state conversions and capture helpers. Assembly is in
 // assemble.hip, the linear solve and node update in solve.hip. The per-frame
 // kernels take a batch of streams (one work list, see swgn_frame.h).
@@ -95,22 +96,52 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
 }
 
 // ---------------------------------------------------------------------------
-// Correspondence, residual and Jacobian. Each surfel's row [J | r | 0] (node
-// blocks by position within the surfel's ascending node set) is staged in
-// LDS and written out as whole 128-byte lines.
+// Correspondence, residual, Jacobian and the segment Gram matrices.
+//
+// A tile is a pack of whole segments (consecutive surfels, at most 256; a
+// segment is at most 128 surfels sharing one node set). Each thread forms
+// its surfel's row [J | r | 0] (node blocks by position within the ascending
+// node set) in LDS; then each wave takes segments of the pack and sums the
+// 25 x 25 Gram matrix [J | r]^T [J | r] over the segment's surfels with the
+// 32x32x2 FP32 MFMA, the sum over surfels being the MFMA's k dimension (two
+// surfels per instruction; the A and B operands are the same register:
+// lane = component, half-wave = surfel). The Gram's 10 upper 6x6 sub-blocks,
+// J^T r and r^T r are stored per segment for the block fold. Jacobian rows
+// leave the chip only when an iteration is captured.
 // ---------------------------------------------------------------------------
 constexpr int kRowPad = 33;   // LDS row stride in floats (odd: no bank conflicts)
 
-__global__ void __launch_bounds__(kCorrBlock) k_corr_jac(Batch b) {
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// slot of the upper sub-block (pa <= pb) among the 10 of a segment
+__device__ __forceinline__ int sub_block(int pa, int pb) {
+    const int first[4] = {0, 4, 7, 9};
+    return first[pa] + (pb - pa);
+}
+
+// Jacobian entry as stored: fp32, or rounded to nearest-even bf16 / fp16 and
+// held in an fp32 register (products and sums stay fp32).
+__device__ __forceinline__ float keep_jac(float v, int dtype) {
+    if (dtype == 1) {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+        return __uint_as_float(u & 0xffff0000u);
+    }
+    if (dtype == 2) return (float)(_Float16)v;
+    return v;
+}
+
+__global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
-    __shared__ float rows[kCorrBlock / kWave][kWave * kRowPad];
+    __shared__ float rows[kCorrBlock * kRowPad];
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
-    const int i = at.tile * kCorrBlock + threadIdx.x;
+    const int p0 = d.pack_start[at.tile], p1 = d.pack_start[at.tile + 1];
+    const int i = p0 + (int)threadIdx.x;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const bool live = i < d.ns;
+    const bool live = i < p1;
     float r = 0.f;
     float Jw[4][3], Jt[4][3];
 #pragma unroll
@@ -173,32 +204,20 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_jac(Batch b) {
         }
     }
     {
-        // stage the row: node block k goes to position = rank of its id in the set
-        float* row = &rows[wave][lane * kRowPad];
+        // the row: node block k goes to position = rank of its id in the set
+        float* row = &rows[threadIdx.x * kRowPad];
         const int ids[4] = {id.x, id.y, id.z, id.w};
+        const int jd = d.jac_dtype;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
             float* o = row + pos * 6;
-            o[0] = Jw[k][0]; o[1] = Jw[k][1]; o[2] = Jw[k][2];
-            o[3] = Jt[k][0]; o[4] = Jt[k][1]; o[5] = Jt[k][2];
+            o[0] = keep_jac(Jw[k][0], jd); o[1] = keep_jac(Jw[k][1], jd); o[2] = keep_jac(Jw[k][2], jd);
+            o[3] = keep_jac(Jt[k][0], jd); o[4] = keep_jac(Jt[k][1], jd); o[5] = keep_jac(Jt[k][2], jd);
         }
         row[24] = r;
 #pragma unroll
         for (int c = 25; c < 32; ++c) row[c] = 0.f;
-    }
-    __syncthreads();
-    {
-        // the wave's rows [base, base + 64) of the stream, two rows per store
-        const int base = at.tile * kCorrBlock + wave * kWave;
-        const float* src = rows[wave];
-        float* dst = d.J + (size_t)base * 32;
-        const int nrow = min(kWave, d.ns - base);
-#pragma unroll 4
-        for (int q = 0; q < kWave / 2; ++q) {
-            const int rr = 2 * q + (lane >> 5), c = lane & 31;
-            if (rr < nrow) dst[rr * 32 + c] = src[rr * kRowPad + c];
-        }
     }
     if (live && capture) {
         float nanv = __int_as_float(0x7fc00000);
@@ -207,7 +226,7 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_jac(Batch b) {
         d.dbg_live[3 * org + 2] = wp.ok ? wp.v.z : nanv;
         if (matched) d.dbg_corr[pix] = org;
     }
-    double e = block_sum((double)r * (double)r, sh);
+    double e = block_sum((double)r * (double)r, sh);   // (synchronises the rows too)
     int cnt = wave_sumi(matched ? 1 : 0);
     if ((threadIdx.x % kWave) == 0) shi[threadIdx.x / kWave] = cnt;
     __syncthreads();
@@ -216,6 +235,49 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_jac(Batch b) {
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
         d.part_e[at.tile] = e;
         d.part_n[at.tile] = c;
+    }
+    if (capture) {
+        // the wave's rows as whole 128-byte lines, two rows per store
+        const int base = wave * kWave;
+        float* dst = d.J + (size_t)(p0 + base) * 32;
+        const int nrow = min(kWave, p1 - p0 - base);
+        for (int q = 0; q < kWave / 2; ++q) {
+            const int rr = 2 * q + (lane >> 5), c = lane & 31;
+            if (rr < nrow) dst[rr * 32 + c] = rows[(base + rr) * kRowPad + c];
+        }
+    }
+    // segment Gram matrices, one wave per segment
+    const int comp = lane & 31, half = lane >> 5;
+    const int g0 = d.pack_seg[at.tile], g1 = d.pack_seg[at.tile + 1];
+    for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
+        const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
+        f32x16 acc;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = 0.f;
+        for (int m0 = s0; m0 < s1; m0 += 16) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int sr = m0 + 2 * q + half;   // surfel of this half-wave
+                v[q] = sr < s1 ? rows[sr * kRowPad + comp] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
+        }
+        // accumulator element t of lane l is G[i][j], j = l % 32,
+        // i = (t / 4) * 8 + (l / 32) * 4 + t % 4
+        float* out = d.part + (size_t)seg * kSegSlots;
+        const int j = comp;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int ii = (t >> 2) * 8 + half * 4 + (t & 3);
+            if (ii < 24 && j < 24) {
+                const int pa = ii / 6, pb = j / 6;
+                if (pa <= pb) out[sub_block(pa, pb) * 36 + (ii % 6) * 6 + (j % 6)] = acc[t];
+            } else if (j == 24 && ii <= 24) {
+                out[360 + ii] = acc[t];          // J^T r (ii < 24), r^T r (ii = 24)
+            }
+        }
     }
 }
 
@@ -297,7 +359,7 @@ void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStre
     switch (stage) {
         case kStDepth: hipLaunchKernelGGL(k_depth_prep, dim3(grid), dim3(256), 0, st, b, *depth); break;
         case kStWarp: hipLaunchKernelGGL(k_warp_zbuf, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
-        case kStCorr: hipLaunchKernelGGL(k_corr_jac, dim3(grid), dim3(kCorrBlock), 0, st, b); break;
+        case kStCorr: hipLaunchKernelGGL(k_corr_gram, dim3(grid), dim3(kCorrBlock), 0, st, b); break;
         default: break;
     }
 }

@@ -39,15 +39,24 @@ void* Arena::raw(size_t bytes) {
     bytes = ((bytes == 0 ? 1 : bytes) + 255) & ~size_t(255);
     SWGN_HIP(hipMalloc(&p, bytes));
     ptrs_.push_back(p);
+    bytes_ += bytes;
     return p;
 }
 
 void Arena::release() {
     for (void* p : ptrs_) (void)hipFree(p);
     ptrs_.clear();
+    bytes_ = 0;
+}
+
+void Executor::drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    graph_key.clear();
 }
 
 Executor::~Executor() {
+    drop_graph();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     if (stats_host) (void)hipHostFree(stats_host);
     if (stats_dev) (void)hipFree(stats_dev);
@@ -92,9 +101,9 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.stats, sizeof(IterStats) * kMaxIters);
     take(h.rq_bak, 16 * nn);
     take(h.tt_bak, 16 * nn);
-    take(h.J, 128 * (size_t)h.pitch);
     take(h.part, 4 * (size_t)kSegSlots * (size_t)std::max(1, h.nseg));
     take(h.H, 144 * (size_t)h.nb);
+    take(h.Hf, 144 * nn * (size_t)h.ell_w);
     take(h.g, 24 * nn);
     take(h.ereg, 4 * nn);
     take(h.Minv, 288 * nn);
@@ -144,7 +153,7 @@ sw_status check_config(const sw_config* c, std::string& why) {
     }
     if (!(finite(c->edge_gate) && c->edge_gate >= 0)) { why = "edge_gate must be >= 0"; return SW_EINVAL; }
     if (!(finite(c->damping) && c->damping >= 0)) { why = "damping must be >= 0"; return SW_EINVAL; }
-    if (c->jac_dtype != 0) { why = "jac_dtype: only 0 (fp32) is supported"; return SW_EINVAL; }
+    if (c->jac_dtype < 0 || c->jac_dtype > 2) { why = "jac_dtype must be 0 (fp32), 1 (bf16) or 2 (fp16)"; return SW_EINVAL; }
     if (c->dot_fp64 != 1) { why = "dot_fp64: PCG dot products accumulate in fp64 (1)"; return SW_EINVAL; }
     if (c->debug_iter < -1 || c->debug_iter >= kMaxIters) { why = "debug_iter out of range"; return SW_EINVAL; }
     if (c->stage_timing != 0 && c->stage_timing != 1) { why = "stage_timing must be 0 or 1"; return SW_EINVAL; }
@@ -188,6 +197,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.cam = s->cam;
     h.pcg_iters = s->cfg.pcg_iters;
     h.debug_iter = s->cfg.debug_iter;
+    h.jac_dtype = s->cfg.jac_dtype;
     h.edge_gate = s->cfg.edge_gate;
     h.dist2 = s->cfg.corr_dist * s->cfg.corr_dist;
     h.cosn = s->cfg.corr_normal;
@@ -244,6 +254,31 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     int* seg_start = G.alloc<int>(h.nseg + 1);
     launch_run_starts(ns, flag, fpos, seg_start, st);
     h.seg_start = seg_start;
+    {
+        // packs for the correspondence kernel: greedy runs of whole segments
+        // with at most kCorrBlock surfels
+        std::vector<int> hs(h.nseg + 1), ps, pg;
+        SWGN_HIP(hipMemcpyAsync(hs.data(), seg_start, sizeof(int) * (h.nseg + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        ps.push_back(0);
+        pg.push_back(0);
+        for (int g = 0; g < h.nseg; ++g) {
+            if (hs[g + 1] - ps.back() > kCorrBlock) {
+                ps.push_back(hs[g]);
+                pg.push_back(g);
+            }
+        }
+        ps.push_back(ns);
+        pg.push_back(h.nseg);
+        h.npack = (int)ps.size() - 1;
+        int* pack_start = G.alloc<int>(ps.size());
+        int* pack_seg = G.alloc<int>(pg.size());
+        SWGN_HIP(hipMemcpyAsync(pack_start, ps.data(), sizeof(int) * ps.size(), hipMemcpyHostToDevice, st));
+        SWGN_HIP(hipMemcpyAsync(pack_seg, pg.data(), sizeof(int) * pg.size(), hipMemcpyHostToDevice, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        h.pack_start = pack_start;
+        h.pack_seg = pack_seg;
+    }
 
     // upper block pattern
     const int words = (nn + 31) / 32;
@@ -323,6 +358,11 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     int* ell_col = G.alloc<int>((size_t)nn * h.ell_w);
     launch_ell(nn, h.ell_w, frow_ptr, fblk, fcol, ell_blk, ell_col, st);
     h.ell_blk = ell_blk; h.ell_col = ell_col;
+    int* slot_u = G.alloc<int>(h.nb);
+    int* slot_t = G.alloc<int>(h.nb);
+    launch_fill_i32(slot_t, h.nb, -1, st);
+    launch_ell_slots(nn, h.ell_w, ell_blk, slot_u, slot_t, st);
+    h.slot_u = slot_u; h.slot_t = slot_t;
 
     // capture buffers, only when an iteration is to be captured
     s->dbg_index = nullptr;
@@ -335,6 +375,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
         s->dbg_g = G.alloc<float>(6 * (size_t)nn);
         s->dbg_x = G.alloc<float>(6 * (size_t)nn);
         s->dbg_J = G.alloc<float>(32 * (size_t)h.pitch);
+        h.J = s->dbg_J;
     }
 
     // the stream's own workspace
@@ -354,13 +395,12 @@ double model_bytes(const FrameDesc& h, int gn_iters, int64_t n_corr_total) {
     const double ns = h.ns, nn = h.nn, nb = h.nb, npx = h.npx;
     double per_iter = 0.0;
     per_iter += 48.0 * ns + 8.0 * ns + 8.0 * npx;                 // warp + z-buffer (+ clear)
-    per_iter += 60.0 * ns + 8.0 * ns + 16.0 * ns + 100.0 * ns;    // correspondence + J
+    per_iter += 60.0 * ns + 8.0 * ns + 16.0 * ns;                  // correspondence + J (in LDS)
     per_iter += 2.0 * kSegSlots * 4.0 * h.nseg + 144.0 * nb + 24.0 * nn;  // segment Grams + blocks
     per_iter += 144.0 * nn + 288.0 * nn;                          // block-Jacobi
     per_iter += h.pcg_iters * (144.0 * nb + 7.0 * 24.0 * nn);     // PCG
-    double frame = gn_iters * per_iter + 20.0 * npx;
-    frame += 100.0 * (double)n_corr_total;                        // J read by the assembly
-    return frame;
+    (void)n_corr_total;
+    return gn_iters * per_iter + 20.0 * npx;
 }
 
 }  // namespace
@@ -448,7 +488,6 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
         // the solve step updates the node state: keep this iteration's system first
         sw_stream s = ss[i];
         const FrameDesc& h = s->h;
-        SWGN_HIP(hipMemcpyAsync(s->dbg_J, h.J, sizeof(float) * 32 * h.pitch, hipMemcpyDeviceToDevice, st));
         SWGN_HIP(hipMemcpyAsync(s->dbg_H, h.H, sizeof(float) * 36 * h.nb, hipMemcpyDeviceToDevice, st));
         SWGN_HIP(hipMemcpyAsync(s->dbg_g, h.g, sizeof(float) * 6 * h.nn, hipMemcpyDeviceToDevice, st));
     }
@@ -469,14 +508,24 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
 // Brings back the statistics of the streams' finished frames (one launch,
 // one copy, one synchronisation), fills stats / status and restores the node
 // state of every stream whose frame failed numerically.
-sw_status collect_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
-                         sw_frame_stats* stats, sw_status* status) {
-    hipStream_t st = ex.st;
+void enqueue_collect(Executor& ex, const std::vector<sw_stream>& ss) {
     const int n = (int)ss.size();
     std::vector<int> its(n, 0), ev;
     run_stage(ex, kStStatsOut, ss, its, 0, nullptr, false, ev);
+    SWGN_HIP(hipMemcpyAsync(ex.stats_host, ex.stats_dev, (size_t)kStatsOutBytes * n, hipMemcpyDeviceToHost, ex.st));
+}
+
+sw_status collect_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
+                         sw_frame_stats* stats, sw_status* status) {
+    enqueue_collect(ex, ss);
     SWGN_HIP(hipGetLastError());
-    SWGN_HIP(hipMemcpyAsync(ex.stats_host, ex.stats_dev, (size_t)kStatsOutBytes * n, hipMemcpyDeviceToHost, st));
+    return finish_frames(ex, ss, stage_us, stats, status);
+}
+
+sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
+                        sw_frame_stats* stats, sw_status* status) {
+    hipStream_t st = ex.st;
+    const int n = (int)ss.size();
     SWGN_HIP(hipStreamSynchronize(st));
     sw_status rc = SW_OK;
     bool restored = false;
@@ -531,14 +580,51 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
     const int n = (int)ss.size();
     std::vector<int> ev;
     int gmax = 0;
-    for (int i = 0; i < n; ++i) gmax = std::max(gmax, ss[i]->cfg.gn_iters);
+    bool any_capture = false;
+    for (int i = 0; i < n; ++i) {
+        gmax = std::max(gmax, ss[i]->cfg.gn_iters);
+        any_capture |= ss[i]->cfg.debug_iter >= 0 && ss[i]->cfg.debug_iter < ss[i]->cfg.gn_iters;
+    }
     enqueue_depth(ex, ss, depths, on_device, timing, ev);
     std::vector<char> captured(n, 0);
     std::vector<int> its(n, 0);
-    for (int it = 0; it < gmax; ++it) {
-        for (int i = 0; i < n; ++i) its[i] = it < ss[i]->cfg.gn_iters ? it : -1;
-        enqueue_iteration(ex, ss, its, timing, ev, captured);
+    auto body = [&]() {
+        for (int it = 0; it < gmax; ++it) {
+            for (int i = 0; i < n; ++i) its[i] = it < ss[i]->cfg.gn_iters ? it : -1;
+            enqueue_iteration(ex, ss, its, timing, ev, captured);
+        }
+        enqueue_collect(ex, ss);
+    };
+    if (ex.graphs && !timing && !any_capture) {
+        // the iterations and the statistics copy of this exact batch as one
+        // graph, captured on first use and replayed while the batch and its
+        // streams' buffers are unchanged
+        std::vector<std::pair<sw_stream, uint64_t>> key;
+        for (sw_stream s : ss) key.emplace_back(s, s->generation);
+        if (!ex.graph_exec || key != ex.graph_key) {
+            ex.drop_graph();
+            hipGraph_t g = nullptr;
+            SWGN_HIP(hipStreamBeginCapture(ex.st, hipStreamCaptureModeThreadLocal));
+            try {
+                body();
+            } catch (...) {
+                (void)hipStreamEndCapture(ex.st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SWGN_HIP(hipStreamEndCapture(ex.st, &g));
+            hipGraphExec_t ge = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SWGN_HIP(e);
+            ex.graph_exec = ge;
+            ex.graph_key = key;
+        }
+        SWGN_HIP(hipGraphLaunch(ex.graph_exec, ex.st));
+    } else {
+        body();
     }
+    SWGN_HIP(hipGetLastError());
     float stage_us[kNumStages] = {0.f};
     if (timing) {
         SWGN_HIP(hipStreamSynchronize(ex.st));
@@ -549,7 +635,7 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
             stage_us[ev[a]] += 1000.f * ms;
         }
     }
-    const sw_status rc = collect_frames(ex, ss, timing ? stage_us : nullptr, stats, status);
+    const sw_status rc = finish_frames(ex, ss, timing ? stage_us : nullptr, stats, status);
     for (int i = 0; i < n; ++i)
         if (captured[i]) ss[i]->captured = true;
     return rc;
@@ -719,6 +805,15 @@ sw_status sw_get_sizes(sw_stream s, int64_t* n_surfels, int32_t* n_nodes, int32_
     if (n_surfels) *n_surfels = s->ns;
     if (n_nodes) *n_nodes = s->graph_set ? s->h.nn : 0;
     if (n_blocks) *n_blocks = s->graph_set ? s->h.nb : 0;
+    return SW_OK;
+}
+
+sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes) {
+    if (!s) return SW_EINVAL;
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
+    if (resident_bytes)
+        *resident_bytes = (int64_t)(s->surf_mem.bytes() + s->graph_mem.bytes() + s->frame_mem.bytes());
+    if (workspace_bytes) *workspace_bytes = (int64_t)s->ws_bytes;
     return SW_OK;
 }
 

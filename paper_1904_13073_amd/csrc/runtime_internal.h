@@ -38,9 +38,11 @@ public:
         return static_cast<T*>(raw(n * sizeof(T)));
     }
     void release();
+    size_t bytes() const { return bytes_; }
 
 private:
     std::vector<void*> ptrs_;
+    size_t bytes_ = 0;
 };
 
 // A HIP stream plus what a solve needs besides the streams' own memory: the
@@ -52,9 +54,14 @@ struct Executor {
     char* stats_dev = nullptr;
     void* stats_host = nullptr;
     std::vector<hipEvent_t> events;
+    // replay of a batch's iterations as one HIP graph
+    bool graphs = false;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<std::pair<sw_stream, uint64_t>> graph_key;   // (stream, generation) it was captured for
     ~Executor();
     void init(void* hip_stream);
     hipEvent_t event(size_t i);
+    void drop_graph();
 };
 
 inline sw_status fail(std::string& err, sw_status code, const std::string& msg) {
@@ -120,8 +127,11 @@ void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* 
                    bool timing, std::vector<int>& ev);
 void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std::vector<int>& its, bool timing,
                        std::vector<int>& ev, std::vector<char>& captured);
+void enqueue_collect(Executor& ex, const std::vector<sw_stream>& ss);
 sw_status collect_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
                          sw_frame_stats* stats, sw_status* status);
+sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
+                        sw_frame_stats* stats, sw_status* status);
 void server_quiesce(sw_server sv, sw_stream s);
 void server_forget(sw_server sv, sw_stream s);
 sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths,

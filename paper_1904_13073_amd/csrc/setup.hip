@@ -464,6 +464,19 @@ __global__ void k_ell(int nn, int ell_w, const int* __restrict__ frow_ptr, const
     ell_col[t] = in ? fcol[f] : 0;
 }
 
+// Where each upper block is stored in the explicit full rows of the product:
+// slot_u[b] = ELL slot of block b in its row, slot_t[b] = ELL slot of its
+// transpose in the column's row (-1 for a diagonal block, set by the caller).
+__global__ void k_ell_slots(int nn, int ell_w, const uint32_t* __restrict__ ell_blk, int* __restrict__ slot_u,
+                            int* __restrict__ slot_t) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * ell_w) return;
+    const uint32_t bb = ell_blk[t];
+    if (bb == 0xffffffffu) return;
+    if (bb & 0x80000000u) slot_t[bb & 0x7fffffffu] = t;
+    else slot_u[bb] = t;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -559,6 +572,11 @@ void launch_ell(int nn, int ell_w, const int* frow_ptr, const uint32_t* fblk, co
     int n = nn * ell_w;
     hipLaunchKernelGGL(k_ell, dim3((n + 255) / 256), dim3(256), 0, st, nn, ell_w, frow_ptr, fblk, fcol, ell_blk,
                        ell_col);
+}
+
+void launch_ell_slots(int nn, int ell_w, const uint32_t* ell_blk, int* slot_u, int* slot_t, hipStream_t st) {
+    const int n = nn * ell_w;
+    hipLaunchKernelGGL(k_ell_slots, dim3((n + 255) / 256), dim3(256), 0, st, nn, ell_w, ell_blk, slot_u, slot_t);
 }
 
 void launch_in_edge_store(int n, const uint32_t* val, int* in_list, hipStream_t st) {

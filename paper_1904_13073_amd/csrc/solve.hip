@@ -4,7 +4,8 @@
 //                the start of preconditioned conjugate gradients on
 //                (J^T J + mu I) delta = -g: r = -g, z = M r, p = z, x = 0
 //   pcg_spmv     q = A p with p = z + beta p_old formed on the fly (one wave per
-//                block row, rows in ELL layout)
+//                block row; the row's blocks, transposes written out, in ELL
+//                layout)
 //   pcg_update   x += alpha p, r -= alpha q, z = M r (8 lanes per node)
 //   node_update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
 //                the reset of the index map for the next iteration and the
@@ -133,23 +134,33 @@ __global__ void __launch_bounds__(64 * kSpmvRows) k_pcg_spmv(Batch b) {
     const int k = at.tile * kSpmvRows + wave;
     const int sub = lane & 7, fl = lane >> 3;
     float az = 0.f, ap = 0.f;
-    if (k < a.nn && sub < 6) {
+    if (k < a.nn) {
+        // 8-lane group fl takes the row's slots fl, fl + 8, ...; lane sub < 6
+        // holds row sub of the slot's block (one 24-byte line) and element sub
+        // of the column's z and p_old, which the group shares by shuffles
         const uint32_t* eb = a.ell_blk + (size_t)k * a.ell_w;
         const int* ec = a.ell_col + (size_t)k * a.ell_w;
+        const int base = lane & ~7;
+        const int sl = sub < 6 ? sub : 0;
 #pragma unroll 2
         for (int f = fl; f < a.ell_w; f += 8) {
             const uint32_t bb = eb[f];
             if (bb == 0xffffffffu) break;
             const int col = ec[f];
-            const float* B = a.H + (size_t)(bb & ~kTransposed) * 36;
-            const bool tr = (bb & kTransposed) != 0;
+            const float2* B = reinterpret_cast<const float2*>(a.Hf + ((size_t)k * a.ell_w + f) * 36 + sl * 6);
+            const float2 h01 = B[0], h23 = B[1], h45 = B[2];
+            const float h[6] = {h01.x, h01.y, h23.x, h23.y, h45.x, h45.y};
+            const float zv = a.z[6 * col + sl];
+            const float pv = pold[6 * col + sl];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                const float h = tr ? B[c * 6 + sub] : B[sub * 6 + c];
-                az = fmaf(h, a.z[6 * col + c], az);
-                ap = fmaf(h, pold[6 * col + c], ap);
+                const float zc = __shfl(zv, base + c, kWave);
+                const float pc = __shfl(pv, base + c, kWave);
+                az = fmaf(h[c], zc, az);
+                ap = fmaf(h[c], pc, ap);
             }
         }
+        if (sub >= 6) { az = 0.f; ap = 0.f; }
     }
     az += __shfl_xor(az, 8, kWave);
     az += __shfl_xor(az, 16, kWave);

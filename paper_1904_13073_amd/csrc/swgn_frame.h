@@ -25,7 +25,6 @@ constexpr int kMaxPcg = 4096;
 constexpr int kDepthTile = 16;        // 16 x 16 pixels per workgroup
 constexpr int kWarpBlock = 256;       // surfels per workgroup
 constexpr int kCorrBlock = 256;
-constexpr int kSegWaves = 4;          // segments per workgroup (one wave each)
 constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
 constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes
 constexpr int kSpmvRows = 4;          // block rows per workgroup (one wave each)
@@ -37,7 +36,9 @@ constexpr int kSegSlots = 400;        // per segment: 10 upper 6x6 blocks, J^T r
 struct FrameDesc {
     // shapes
     int ns, nn, nb, noff, nseg, pitch, npx, ell_w;
-    int pcg_iters, debug_iter, pad0, pad1;
+    int npack;                    // packs: consecutive whole segments, at most kCorrBlock surfels
+    int pcg_iters, debug_iter;
+    int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
     Cam cam;
     float edge_gate, dist2, cosn, lambda, mu, pad2;
     // resident: surfels sorted by node set; orig = caller's index
@@ -51,13 +52,16 @@ struct FrameDesc {
     const int* nbr;
     // resident: upper block pattern and the assembly / product work lists
     const int *row_ptr, *col_idx, *blk_row, *offlist, *seg_start, *ent_ptr;
+    const int *pack_start, *pack_seg;   // [npack + 1] first surfel / first segment of each pack
     const uint32_t* ent;
     const int *in_ptr, *in_list;
-    const uint32_t* ell_blk;
-    const int* ell_col;
+    const uint32_t* ell_blk;      // [nn][ell_w] upper block id (bit 31: used transposed), ~0 = padding
+    const int* ell_col;           // [nn][ell_w] column node
+    const int *slot_u, *slot_t;   // [nb] ELL slot of each upper block and of its transpose (-1: diagonal)
     // resident: capture of one iteration (null unless requested)
     int* dbg_corr;
     float* dbg_live;
+    float* J;                     // [pitch][32]: 24 Jacobian entries, r, zero padding
     // workspace of a frame in flight
     float* depth;                 // copy of a host depth image
     float4* nmap;                 // (normal, depth) per pixel
@@ -65,9 +69,9 @@ struct FrameDesc {
     int* flags;                   // [4] failure bits of the frame
     IterStats* stats;             // [kMaxIters]
     float4 *rq_bak, *tt_bak;      // node state at the start of the frame
-    float* J;                     // [pitch][32]: 24 Jacobian entries, r, zero padding
     float* part;                  // [nseg][kSegSlots] segment Gram sub-blocks
-    float *H, *g, *ereg;
+    float *H, *g, *ereg;          // H: upper blocks (the diagonal always, all when captured)
+    float* Hf;                    // [nn][ell_w][36] full rows of J^T J + mu I, transposes written out
     double* Minv;                 // [nn][36] block-Jacobi inverses
     double* part_e;               // correspondence pass partials
     int* part_n;
@@ -82,7 +86,7 @@ enum Stage {
 };
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-__host__ __device__ inline int corr_tiles(const FrameDesc& d) { return cdiv(d.ns, kCorrBlock); }
+__host__ __device__ inline int corr_tiles(const FrameDesc& d) { return d.npack; }
 __host__ __device__ inline int solve_tiles(const FrameDesc& d) { return cdiv(8 * d.nn, kSolveBlock); }
 __host__ __device__ inline int spmv_tiles(const FrameDesc& d) { return cdiv(d.nn, kSpmvRows); }
 
@@ -95,7 +99,7 @@ inline int stage_tiles(int stage, const FrameDesc& d) {
         }
         case kStWarp: return cdiv(d.ns, kWarpBlock);
         case kStCorr: return corr_tiles(d);
-        case kStAsmSeg: return cdiv(d.nseg, kSegWaves);
+        case kStAsmSeg: return 0;     // the segment Gram matrices are formed by the correspondence kernel
         case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
         case kStPcgInit: return solve_tiles(d);
         case kStSpmv: return spmv_tiles(d);

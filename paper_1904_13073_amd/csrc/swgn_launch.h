@@ -37,6 +37,7 @@ void launch_full_rows(int nn, int ntr, const int* row_ptr, const int* col_idx, c
 
 void launch_in_edge_keys(int nn, int npad, const int* nbr, uint64_t* key, uint32_t* val, int* icount, hipStream_t st);
 void launch_in_edge_store(int n, const uint32_t* val, int* in_list, hipStream_t st);
+void launch_ell_slots(int nn, int ell_w, const uint32_t* ell_blk, int* slot_u, int* slot_t, hipStream_t st);
 void launch_ell(int nn, int ell_w, const int* frow_ptr, const uint32_t* fblk, const int* fcol, uint32_t* ell_blk,
                 int* ell_col, hipStream_t st);
 

@@ -74,11 +74,12 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_get_last_jacobian", "sw_create_batch", "sw_destroy_batch", "sw_batch_last_error",
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
-           "sw_server_submit", "sw_server_poll", "sw_server_counters"]
+           "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint"]
 
 SW_EPENDING = 1
 
 SW_BATCH_TIMING = 1
+SW_BATCH_GRAPH = 2
 
 
 def lib() -> C.CDLL:
@@ -123,6 +124,7 @@ def lib() -> C.CDLL:
         "sw_server_submit": (i32, [vp, vp, fp, i32, C.POINTER(C.c_uint64)]),
         "sw_server_poll": (i32, [vp, C.c_uint64, i32, C.POINTER(SwFrameStats), C.POINTER(SwTicketInfo)]),
         "sw_server_counters": (i32, [vp, C.POINTER(SwServerInfo)]),
+        "sw_get_footprint": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -243,8 +245,8 @@ def sw_solve_batch(b, handles, depths, with_stats: bool = True, raise_numeric: b
 class Batch:
     """A batch executor: solves one frame for each of several Streams per call."""
 
-    def __init__(self, hip_stream: Optional[int] = None, timing: bool = False):
-        self.h = sw_create_batch(hip_stream, SW_BATCH_TIMING if timing else 0)
+    def __init__(self, hip_stream: Optional[int] = None, timing: bool = False, graph: bool = False):
+        self.h = sw_create_batch(hip_stream, (SW_BATCH_TIMING if timing else 0) | (SW_BATCH_GRAPH if graph else 0))
 
     def close(self):
         if self.h:
@@ -337,6 +339,12 @@ def sw_get_sizes(h):
     ns, nn, nb = C.c_int64(), C.c_int32(), C.c_int32()
     _check(h, lib().sw_get_sizes(h, C.byref(ns), C.byref(nn), C.byref(nb)))
     return ns.value, nn.value, nb.value
+
+
+def sw_get_footprint(h):
+    res, ws = C.c_int64(), C.c_int64()
+    _check(h, lib().sw_get_footprint(h, C.byref(res), C.byref(ws)))
+    return res.value, ws.value
 
 
 def sw_get_node_se3(h) -> np.ndarray:
@@ -435,6 +443,10 @@ class Stream:
 
     def sizes(self):
         return sw_get_sizes(self.h)
+
+    def footprint(self):
+        """(resident bytes, workspace bytes of one frame in flight)."""
+        return sw_get_footprint(self.h)
 
     def skinning(self):
         return sw_get_skinning(self.h)
