@@ -36,6 +36,10 @@ def parse():
                     help="streams of the 640x480 workload in the served leg (0 = skip)")
     ap.add_argument("--serve-hz", type=float, default=30.0, help="Poisson frame rate of each served stream")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the arrival trace")
+    ap.add_argument("--counters", action="store_true",
+                    help="short fixed run for hardware-counter passes: 2 plain frames, 2 batched frames of "
+                         "--batch streams and three 256 MiB device copies (the byte-counter calibration); "
+                         "prints no JSON")
     ap.add_argument("--cpu-gn-iters", type=int, default=2,
                     help="oracle Gauss-Newton iterations timed for the CPU baseline")
     return ap.parse_args()
@@ -89,7 +93,7 @@ def replay_us(bx, streams, pcg_iters, reps=200):
     return out
 
 
-def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0):
+def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):
     """Achieved GB/s of every replayed kernel (algorithmic bytes x scale / mean
     time per launch) and the roofline entry of the kernel with the largest
     share of the frame."""
@@ -98,8 +102,9 @@ def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0):
     share = {k: per_frame_us[i] for i, k in enumerate(KERNELS) if k in replay}
     name = max(share, key=share.get)
     achieved = rates[name]
+    traffic = measured_traffic(name, streams)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": scale * kb[name], "avg_launch_us": round(float(replay[name]), 3),
             "launches_per_frame": int(launches[KERNELS.index(name)])}
     return roof, {k: round(v, 1) for k, v in rates.items()}
@@ -204,6 +209,37 @@ def run_plain_fifo(sts, depth, trace):
             "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)}}
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1904_13073_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, streams):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_640x480.md")
+    if not os.path.exists(path):
+        return None
+    src, table = None, {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] == "sources":
+                src = parts[1]
+            elif len(parts) == 4 and parts[0] == "traffic":
+                table[(parts[1], int(parts[2]))] = float(parts[3])
+    if src != kernel_source_hash():
+        return None
+    name = {"corr_jac": "corr_gram"}.get(kernel, kernel)
+    return table.get((name, streams))
+
+
 def cpu_baseline(scene, gn_iters):
     """The FP64 oracle timed on this host: one frame's depth preparation and a
     bounded number of its Gauss-Newton iterations, scaled to frames/s."""
@@ -268,6 +304,26 @@ def main():
         return st
 
     depth = torch.from_numpy(scene.depth).to(dev)
+    if args.counters:
+        one = make_stream()
+        for _ in range(2):
+            one.solve_frame(depth, with_stats=False)
+        one.close()
+        B = max(1, min(args.batch, 64))
+        sts = [make_stream() for _ in range(B)]
+        bx = swgn.Batch(hip_stream=hip_stream)
+        for _ in range(2):
+            bx.solve(sts, [depth] * B, with_stats=False)
+        bx.close()
+        for t in sts:
+            t.close()
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] counters run done: {ns} surfels, batch {B}, copy 256 MiB x3", file=sys.stderr, flush=True)
+        return
     st = make_stream()
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -320,6 +376,8 @@ def main():
         torch.cuda.synchronize()
         for _ in range(max(2, args.warmup // 2)):
             bx.solve(sts, depths, with_stats=False)
+        orders = bx.autotune(sts, reps=10)      # tile order per stage for this batch shape
+        bx.solve(sts, depths, with_stats=False)
         torch.cuda.synchronize()
         nbs = max(5, args.steps // B)
         blat = []
@@ -335,6 +393,8 @@ def main():
         for t in sts:
             t.set_node_se3(np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (nn, 1)))
         tb = swgn.Batch(hip_stream=hip_stream, timing=True)
+        tb.solve(sts, depths, with_stats=False)
+        tb.autotune(sts, reps=10)
         btot = np.zeros(len(KERNELS))
         breps = 3
         for _ in range(breps):
@@ -344,14 +404,17 @@ def main():
         tb.close()
         for t in sts:
             t.close()
-        b_roof, b_rates = stage_roofline(btot / breps, launches, kb, b_replay, scale=B)
+        b_roof, b_rates = stage_roofline(btot / breps, launches, kb, b_replay, scale=B, streams=B)
         batched = {"streams": B, "value": round(B * nbs / bel, 2), "unit": "frames/s",
                    "ms_per_batch": round(1000.0 * bel / nbs, 3),
                    "latency_ms": {"p50": round(1000 * percentile(blat, 0.5), 4),
                                   "p99": round(1000 * percentile(blat, 0.99), 4)},
                    "kernel_us_per_batch_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, btot / breps)},
                    "kernel_us_per_launch": {k: round(v, 3) for k, v in b_replay.items()},
-                   "kernel_gbs": b_rates, "roofline": b_roof, "identical_results": bool(same)}
+                   "kernel_gbs": b_rates, "roofline": b_roof, "identical_results": bool(same),
+                   "launch_variant": {k: ("xcd" if orders[i] & 1 else "linear") + ("+wide" if orders[i] & 2 else "")
+                                      for i, k in enumerate(KERNELS)
+                                      if k not in ("depth_prep", "node_update", "asm_segments")}}
         print(f"[bench] batched x{B}: {batched['value']} frames/s", file=sys.stderr, flush=True)
 
     served = None

@@ -183,6 +183,22 @@ sw_status sw_solve_batch(sw_batch b, const sw_stream* streams, int32_t n,
 sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int32_t stage,
                            int32_t pcg_it, int32_t reps, float* us_per_launch);
 
+/* Autotuner: for the shape bucket of this batch (stream count and the
+ * powers of two of its total surfels and nodes) time each per-frame stage
+ * (1 warp, 2 correspondence, 8 fold, 4 PCG start, 5 product, 6 update) reps
+ * times back to back in each launch variant and keep the fastest for later
+ * solves of batches in that bucket on this executor. Variants: the tile
+ * order — linear, or XCD-contiguous (the workgroups an XCD runs take one
+ * contiguous range of tiles, keeping a stream's data in few L2 caches) — and,
+ * for the product and the update, 1 or 2 block rows per wave / nodes per lane
+ * group. Every variant computes the same tiles with the same reductions, so
+ * results do not change. Use after a solve of the batch (the stages replay
+ * its last frame; workspaces are overwritten, warp fields are not). variants
+ * (NULL or 12 entries, indexed like stage_us) receives the choices: bit 0 =
+ * XCD-contiguous order, bit 1 = 2 rows / nodes. */
+sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int32_t reps,
+                            int32_t* variants);
+
 /* ---- serving: frames of many streams arriving at any time ----
  *
  * A server owns a HIP stream (or uses the caller's), one device slab for the

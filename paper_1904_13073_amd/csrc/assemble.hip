@@ -128,34 +128,41 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
 #pragma unroll
     for (int t = 0; t < 6; ++t) gacc[t] = row16_sum(gacc[t]);
     er = row16_sum(er);
-    if (active && g == 0) {
-        if (diag) {
+    if (active && diag) {
 #pragma unroll
-            for (int a = 0; a < 6; ++a) acc[7 * a] += in.mu;
+        for (int a = 0; a < 6; ++a) acc[7 * a] += in.mu;
+        if (g == 0) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) in.g[6 * k + c] = gacc[c];
             in.ereg[k] = er;
         }
-        // the product's explicit rows: the block in its row, its transpose in the column's row
-        float4* fu = reinterpret_cast<float4*>(in.Hf + (size_t)in.slot_u[b] * 36);
+    }
+    if (active) {
+        // every lane of the group holds the block: lane g stores float4 g of
+        // the block into its row of the product (g < 9) and float4 g - 9 of
+        // the transpose into the column's row (9 <= g; g < 2 take float4 7, 8);
+        // the selects keep every register index a compile-time constant
+        const int vu = g < 9 ? g : 0;
+        const int vt = g < 9 ? 7 + g : g - 9;   // g < 2: float4 7 or 8; 9 <= g: float4 0..6
+        float u4[4], t4[4];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) fu[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
-        if (!diag) {
-            float tr[36];
+        for (int e = 0; e < 4; ++e) {
+            float su = acc[e], st = acc[6 * e];
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
-#pragma unroll
-                for (int j = 0; j < 6; ++j) tr[6 * i + j] = acc[6 * j + i];
-            float4* ft = reinterpret_cast<float4*>(in.Hf + (size_t)in.slot_t[b] * 36);
-#pragma unroll
-            for (int v = 0; v < 9; ++v) ft[v] = make_float4(tr[4 * v], tr[4 * v + 1], tr[4 * v + 2], tr[4 * v + 3]);
+            for (int v = 1; v < 9; ++v) {
+                const int q = 4 * v + e;             // element q of the block, row-major
+                su = (vu == v) ? acc[q] : su;
+                st = (vt == v) ? acc[6 * (q % 6) + q / 6] : st;
+            }
+            u4[e] = su;
+            t4[e] = st;
         }
-        if (diag || capture) {
-            float4* out = reinterpret_cast<float4*>(in.H + (size_t)b * 36);
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                out[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
-        }
+        const float4 fu4 = make_float4(u4[0], u4[1], u4[2], u4[3]);
+        const float4 ft4 = make_float4(t4[0], t4[1], t4[2], t4[3]);
+        float* Hf = in.Hf;
+        if (g < 9) reinterpret_cast<float4*>(Hf + (size_t)in.slot_u[b] * 36)[g] = fu4;
+        if (!diag && (g >= 9 || g < 2)) reinterpret_cast<float4*>(Hf + (size_t)in.slot_t[b] * 36)[vt] = ft4;
+        if ((diag || capture) && g < 9) reinterpret_cast<float4*>(in.H + (size_t)b * 36)[g] = fu4;
     }
 }
 

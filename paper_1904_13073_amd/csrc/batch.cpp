@@ -97,6 +97,7 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
     }
     return guarded(b->err, [&]() -> sw_status {
         std::vector<int> its(n, 0), ev;
+        b->exec.bucket = shape_bucket(ss);
         run_stage(b->exec, stage, ss, its, pcg_it, nullptr, false, ev);   // warm
         hipEvent_t e0 = b->exec.event(0), e1 = b->exec.event(1);
         SWGN_HIP(hipEventRecord(e0, b->exec.st));
@@ -106,6 +107,57 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
         float ms = 0.f;
         SWGN_HIP(hipEventElapsedTime(&ms, e0, e1));
         *us_per_launch = 1000.f * ms / (float)reps;
+        return SW_OK;
+    });
+}
+
+sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int32_t reps, int32_t* variants) {
+    if (!b) return SW_EINVAL;
+    if (!streams) return fail(b->err, SW_EINVAL, "streams must not be NULL");
+    if (n < 1 || n > kMaxBatch) return fail(b->err, SW_EINVAL, "batch size must be in [1, 64]");
+    if (reps < 1 || reps > 10000) return fail(b->err, SW_EINVAL, "reps must be in [1, 10000]");
+    std::vector<sw_stream> ss(streams, streams + n);
+    for (int i = 0; i < n; ++i) {
+        if (!ss[i]) return fail(b->err, SW_EINVAL, "NULL stream in the batch");
+        if (!ss[i]->graph_set) return fail(b->err, SW_ESTATE, "every stream needs a node graph");
+        if (ss[i]->server) return fail(b->err, SW_ESTATE, "a stream in the batch is attached to a server");
+    }
+    return guarded(b->err, [&]() -> sw_status {
+        Executor& ex = b->exec;
+        const uint64_t key = shape_bucket(ss);
+        std::vector<int> choice(kNumStages, 0);
+        const int stages[] = {kStWarp, kStCorr, kStAsmFold, kStPcgInit, kStSpmv, kStUpdate};
+        std::vector<int> its(n, 0), ev;
+        for (int stage : stages) {
+            const bool has_wide = stage == kStSpmv || stage == kStUpdate;
+            float best = 0.f;
+            bool first = true;
+            for (int variant = 0; variant < (has_wide ? 4 : 2); ++variant) {
+                // time `reps` back-to-back launches of the stage in this variant
+                std::vector<int> trial = choice;
+                trial[stage] = variant;
+                ex.tuned[key] = trial;
+                ex.bucket = key;
+                const int pit = has_wide ? 1 : 0;
+                run_stage(ex, stage, ss, its, pit, nullptr, false, ev);
+                hipEvent_t e0 = ex.event(0), e1 = ex.event(1);
+                SWGN_HIP(hipEventRecord(e0, ex.st));
+                for (int r = 0; r < reps; ++r) run_stage(ex, stage, ss, its, pit, nullptr, false, ev);
+                SWGN_HIP(hipEventRecord(e1, ex.st));
+                SWGN_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                SWGN_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (first || ms < best) {
+                    best = ms;
+                    choice[stage] = variant;
+                    first = false;
+                }
+            }
+        }
+        ex.tuned[key] = choice;
+        ex.tune_epoch += 1;
+        if (variants)
+            for (int k = 0; k < kNumStages; ++k) variants[k] = choice[k];
         return SW_OK;
     });
 }

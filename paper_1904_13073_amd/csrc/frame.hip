@@ -109,7 +109,11 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
 // J^T r and r^T r are stored per segment for the block fold. Jacobian rows
 // leave the chip only when an iteration is captured.
 // ---------------------------------------------------------------------------
-constexpr int kRowPad = 33;   // LDS row stride in floats (odd: no bank conflicts)
+// LDS row stride in floats: 25 entries (J, r), odd so that a row per lane is
+// conflict-free. The MFMA reads 32 columns per row; columns 25..31 run into
+// the next row (or the slack after the last one) and only feed Gram entries
+// with an index >= 25, which are discarded.
+constexpr int kRowPad = 25;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -117,6 +121,62 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ int sub_block(int pa, int pb) {
     const int first[4] = {0, 4, 7, 9};
     return first[pa] + (pb - pa);
+}
+
+// d r / d xi_k for the 4 nodes of a matched surfel: the closed form of
+// N^T dF/db(b; v) w_k s_k M(q_k, c_k). With P = N c_r, Q = N c_d, PV = P (0,v)
+// and a_k = w_k s_k / |b_r|:
+//   d r / d tau_k   = a_k vec(P r_k*)
+//   d r / d omega_k = a_k [vec(P d_k*) - vec(W r_k*) - c_k x vec(P r_k*)],
+//   W = PV + Q + (N . v') c_r   (vec(x y*) is linear in x).
+// No integer decision depends on these values, so multiply-adds may fuse here.
+// Quaternion helpers of the Jacobian, with multiply-adds allowed to fuse.
+__device__ __forceinline__ Q4 qmul_c(Q4 a, Q4 b) {
+#pragma clang fp contract(fast)
+    Q4 r;
+    r.w = a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z;
+    r.x = a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y;
+    r.y = a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x;
+    r.z = a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w;
+    return r;
+}
+__device__ __forceinline__ float3 vec_mul_conj_c(Q4 x, Q4 y) {
+#pragma clang fp contract(fast)
+    return make_float3(y.w * x.x - x.w * y.x - (x.y * y.z - x.z * y.y),
+                       y.w * x.y - x.w * y.y - (x.z * y.x - x.x * y.z),
+                       y.w * x.z - x.w * y.z - (x.x * y.y - x.y * y.x));
+}
+
+__device__ __forceinline__ void jacobian_rows(const FrameDesc& d, int4 id, float4 w4, float3 v, float3 N,
+                                              const Warp& wp, float (&Jw)[4][3], float (&Jt)[4][3]) {
+#pragma clang fp contract(fast)
+    const Q4 Nq = {0.f, N.x, N.y, N.z};
+    const Q4 P = qmul_c(Nq, wp.cr);
+    const Q4 Qd = qmul_c(Nq, wp.cd);
+    const Q4 PV = qmul_c(P, Q4{0.f, v.x, v.y, v.z});
+    const float ndv = N.x * wp.v.x + N.y * wp.v.y + N.z * wp.v.z;
+    const Q4 W = {PV.w + Qd.w + ndv * wp.cr.w, PV.x + Qd.x + ndv * wp.cr.x, PV.y + Qd.y + ndv * wp.cr.y,
+                  PV.z + Qd.z + ndv * wp.cr.z};
+    const int ids[4] = {id.x, id.y, id.z, id.w};
+    const float wk[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const Q4 rk = q4(d.dq[2 * ids[k]]);
+        const Q4 dk = q4(d.dq[2 * ids[k] + 1]);
+        const float4 c4 = d.cl[ids[k]];
+        const float a = wk[k] * wp.sgn[k] * wp.inv_beta;
+        const float3 h = vec_mul_conj_c(P, rk);
+        const float3 g1 = vec_mul_conj_c(P, dk);
+        const float3 gW = vec_mul_conj_c(W, rk);
+        // c_k x h
+        const float cx = c4.y * h.z - c4.z * h.y, cy = c4.z * h.x - c4.x * h.z, cz = c4.x * h.y - c4.y * h.x;
+        Jw[k][0] = a * (g1.x - gW.x - cx);
+        Jw[k][1] = a * (g1.y - gW.y - cy);
+        Jw[k][2] = a * (g1.z - gW.z - cz);
+        Jt[k][0] = a * h.x;
+        Jt[k][1] = a * h.y;
+        Jt[k][2] = a * h.z;
+    }
 }
 
 // Jacobian entry as stored: fp32, or rounded to nearest-even bf16 / fp16 and
@@ -134,7 +194,8 @@ __device__ __forceinline__ float keep_jac(float v, int dtype) {
 __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
-    __shared__ float rows[kCorrBlock * kRowPad];
+    __shared__ float rows[kCorrBlock * kRowPad + 8];
+    __shared__ float4 stage4[kCorrBlock / kWave][kSegSlots / 4];
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
@@ -173,31 +234,7 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
                     if (d2 < d.dist2 && dot3(wp.n, N) > d.cosn) {
                         matched = true;
                         r = dot3(N, dv);
-                        // d r / d xi_k, closed form of N^T dF/db(b; v) w_k s_k M(q_k, c_k)
-                        Q4 Nq = {0.f, N.x, N.y, N.z};
-                        Q4 P = qmul(Nq, wp.cr);
-                        Q4 Qd = qmul(Nq, wp.cd);
-                        Q4 PV = qmul(P, Q4{0.f, v.x, v.y, v.z});
-                        float ndv = dot3(N, wp.v);
-                        const int ids[4] = {id.x, id.y, id.z, id.w};
-                        const float wk[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            Q4 rk = q4(d.dq[2 * ids[k]]);
-                            Q4 dk = q4(d.dq[2 * ids[k] + 1]);
-                            float4 c4 = d.cl[ids[k]];
-                            float3 ck = make_float3(c4.x, c4.y, c4.z);
-                            float a = (wk[k] * wp.sgn[k]) * wp.inv_beta;
-                            float3 h = vec_mul_conj(P, rk);
-                            float3 g1 = vec_mul_conj(P, dk);
-                            float3 g2 = vec_mul_conj(PV, rk);
-                            float3 g3 = vec_mul_conj(Qd, rk);
-                            float3 g4 = vec_mul_conj(wp.cr, rk);
-                            float3 g5 = cross3(ck, h);
-                            float3 gw = sub3(sub3(sub3(g1, g2), g3), add3(scale3(g4, ndv), g5));
-                            Jw[k][0] = a * gw.x; Jw[k][1] = a * gw.y; Jw[k][2] = a * gw.z;
-                            Jt[k][0] = a * h.x;  Jt[k][1] = a * h.y;  Jt[k][2] = a * h.z;
-                        }
+                        jacobian_rows(d, id, w4, v, N, wp, Jw, Jt);
                     }
                 }
             }
@@ -207,17 +244,28 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
         // the row: node block k goes to position = rank of its id in the set
         float* row = &rows[threadIdx.x * kRowPad];
         const int ids[4] = {id.x, id.y, id.z, id.w};
-        const int jd = d.jac_dtype;
+        const int jd = d.jac_dtype;          // uniform: one branch for the whole row
+        if (jd != 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Jw[k][c] = keep_jac(Jw[k][c], jd);
+                    Jt[k][c] = keep_jac(Jt[k][c], jd);
+                }
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
             float* o = row + pos * 6;
-            o[0] = keep_jac(Jw[k][0], jd); o[1] = keep_jac(Jw[k][1], jd); o[2] = keep_jac(Jw[k][2], jd);
-            o[3] = keep_jac(Jt[k][0], jd); o[4] = keep_jac(Jt[k][1], jd); o[5] = keep_jac(Jt[k][2], jd);
+            o[0] = Jw[k][0]; o[1] = Jw[k][1]; o[2] = Jw[k][2];
+            o[3] = Jt[k][0]; o[4] = Jt[k][1]; o[5] = Jt[k][2];
         }
         row[24] = r;
+        if (threadIdx.x == kCorrBlock - 1) {
 #pragma unroll
-        for (int c = 25; c < 32; ++c) row[c] = 0.f;
+            for (int c = 0; c < 8; ++c) rows[kCorrBlock * kRowPad + c] = 0.f;
+        }
     }
     if (live && capture) {
         float nanv = __int_as_float(0x7fc00000);
@@ -243,11 +291,26 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
         const int nrow = min(kWave, p1 - p0 - base);
         for (int q = 0; q < kWave / 2; ++q) {
             const int rr = 2 * q + (lane >> 5), c = lane & 31;
-            if (rr < nrow) dst[rr * 32 + c] = rows[(base + rr) * kRowPad + c];
+            if (rr < nrow) dst[rr * 32 + c] = c < 25 ? rows[(base + rr) * kRowPad + c] : 0.f;
         }
     }
-    // segment Gram matrices, one wave per segment
+    // segment Gram matrices, one wave per segment. Accumulator element t of
+    // lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4;
+    // its slot among the segment's 400 floats (-1: not stored) is fixed per lane
     const int comp = lane & 31, half = lane >> 5;
+    int slot[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int ii = (t >> 2) * 8 + half * 4 + (t & 3), j = comp;
+        int sl = -1;
+        if (ii < 24 && j < 24) {
+            const int pa = ii / 6, pb = j / 6;
+            if (pa <= pb) sl = sub_block(pa, pb) * 36 + (ii % 6) * 6 + (j % 6);
+        } else if (j == 24 && ii <= 24) {
+            sl = 360 + ii;                       // J^T r (ii < 24), r^T r (ii = 24)
+        }
+        slot[t] = sl;
+    }
     const int g0 = d.pack_seg[at.tile], g1 = d.pack_seg[at.tile + 1];
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
         const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
@@ -264,20 +327,19 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
         }
-        // accumulator element t of lane l is G[i][j], j = l % 32,
-        // i = (t / 4) * 8 + (l / 32) * 4 + t % 4
-        float* out = d.part + (size_t)seg * kSegSlots;
-        const int j = comp;
+        // staged in LDS, stored as whole lines
+        float* sg = reinterpret_cast<float*>(stage4[wave]);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int ii = (t >> 2) * 8 + half * 4 + (t & 3);
-            if (ii < 24 && j < 24) {
-                const int pa = ii / 6, pb = j / 6;
-                if (pa <= pb) out[sub_block(pa, pb) * 36 + (ii % 6) * 6 + (j % 6)] = acc[t];
-            } else if (j == 24 && ii <= 24) {
-                out[360 + ii] = acc[t];          // J^T r (ii < 24), r^T r (ii = 24)
-            }
-        }
+        for (int t = 0; t < 16; ++t)
+            if (slot[t] >= 0) sg[slot[t]] = acc[t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float4* out = reinterpret_cast<float4*>(d.part + (size_t)seg * kSegSlots);
+        for (int q = lane; q < kSegSlots / 4; q += kWave) out[q] = stage4[wave][q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 

@@ -74,6 +74,32 @@ void Executor::init(void* hip_stream) {
     SWGN_HIP(hipHostMalloc(&stats_host, (size_t)kStatsOutBytes * kMaxBatch, hipHostMallocDefault));
 }
 
+int Executor::variant_of(int stage, int64_t rows) const {
+    const auto it = tuned.find(bucket);
+    if (it != tuned.end()) return it->second[stage];
+    // untuned: the wide geometries only when the launch still has two
+    // workgroups per CU with them
+    const bool wide = (stage == kStSpmv && rows >= 256 * 2 * 2 * kSpmvWaves) ||
+                      (stage == kStUpdate && rows >= 256 * 2 * 2 * kSolvePart);
+    return wide ? kVarWide : 0;
+}
+
+// Shape bucket of a batch: the stream count and the powers of two of its total
+// surfels and nodes. Tuned choices are kept per bucket.
+uint64_t shape_bucket(const std::vector<sw_stream>& ss) {
+    int64_t ns = 0, nn = 0;
+    for (sw_stream s : ss) {
+        ns += s->h.ns;
+        nn += s->h.nn;
+    }
+    auto lg = [](int64_t v) {
+        uint64_t b = 0;
+        while (((int64_t)1 << b) < v) ++b;
+        return b;
+    };
+    return ((uint64_t)ss.size() << 16) | (lg(ns) << 8) | lg(nn);
+}
+
 hipEvent_t Executor::event(size_t i) {
     while (events.size() <= i) {
         hipEvent_t e;
@@ -93,7 +119,7 @@ size_t carve_workspace(FrameDesc& h, char* base) {
         off += (bytes + 255) & ~size_t(255);
     };
     const size_t npx = (size_t)h.npx, nn = (size_t)h.nn;
-    const size_t nsol = (size_t)solve_tiles(h), nspm = (size_t)spmv_tiles(h), ncor = (size_t)corr_tiles(h);
+    const size_t nsol = (size_t)solve_parts(h), nspm = (size_t)spmv_parts(h), ncor = (size_t)corr_tiles(h);
     take(h.depth, 4 * npx);
     take(h.nmap, 16 * npx);
     take(h.zbuf, 8 * npx);
@@ -415,13 +441,19 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
     Batch b{};
     b.n = (int)ss.size();
     b.pcg_it = pcg_it;
+    int64_t rows = 0;
+    for (int i = 0; i < b.n; ++i)
+        if (its[i] >= 0) rows += ss[i]->h.nn;
+    const int variant = ex.variant_of(stage, rows);
+    b.order = (variant & kVarXcd) ? kOrderXcd : kOrderLinear;
+    b.wide = (variant & kVarWide) ? 1 : 0;
     int off = 0;
     for (int i = 0; i < b.n; ++i) {
         const FrameDesc& h = ss[i]->h;
         b.off[i] = off;
         b.d[i] = ss[i]->d_desc;
         b.it[i] = (int8_t)its[i];
-        int t = stage_tiles(stage, h);
+        int t = stage_tiles(stage, h, variant);
         if (its[i] < 0) t = 0;
         if ((stage == kStSpmv || stage == kStUpdate) && pcg_it >= h.pcg_iters) t = 0;
         off += t;
@@ -578,6 +610,7 @@ sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const fl
 sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths,
                        int32_t on_device, bool timing, sw_frame_stats* stats, sw_status* status) {
     const int n = (int)ss.size();
+    ex.bucket = shape_bucket(ss);
     std::vector<int> ev;
     int gmax = 0;
     bool any_capture = false;
@@ -601,6 +634,7 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
         // streams' buffers are unchanged
         std::vector<std::pair<sw_stream, uint64_t>> key;
         for (sw_stream s : ss) key.emplace_back(s, s->generation);
+        key.emplace_back(nullptr, ex.tune_epoch);
         if (!ex.graph_exec || key != ex.graph_key) {
             ex.drop_graph();
             hipGraph_t g = nullptr;

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,12 @@ struct Executor {
     char* stats_dev = nullptr;
     void* stats_host = nullptr;
     std::vector<hipEvent_t> events;
+    // launch variant per stage (kVarXcd | kVarWide bits), per shape bucket of
+    // a batch; chosen by the autotuner, a size rule where it has not run
+    std::map<uint64_t, std::vector<int>> tuned;
+    uint64_t bucket = 0;                  // bucket of the batch being launched
+    uint64_t tune_epoch = 0;              // bumped when a choice changes (captured graphs are stale)
+    int variant_of(int stage, int64_t rows) const;
     // replay of a batch's iterations as one HIP graph
     bool graphs = false;
     hipGraphExec_t graph_exec = nullptr;
@@ -132,6 +139,7 @@ sw_status collect_frames(Executor& ex, const std::vector<sw_stream>& ss, const f
                          sw_frame_stats* stats, sw_status* status);
 sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* stage_us,
                         sw_frame_stats* stats, sw_status* status);
+uint64_t shape_bucket(const std::vector<sw_stream>& ss);
 void server_quiesce(sw_server sv, sw_stream s);
 void server_forget(sw_server sv, sw_stream s);
 sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths,

@@ -119,25 +119,20 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     }
 }
 
-// q = A p_it with p_it = z + beta p_{it-1} (beta = 0 and p_0 = z at it = 0).
-// The row's products with z and with p_{it-1} are accumulated separately, so
-// the matrix loads run before beta (a grid-wide sum) is known.
-__global__ void __launch_bounds__(64 * kSpmvRows) k_pcg_spmv(Batch b) {
-    __shared__ double sh[40];
-    const Where at = locate(b);
-    const FrameDesc a = *b.d[at.s];
-    const int it = b.pcg_it;
-    float* const pbuf[2] = {a.p0, a.p1};
-    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];
-    float* pcur = pbuf[it & 1];
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int k = at.tile * kSpmvRows + wave;
+// Products of one block row with z and with p_old: 8-lane group fl takes the
+// row's slots fl, fl + 8, ...; lane sub < 6 holds row sub of the slot's block
+// (one 24-byte line) and element sub of the column's z and p_old, which the
+// group shares by shuffles. The row's products with z and with p_{it-1} are
+// accumulated separately, so the matrix loads run before beta (a grid-wide
+// sum) is known.
+struct RowAcc {
+    float az, ap;
+};
+
+__device__ __forceinline__ RowAcc row_products(const FrameDesc& a, const float* __restrict__ pold, int k, int lane) {
     const int sub = lane & 7, fl = lane >> 3;
     float az = 0.f, ap = 0.f;
     if (k < a.nn) {
-        // 8-lane group fl takes the row's slots fl, fl + 8, ...; lane sub < 6
-        // holds row sub of the slot's block (one 24-byte line) and element sub
-        // of the column's z and p_old, which the group shares by shuffles
         const uint32_t* eb = a.ell_blk + (size_t)k * a.ell_w;
         const int* ec = a.ell_col + (size_t)k * a.ell_w;
         const int base = lane & ~7;
@@ -168,72 +163,156 @@ __global__ void __launch_bounds__(64 * kSpmvRows) k_pcg_spmv(Batch b) {
     ap += __shfl_xor(ap, 8, kWave);
     ap += __shfl_xor(ap, 16, kWave);
     ap += __shfl_xor(ap, 32, kWave);
-    const double rho = reduce_partials(a.part_rho, solve_tiles(a), sh);
+    return RowAcc{az, ap};
+}
+
+// Sum of n partials in the fixed shape of a 256-thread reduction (thread t
+// adds part[t], part[t + 256], ..., then the wave sums, then the 4 waves in
+// order), whatever the workgroup size; result in every thread.
+__device__ __forceinline__ double reduce_parts256(const double* __restrict__ part, int n, double* sh) {
+    double v = 0.0;
+    if (threadIdx.x < 256)
+        for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0 && w < 4) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < 4; ++q) t += sh[q];
+        sh[32] = t;
+    }
+    __syncthreads();
+    const double r = sh[32];
+    __syncthreads();
+    return r;
+}
+
+// q = A p_it with p_it = z + beta p_{it-1} (beta = 0 and p_0 = z at it = 0);
+// one workgroup = 4 waves of RPW block rows each.
+template <int RPW>
+__global__ void __launch_bounds__(64 * kSpmvWaves) k_pcg_spmv(Batch b) {
+    __shared__ double sh[40];
+    __shared__ double rs[8];
+    const Where at = locate(b);
+    const FrameDesc a = *b.d[at.s];
+    const int it = b.pcg_it;
+    float* const pbuf[2] = {a.p0, a.p1};
+    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];
+    float* pcur = pbuf[it & 1];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int k0 = at.tile * kSpmvWaves * RPW + RPW * wave;
+    RowAcc ra[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) ra[u] = row_products(a, pold, k0 + u, lane);
+    const double rho = reduce_parts256(a.part_rho, solve_parts(a), sh);
     const bool stop = (rho == 0.0);
     const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[(it - 1) & 1]) : 0.f;
     if (at.tile == 0 && threadIdx.x == 0) a.sc[it & 1] = rho;   // read by this iteration's update
-    double pq = 0.0;
-    if (!stop && k < a.nn && lane < 6) {
-        const int t = 6 * k + lane;
-        const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
-        const float qv = az + beta * ap;
-        if (it > 0) pcur[t] = pk;
-        a.q[t] = qv;
-        pq = (double)pk * (double)qv;
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+        const int k = k0 + u;
+        double pq = 0.0;
+        if (!stop && k < a.nn && lane < 6) {
+            const int t = 6 * k + lane;
+            const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
+            const float qv = ra[u].az + beta * ra[u].ap;
+            if (it > 0) pcur[t] = pk;
+            a.q[t] = qv;
+            pq = (double)pk * (double)qv;
+        }
+        pq = wave_sum(pq);
+        if (lane == 0) rs[RPW * wave + u] = pq;
     }
-    pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) a.part_pq[at.tile] = pq;
+    __syncthreads();
+    // partials per 4 rows, each the in-order sum of its rows' wave sums
+    if (threadIdx.x < RPW) {
+        const int quad = at.tile * RPW + threadIdx.x;
+        if (quad < spmv_parts(a)) {
+            double t = 0.0;
+            for (int q = 0; q < 4; ++q) t += rs[4 * threadIdx.x + q];
+            a.part_pq[quad] = t;
+        }
+    }
 }
 
+// x += alpha p, r -= alpha q, z = M r: 8 lanes per node, NPG nodes per lane
+// group (k, k + 32, ... of the workgroup's 32 NPG).
+template <int NPG>
 __global__ void __launch_bounds__(kSolveBlock) k_pcg_update(Batch b) {
     __shared__ double sh[40];
+    __shared__ double ws[NPG][2][4];
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
     const int it = b.pcg_it;
     const float* p = (it & 1) ? a.p1 : a.p0;
-    const int gid = at.tile * kSolveBlock + threadIdx.x;
-    const int k = gid >> 3, c = gid & 7;
-    const bool on = (k < a.nn) && (c < 6);
-    const int t = 6 * k + c;
-    float rc = 0.f, xc = 0.f, pc = 0.f, qc = 0.f;
-    double mrow[6];
-    if (on) {
-        rc = a.r[t]; xc = a.x[t]; pc = p[t]; qc = a.q[t];
+    const int c = threadIdx.x & 7;
+    const int base = (threadIdx.x & ~7);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    float rc[NPG], xc[NPG], pc[NPG], qc[NPG];
+    double mrow[NPG][6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) mrow[j] = a.Minv[(size_t)k * 36 + c * 6 + j];
-    } else {
+    for (int u = 0; u < NPG; ++u) {
+        const int k = at.tile * NPG * kSolvePart + u * kSolvePart + (threadIdx.x >> 3);
+        const bool on = (k < a.nn) && (c < 6);
+        const int t = 6 * k + c;
+        rc[u] = xc[u] = pc[u] = qc[u] = 0.f;
+        if (on) {
+            rc[u] = a.r[t]; xc[u] = a.x[t]; pc[u] = p[t]; qc[u] = a.q[t];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) mrow[j] = 0.0;
+            for (int j = 0; j < 6; ++j) mrow[u][j] = a.Minv[(size_t)k * 36 + c * 6 + j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) mrow[u][j] = 0.0;
+        }
     }
     const double rho = a.sc[it & 1];
     const bool stop = (rho == 0.0);
-    const double pq = reduce_partials(a.part_pq, spmv_tiles(a), sh);
-    double rz = 0.0, rr = 0.0;
-    if (!stop) {
-        const float alpha = (float)(rho / pq);
-        xc = xc + alpha * pc;
-        rc = rc - alpha * qc;
-        if (on) {
-            a.x[t] = xc;
-            a.r[t] = rc;
-        }
-        // z_c = sum_j M[c][j] r_j: the node's 6 residual entries from its lanes
-        const int base = (threadIdx.x & ~7);
-        double zc = 0.0;
+    const double pq = reduce_parts256(a.part_pq, spmv_parts(a), sh);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) zc += mrow[j] * (double)__shfl(rc, base + j, kWave);
-        if (on) {
-            const float zf = (float)zc;
-            a.z[t] = zf;
-            rz = (double)rc * (double)zf;
+    for (int u = 0; u < NPG; ++u) {
+        const int k = at.tile * NPG * kSolvePart + u * kSolvePart + (threadIdx.x >> 3);
+        const bool on = (k < a.nn) && (c < 6);
+        const int t = 6 * k + c;
+        double rz = 0.0, rr = 0.0;
+        float r1 = rc[u];
+        if (!stop) {
+            const float alpha = (float)(rho / pq);
+            const float x1 = xc[u] + alpha * pc[u];
+            r1 = rc[u] - alpha * qc[u];
+            if (on) {
+                a.x[t] = x1;
+                a.r[t] = r1;
+            }
+            // z_c = sum_j M[c][j] r_j: the node's 6 residual entries from its lanes
+            double zc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) zc += mrow[u][j] * (double)__shfl(r1, base + j, kWave);
+            if (on) {
+                const float zf = (float)zc;
+                a.z[t] = zf;
+                rz = (double)r1 * (double)zf;
+            }
+        }
+        if (on) rr = (double)r1 * (double)r1;
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
+        if (lane == 0) {
+            ws[u][0][wave] = rz;
+            ws[u][1][wave] = rr;
         }
     }
-    if (on) rr = (double)rc * (double)rc;
-    rz = block_sum(rz, sh);
-    rr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        a.part_rho[at.tile] = rz;
-        a.part_rr[at.tile] = rr;
+    __syncthreads();
+    // partials per 32 nodes, in-order sums of 4 wave sums
+    if (threadIdx.x < NPG) {
+        const int u = threadIdx.x;
+        const int part = at.tile * NPG + u;
+        if (part < solve_parts(a)) {
+            double tz = 0.0, tr = 0.0;
+            for (int q = 0; q < 4; ++q) { tz += ws[u][0][q]; tr += ws[u][1][q]; }
+            a.part_rho[part] = tz;
+            a.part_rr[part] = tr;
+        }
     }
 }
 
@@ -247,7 +326,7 @@ __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
     if (at.tile == 0) {
         const int nparts = corr_tiles(a);
         IterStats* stats = a.stats + b.it[at.s];
-        const double rr = reduce_partials(a.part_rr, solve_tiles(a), sh);
+        const double rr = reduce_partials(a.part_rr, solve_parts(a), sh);
         // energies at this iteration's linearisation point
         double e = 0.0, n = 0.0, er = 0.0;
         for (int t = threadIdx.x; t < nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
@@ -284,8 +363,14 @@ void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t 
     if (grid <= 0) return;
     switch (stage) {
         case kStPcgInit: hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kSolveBlock), 0, st, b); break;
-        case kStSpmv: hipLaunchKernelGGL(k_pcg_spmv, dim3(grid), dim3(64 * kSpmvRows), 0, st, b); break;
-        case kStUpdate: hipLaunchKernelGGL(k_pcg_update, dim3(grid), dim3(kSolveBlock), 0, st, b); break;
+        case kStSpmv:
+            if (b.wide) hipLaunchKernelGGL(k_pcg_spmv<2>, dim3(grid), dim3(64 * kSpmvWaves), 0, st, b);
+            else hipLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(64 * kSpmvWaves), 0, st, b);
+            break;
+        case kStUpdate:
+            if (b.wide) hipLaunchKernelGGL(k_pcg_update<2>, dim3(grid), dim3(kSolveBlock), 0, st, b);
+            else hipLaunchKernelGGL(k_pcg_update<1>, dim3(grid), dim3(kSolveBlock), 0, st, b);
+            break;
         case kStNodeUpdate: hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
         case kStStatsOut:
             hipLaunchKernelGGL(k_stats_out, dim3(grid), dim3(64), 0, st, b, static_cast<char*>(stats_out));

@@ -26,8 +26,13 @@ constexpr int kDepthTile = 16;        // 16 x 16 pixels per workgroup
 constexpr int kWarpBlock = 256;       // surfels per workgroup
 constexpr int kCorrBlock = 256;
 constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
-constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes
-constexpr int kSpmvRows = 4;          // block rows per workgroup (one wave each)
+constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes; the update may take 2 nodes per lane group
+constexpr int kSpmvWaves = 4;         // product workgroup: 4 waves of 1 or 2 block rows each
+// Partial sums of the PCG dot products are taken per 32 nodes (r.z, r.r) and
+// per 4 block rows (p.q), whatever the launch geometry, so every reduction
+// has one fixed shape.
+constexpr int kSolvePart = 32;
+constexpr int kSpmvPart = 4;
 constexpr int kNodeBlock = 256;
 
 constexpr int kSegLen = 128;          // surfels per segment at most (one node set)
@@ -87,10 +92,16 @@ enum Stage {
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int corr_tiles(const FrameDesc& d) { return d.npack; }
-__host__ __device__ inline int solve_tiles(const FrameDesc& d) { return cdiv(8 * d.nn, kSolveBlock); }
-__host__ __device__ inline int spmv_tiles(const FrameDesc& d) { return cdiv(d.nn, kSpmvRows); }
+__host__ __device__ inline int solve_parts(const FrameDesc& d) { return cdiv(d.nn, kSolvePart); }
+__host__ __device__ inline int spmv_parts(const FrameDesc& d) { return cdiv(d.nn, kSpmvPart); }
 
-inline int stage_tiles(int stage, const FrameDesc& d) {
+// Launch variant of a stage: bit 0 = tile order (kOrderXcd), bit 1 = the
+// wider geometry of the stage where it has one (2 block rows per product
+// wave, 2 nodes per update lane group). No variant changes any arithmetic.
+constexpr int kVarXcd = 1;
+constexpr int kVarWide = 2;
+
+inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
     switch (stage) {
         case kStDepth: {
             const int px = cdiv(d.cam.W, kDepthTile) * cdiv(d.cam.H, kDepthTile);
@@ -101,9 +112,9 @@ inline int stage_tiles(int stage, const FrameDesc& d) {
         case kStCorr: return corr_tiles(d);
         case kStAsmSeg: return 0;     // the segment Gram matrices are formed by the correspondence kernel
         case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
-        case kStPcgInit: return solve_tiles(d);
-        case kStSpmv: return spmv_tiles(d);
-        case kStUpdate: return solve_tiles(d);
+        case kStPcgInit: return cdiv(d.nn, kSolvePart);
+        case kStSpmv: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSpmvWaves : kSpmvWaves);
+        case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolvePart : kSolvePart);
         case kStNodeUpdate: return cdiv(d.nn > d.npx ? d.nn : d.npx, kNodeBlock);
         case kStStatsOut: return 1;
         default: return 0;
@@ -114,6 +125,8 @@ inline int stage_tiles(int stage, const FrameDesc& d) {
 struct Batch {
     int n;                        // streams
     int pcg_it;                   // PCG iteration of this launch
+    int order;                    // kOrderXcd: tiles in XCD-contiguous order
+    int wide;                     // the stage's wider geometry (kVarWide)
     int off[kMaxBatch + 1];       // stream s owns tiles [off[s], off[s+1])
     const FrameDesc* d[kMaxBatch];
     int8_t it[kMaxBatch];         // Gauss-Newton iteration of each stream
@@ -123,6 +136,22 @@ struct DepthIn {
     const float* p[kMaxBatch];    // depth image of each stream (device)
 };
 
+// Tile order of a launch. Workgroups are dealt to the 8 XCDs round-robin
+// (workgroup i runs on XCD i mod 8). With kOrderXcd, XCD x takes one
+// contiguous range of tiles instead of every 8th tile, so a stream's tiles
+// (and the node tables, maps and blocks they touch) stay in few L2s. The
+// mapping is a bijection on [0, tiles) and changes no arithmetic.
+constexpr int kOrderLinear = 0;
+constexpr int kOrderXcd = 1;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int tile_of_block(int i, int tiles, int order) {
+    if (order != kOrderXcd) return i;
+    const int x = i % kXcds, k = i / kXcds;
+    const int q = tiles / kXcds, r = tiles % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 struct Where {
     int s;       // stream index in the batch
     int tile;    // tile index within the stream
@@ -130,7 +159,7 @@ struct Where {
 
 // Largest s with off[s] <= tile (streams with no tiles are skipped).
 __device__ __forceinline__ Where locate(const Batch& b) {
-    const int t = blockIdx.x;
+    const int t = tile_of_block(blockIdx.x, b.off[b.n], b.order);
     int lo = 0, hi = b.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

@@ -74,7 +74,8 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_get_last_jacobian", "sw_create_batch", "sw_destroy_batch", "sw_batch_last_error",
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
-           "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint"]
+           "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
+           "sw_batch_autotune"]
 
 SW_EPENDING = 1
 
@@ -125,6 +126,7 @@ def lib() -> C.CDLL:
         "sw_server_poll": (i32, [vp, C.c_uint64, i32, C.POINTER(SwFrameStats), C.POINTER(SwTicketInfo)]),
         "sw_server_counters": (i32, [vp, C.POINTER(SwServerInfo)]),
         "sw_get_footprint": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+        "sw_batch_autotune": (i32, [vp, C.POINTER(vp), i32, i32, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -261,6 +263,17 @@ class Batch:
 
     def solve(self, streams, depths, with_stats: bool = True, raise_numeric: bool = True):
         return sw_solve_batch(self.h, [s.h for s in streams], depths, with_stats, raise_numeric)
+
+    def autotune(self, streams, reps: int = 20):
+        """Pick each stage's launch variant for this batch's shape bucket; returns the 12
+        choices (bit 0: XCD-contiguous tile order, bit 1: 2 rows / nodes per wave or group)."""
+        n = len(streams)
+        hs = (C.c_void_p * n)(*[s.h.value for s in streams])
+        out = (C.c_int32 * 12)()
+        st = lib().sw_batch_autotune(self.h, hs, n, int(reps), out)
+        if st != SW_OK:
+            raise SwError(st, f"{lib().sw_status_string(st).decode()}: {lib().sw_batch_last_error(self.h).decode()}")
+        return list(out)
 
     def profile_stage(self, streams, stage: int, reps: int = 100, pcg_it: int = 0) -> float:
         """Mean microseconds per launch of one stage over these streams."""

@@ -175,3 +175,26 @@ def test_graph_replays_equal_eager_launches(swgn, scene_cache):
     for st in sts:
         st.close()
     b.close()
+
+
+def test_autotuned_tile_order_changes_no_result(swgn, scene_cache):
+    """The autotuner only changes which workgroup takes which tile and how
+    many rows or nodes a wave takes, never a reduction's shape: frames solved
+    after tuning end exactly where untuned solves end."""
+    scenes = _scenes(scene_cache, MIX[:4])
+    frames = [[s.depth for s in scenes], [s.depth for s in scenes]]
+    cfgs = [{} for _ in scenes]
+    plain = _batched(swgn, scenes, frames, cfgs)
+    sts = [stream_for(swgn, sc) for sc in scenes]
+    b = swgn.Batch()
+    res0, _ = b.solve(sts, frames[0])
+    snap = [st.node_se3() for st in sts]
+    variants = b.autotune(sts, reps=5)
+    assert len(variants) == 12 and set(variants) <= {0, 1, 2, 3}
+    for st, se3 in zip(sts, snap):       # the tuning replays leave the warp fields alone
+        assert np.array_equal(st.node_se3(), se3)
+    res1, _ = b.solve(sts, frames[1])
+    _assert_same(plain[0], plain[1], [st.node_se3() for st in sts], [[a, c] for a, c in zip(res0, res1)])
+    for st in sts:
+        st.close()
+    b.close()
