@@ -46,6 +46,7 @@ class SolverParams:
     corr_normal: float = 0.5
     edge_gate: float = 0.03
     damping: float = 1e-4
+    rigid_iters: int = 0          # rigid alignment steps before the non-rigid ones
 
 
 @dataclasses.dataclass

@@ -26,7 +26,7 @@ import numpy as np
 import scipy.linalg
 import scipy.sparse as sp
 
-from . import assoc, depth as depthmod, skin
+from . import assoc, depth as depthmod, rigid, skin
 from .quat import dq_from_rt, exp_so3, rt_to_se3, se3_to_rt
 from .terms import arap_jacobians, arap_residuals, data_jacobian, data_residuals
 from .warp import apply_blend, blend
@@ -197,8 +197,10 @@ def update_nodes(node_pos: np.ndarray, R: np.ndarray, t: np.ndarray, delta: np.n
 
 
 def gn_solve(pb: Problem, se3_init: np.ndarray, gn_iters: int, pcg_iters: Optional[int] = 10,
-             linear: str = "pcg", final_energy: bool = False, keep: Optional[List[int]] = None):
-    """Run exactly gn_iters Gauss-Newton iterations from se3_init.
+             linear: str = "pcg", final_energy: bool = False, keep: Optional[List[int]] = None,
+             rigid_iters: int = 0):
+    """Run exactly gn_iters Gauss-Newton iterations from se3_init (after
+    rigid_iters steps of rigid alignment composed into the nodes, see rigid.py).
 
     linear = "chol" solves each step exactly (dense Cholesky), "pcg" runs
     block-Jacobi PCG for pcg_iters iterations. Returns the final (Nn,12) [R|t]
@@ -206,6 +208,9 @@ def gn_solve(pb: Problem, se3_init: np.ndarray, gn_iters: int, pcg_iters: Option
     listed in `keep`, the full linearisation."""
     R, t = se3_to_rt(se3_init)
     trace: Dict = dict(e_data=[], e_reg=[], n_corr=[], pcg_resid=[], lin={}, steps=[])
+    if rigid_iters > 0:
+        Rc, tc, trace["rigid"] = rigid.rigid_align(pb, warp_surfels(pb, R, t), rigid_iters, pb.damping)
+        R, t = rigid.compose(R, t, Rc, tc)
     for it in range(gn_iters):
         lin = linearize(pb, R, t)
         trace["e_data"].append(lin["e_data"])
@@ -236,6 +241,7 @@ def oracle_solve(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
     pb = make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params)
     if se3_init is None:
         se3_init = identity_se3(node_pos.shape[0])
+    kw.setdefault("rigid_iters", getattr(params, "rigid_iters", 0))
     return gn_solve(pb, se3_init, params.gn_iters, params.pcg_iters, linear=linear, **kw)
 
 
