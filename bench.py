@@ -356,7 +356,7 @@ def main():
     stats = None
     for _ in range(reps):
         stats = tst.solve_frame(depth)
-        tot += np.array(stats["stage_us"])
+        tot += np.array(stats["stage_us"][:len(KERNELS)])
     per_frame_us = tot / reps
     G, Pi = p.gn_iters, p.pcg_iters
     launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G, G], dtype=float)
@@ -399,7 +399,7 @@ def main():
         breps = 3
         for _ in range(breps):
             res, _ = tb.solve(sts, depths)
-            btot += np.array(res[0]["stage_us"])
+            btot += np.array(res[0]["stage_us"][:len(KERNELS)])
         b_replay = replay_us(tb, sts, Pi, reps=50)
         tb.close()
         for t in sts:

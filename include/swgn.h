@@ -59,6 +59,10 @@ typedef struct sw_config {
     int32_t dot_fp64;          /* 1 = accumulate PCG dot products in fp64 (default 1) */
     int32_t debug_iter;        /* -1 = capture nothing; k = capture GN iteration k */
     int32_t stage_timing;      /* 1 = time every kernel with HIP events into stage_us */
+    int32_t rigid_iters;       /* rigid alignment steps before the non-rigid ones (Sec. 7,
+                                  as in KinectFusion): projective point-to-plane ICP of one
+                                  rigid transform applied after the warp field, then
+                                  composed into every node; 0 = none (default), <= 16 */
 } sw_config;
 
 /* Per-frame statistics, one entry per Gauss-Newton iteration (<= 16). */
@@ -73,9 +77,14 @@ typedef struct sw_frame_stats {
                                   index map, [2] correspondence + Jacobians +
                                   segment Gram matrices, [3] unused, [4] block-Jacobi +
                                   PCG start, [5] PCG products, [6] PCG updates,
-                                  [7] node update, [8] assembly of the blocks;
-                                  measured with HIP events */
+                                  [7] node update, [8] assembly of the blocks,
+                                  [9] rigid warp + index map, [10] rigid 6x6 sums,
+                                  [11] rigid solve + composition; measured with HIP
+                                  events */
     double alg_bytes;          /* algorithmic bytes moved by the frame (model) */
+    int32_t rigid_steps;       /* rigid alignment steps run */
+    float rigid_e[16];         /* point-to-plane energy at each rigid step */
+    int32_t rigid_n[16];       /* correspondences at each rigid step */
 } sw_frame_stats;
 
 /* Fill *cfg with the defaults listed in sw_config. */

@@ -157,7 +157,7 @@ sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int
         ex.tuned[key] = choice;
         ex.tune_epoch += 1;
         if (variants)
-            for (int k = 0; k < kNumStages; ++k) variants[k] = choice[k];
+            for (int k = 0; k < 12; ++k) variants[k] = choice[k];
         return SW_OK;
     });
 }

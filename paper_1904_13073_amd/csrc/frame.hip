@@ -30,6 +30,12 @@ __global__ void __launch_bounds__(256) k_depth_prep(Batch b, DepthIn in) {
     const float* __restrict__ depth = in.p[at.s];
     const int gid = at.tile * 256 + threadIdx.x;
     if (at.tile == 0 && threadIdx.x < 4) d.flags[threadIdx.x] = 0;
+    if (at.tile == 0 && threadIdx.x < 12) {
+        // the frame's rigid alignment starts from the identity
+        const float e = (threadIdx.x == 0 || threadIdx.x == 4 || threadIdx.x == 8) ? 1.f : 0.f;
+        d.rig[threadIdx.x] = e;
+        d.rig64[threadIdx.x] = (double)e;
+    }
     if (gid < d.nn) {
         d.rq_bak[gid] = d.rq[gid];
         d.tt_bak[gid] = d.tt[gid];
@@ -343,6 +349,256 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rigid alignment before the non-rigid steps (Sec. 7: a rigid alignment as in
+// KinectFusion precedes the non-rigid estimation): projective point-to-plane
+// ICP of one transform T = (R_c, t_c) applied after the warp field.
+//   rigid_warp   y_i = R_c v'_i + t_c into the index map
+//   rigid_sys    correspondence on y_i, r_i = N^T (y_i - V), J_i = (y_i x N, N);
+//                per tile the sums of J J^T (upper 21), J r, r^2 and the count
+//   rigid_solve  (sum J J^T + mu I) xi = -sum J r in FP64 (one workgroup per
+//                stream, fixed summation order), T <- (Exp(w) R_c, Exp(w) t_c + tau);
+//                every workgroup also resets the index map
+//   rigid_compose  T_k <- T o T_k for every node
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 rigid_apply(const float* __restrict__ T, float3 v) {
+    return make_float3(((T[0] * v.x + T[1] * v.y) + T[2] * v.z) + T[9],
+                       ((T[3] * v.x + T[4] * v.y) + T[5] * v.z) + T[10],
+                       ((T[6] * v.x + T[7] * v.y) + T[8] * v.z) + T[11]);
+}
+__device__ __forceinline__ float3 rigid_rotate(const float* __restrict__ T, float3 v) {
+    return make_float3((T[0] * v.x + T[1] * v.y) + T[2] * v.z, (T[3] * v.x + T[4] * v.y) + T[5] * v.z,
+                       (T[6] * v.x + T[7] * v.y) + T[8] * v.z);
+}
+
+__global__ void __launch_bounds__(kWarpBlock) k_rigid_warp(Batch b) {
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const int i = at.tile * kWarpBlock + threadIdx.x;
+    if (i >= d.ns) return;
+    float T[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) T[q] = d.rig[q];
+    const float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
+    const Warp wp = warp_surfel(d.idx[i], d.w[i], v, make_float3(0.f, 0.f, 0.f), d.dq);
+    if (!wp.ok) return;
+    const float3 y = rigid_apply(T, wp.v);
+    int ux, uy;
+    if (!project(d.cam, y, ux, uy)) return;
+    atomicMin(&d.zbuf[uy * d.cam.W + ux], zkey(y.z, d.orig[i]));
+}
+
+__global__ void __launch_bounds__(256) k_rigid_sys(Batch b) {
+    __shared__ double ws[4][kRigidSums];
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    float T[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) T[q] = d.rig[q];
+    double acc[kRigidSums];
+#pragma unroll
+    for (int q = 0; q < kRigidSums; ++q) acc[q] = 0.0;
+    for (int u = 0; u < kRigidSurfels / 256; ++u) {
+        const int i = at.tile * kRigidSurfels + u * 256 + threadIdx.x;
+        if (i >= d.ns) break;
+        const float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
+        const float3 n = make_float3(d.nx[i], d.ny[i], d.nz[i]);
+        const Warp wp = warp_surfel(d.idx[i], d.w[i], v, n, d.dq);
+        if (!wp.ok) continue;
+        const float3 y = rigid_apply(T, wp.v);
+        const float3 ny = rigid_rotate(T, wp.n);
+        int ux, uy;
+        if (!project(d.cam, y, ux, uy)) continue;
+        const int pix = uy * d.cam.W + ux;
+        if (d.zbuf[pix] != zkey(y.z, d.orig[i])) continue;
+        const float4 nm = d.nmap[pix];
+        if (!(nm.w > 0.f)) continue;
+        const float3 V = backproject(d.cam, ux, uy, nm.w);
+        const float3 dv = sub3(y, V);
+        const float d2 = (dv.x * dv.x + dv.y * dv.y) + dv.z * dv.z;
+        const float3 N = make_float3(nm.x, nm.y, nm.z);
+        if (!(d2 < d.dist2 && dot3(ny, N) > d.cosn)) continue;
+        const double r = (double)dot3(N, dv);
+        const float3 c = cross3(y, N);
+        const double J[6] = {c.x, c.y, c.z, N.x, N.y, N.z};
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int bb = a; bb < 6; ++bb) acc[q++] += J[a] * J[bb];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) acc[21 + a] += J[a] * r;
+        acc[27] += r * r;
+        acc[28] += 1.0;
+    }
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kRigidSums; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) ws[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRigidSums) {
+        double t = 0.0;
+        for (int w = 0; w < 4; ++w) t += ws[w][threadIdx.x];
+        d.rig_part[(size_t)at.tile * kRigidSums + threadIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kNodeBlock) k_rigid_solve(Batch b) {
+    __shared__ double part[8][kRigidSums];
+    __shared__ double tot[kRigidSums];
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const int gid = at.tile * kNodeBlock + threadIdx.x;
+    if (gid < d.npx) d.zbuf[gid] = ~0ull;     // index map of the next step
+    if (at.tile != 0) return;
+    // sums over tiles: quantity q, tiles congruent to l mod 8, then the 8 in order
+    const int ntiles = cdiv(d.ns, kRigidSurfels);
+    if (threadIdx.x < 8 * kRigidSums) {
+        const int q = threadIdx.x % kRigidSums, l = threadIdx.x / kRigidSums;
+        double v = 0.0;
+        for (int t = l; t < ntiles; t += 8) v += d.rig_part[(size_t)t * kRigidSums + q];
+        part[l][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRigidSums) {
+        double v = 0.0;
+        for (int l = 0; l < 8; ++l) v += part[l][threadIdx.x];
+        tot[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int step = b.it[at.s];
+    double A[6][6], g[6];
+    int q = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int c = a; c < 6; ++c) {
+            A[a][c] = tot[q];
+            A[c][a] = tot[q];
+            ++q;
+        }
+    for (int a = 0; a < 6; ++a) {
+        A[a][a] += (double)d.mu;
+        g[a] = tot[21 + a];
+    }
+    d.rig_stats[step].e = tot[27];
+    d.rig_stats[step].n = (int)tot[28];
+    // Cholesky A = L L^T, then xi = -A^-1 g
+    double L[6][6];
+    bool ok = true;
+    for (int a = 0; a < 6; ++a) {
+        for (int c = 0; c <= a; ++c) {
+            double s = A[a][c];
+            for (int k = 0; k < c; ++k) s -= L[a][k] * L[c][k];
+            if (a == c) {
+                ok = ok && (s > 0.0);
+                L[a][a] = sqrt(s > 0.0 ? s : 1.0);
+            } else {
+                L[a][c] = s / L[c][c];
+            }
+        }
+    }
+    double y[6], xi[6];
+    for (int a = 0; a < 6; ++a) {
+        double s = -g[a];
+        for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
+        y[a] = s / L[a][a];
+    }
+    for (int a = 5; a >= 0; --a) {
+        double s = y[a];
+        for (int k = a + 1; k < 6; ++k) s -= L[k][a] * xi[k];
+        xi[a] = s / L[a][a];
+    }
+    for (int a = 0; a < 6; ++a) ok = ok && (fabs(xi[a]) < INFINITY);
+    if (!ok) {
+        atomicOr(d.flags, 8);
+        return;
+    }
+    // Exp(w) by Rodrigues, T <- (E R_c, E t_c + tau)
+    const double th = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+    double E[9];
+    {
+        const double kx = xi[0], ky = xi[1], kz = xi[2];
+        double s1, c1;
+        if (th < 1e-12) {
+            s1 = 1.0;            // sin(th) / th
+            c1 = 0.5;            // (1 - cos(th)) / th^2
+        } else {
+            s1 = sin(th) / th;
+            c1 = (1.0 - cos(th)) / (th * th);
+        }
+        E[0] = 1.0 - c1 * (ky * ky + kz * kz); E[1] = c1 * kx * ky - s1 * kz;  E[2] = c1 * kx * kz + s1 * ky;
+        E[3] = c1 * kx * ky + s1 * kz;  E[4] = 1.0 - c1 * (kx * kx + kz * kz); E[5] = c1 * ky * kz - s1 * kx;
+        E[6] = c1 * kx * kz - s1 * ky;  E[7] = c1 * ky * kz + s1 * kx;  E[8] = 1.0 - c1 * (kx * kx + ky * ky);
+    }
+    double Rn[9], tn[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            Rn[3 * r + c] = E[3 * r] * d.rig64[c] + E[3 * r + 1] * d.rig64[3 + c] + E[3 * r + 2] * d.rig64[6 + c];
+        tn[r] = E[3 * r] * d.rig64[9] + E[3 * r + 1] * d.rig64[10] + E[3 * r + 2] * d.rig64[11] + xi[3 + r];
+    }
+    for (int k = 0; k < 9; ++k) {
+        d.rig64[k] = Rn[k];
+        d.rig[k] = (float)Rn[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        d.rig64[9 + k] = tn[k];
+        d.rig[9 + k] = (float)tn[k];
+    }
+}
+
+// Unit quaternion (w >= 0) of a rotation matrix, FP64.
+__device__ __forceinline__ void quat_of(const double* m, double& qw, double& qx, double& qy, double& qz) {
+    const double R00 = m[0], R01 = m[1], R02 = m[2], R10 = m[3], R11 = m[4], R12 = m[5], R20 = m[6],
+                 R21 = m[7], R22 = m[8];
+    const double tr = R00 + R11 + R22;
+    if (tr >= R00 && tr >= R11 && tr >= R22) {
+        const double s = 2.0 * sqrt(fmax(1.0 + tr, 0.0));
+        qw = 0.25 * s; qx = (R21 - R12) / s; qy = (R02 - R20) / s; qz = (R10 - R01) / s;
+    } else if (R00 >= R11 && R00 >= R22) {
+        const double s = 2.0 * sqrt(fmax(1.0 + R00 - R11 - R22, 0.0));
+        qw = (R21 - R12) / s; qx = 0.25 * s; qy = (R01 + R10) / s; qz = (R02 + R20) / s;
+    } else if (R11 >= R22) {
+        const double s = 2.0 * sqrt(fmax(1.0 - R00 + R11 - R22, 0.0));
+        qw = (R02 - R20) / s; qx = (R01 + R10) / s; qy = 0.25 * s; qz = (R12 + R21) / s;
+    } else {
+        const double s = 2.0 * sqrt(fmax(1.0 - R00 - R11 + R22, 0.0));
+        qw = (R10 - R01) / s; qx = (R02 + R20) / s; qy = (R12 + R21) / s; qz = 0.25 * s;
+    }
+    const double nq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double sg = qw < 0 ? -1.0 : 1.0;
+    qw *= sg / nq; qx *= sg / nq; qy *= sg / nq; qz *= sg / nq;
+}
+
+__global__ void __launch_bounds__(kNodeBlock) k_rigid_compose(Batch b) {
+    const Where at = locate(b);
+    const FrameDesc d = *b.d[at.s];
+    const int k = at.tile * kNodeBlock + threadIdx.x;
+    if (k >= d.nn) return;
+    double cw, cx, cy, cz;
+    quat_of(d.rig64, cw, cx, cy, cz);
+    const float4 q = d.rq[k];
+    const double kw = q.x, kx = q.y, ky = q.z, kz = q.w;
+    // q_c (x) q_k, renormalised, w >= 0
+    double rw = cw * kw - cx * kx - cy * ky - cz * kz;
+    double rx = cw * kx + cx * kw + cy * kz - cz * ky;
+    double ry = cw * ky - cx * kz + cy * kw + cz * kx;
+    double rz = cw * kz + cx * ky - cy * kx + cz * kw;
+    const double nr = sqrt(rw * rw + rx * rx + ry * ry + rz * rz) * (rw < 0 ? -1.0 : 1.0);
+    rw /= nr; rx /= nr; ry /= nr; rz /= nr;
+    const float4 t4 = d.tt[k];
+    const double* m = d.rig64;
+    const double tx = m[0] * t4.x + m[1] * t4.y + m[2] * t4.z + m[9];
+    const double ty = m[3] * t4.x + m[4] * t4.y + m[5] * t4.z + m[10];
+    const double tz = m[6] * t4.x + m[7] * t4.y + m[8] * t4.z + m[11];
+    const Q4 r = Q4{(float)rw, (float)rx, (float)ry, (float)rz};
+    const float3 t = make_float3((float)tx, (float)ty, (float)tz);
+    d.rq[k] = f4(r);
+    d.tt[k] = make_float4(t.x, t.y, t.z, 0.f);
+    node_tables(d.pref[k], r, t, d.dq, d.cl, k);
+}
+
 // Node state from [R | t] (FP64 conversion, w >= 0) and its tables.
 __global__ void k_nodes_from_se3(int nn, const float* __restrict__ se3, const float4* __restrict__ pref,
                                  float4* __restrict__ rq, float4* __restrict__ tt, float4* __restrict__ dq,
@@ -422,6 +678,10 @@ void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStre
         case kStDepth: hipLaunchKernelGGL(k_depth_prep, dim3(grid), dim3(256), 0, st, b, *depth); break;
         case kStWarp: hipLaunchKernelGGL(k_warp_zbuf, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
         case kStCorr: hipLaunchKernelGGL(k_corr_gram, dim3(grid), dim3(kCorrBlock), 0, st, b); break;
+        case kStRigidWarp: hipLaunchKernelGGL(k_rigid_warp, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
+        case kStRigidSys: hipLaunchKernelGGL(k_rigid_sys, dim3(grid), dim3(256), 0, st, b); break;
+        case kStRigidSolve: hipLaunchKernelGGL(k_rigid_solve, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
+        case kStRigidCompose: hipLaunchKernelGGL(k_rigid_compose, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
         default: break;
     }
 }

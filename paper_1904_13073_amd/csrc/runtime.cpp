@@ -145,6 +145,10 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.part_rho, 8 * nsol);
     take(h.part_rr, 8 * nsol);
     take(h.part_pq, 8 * nspm);
+    take(h.rig, 12 * 4);
+    take(h.rig64, 12 * 8);
+    take(h.rig_part, 8 * (size_t)kRigidSums * (size_t)cdiv(h.ns, kRigidSurfels));
+    take(h.rig_stats, sizeof(RigidStats) * kMaxIters);
     return off;
 }
 
@@ -183,6 +187,7 @@ sw_status check_config(const sw_config* c, std::string& why) {
     if (c->dot_fp64 != 1) { why = "dot_fp64: PCG dot products accumulate in fp64 (1)"; return SW_EINVAL; }
     if (c->debug_iter < -1 || c->debug_iter >= kMaxIters) { why = "debug_iter out of range"; return SW_EINVAL; }
     if (c->stage_timing != 0 && c->stage_timing != 1) { why = "stage_timing must be 0 or 1"; return SW_EINVAL; }
+    if (c->rigid_iters < 0 || c->rigid_iters > kMaxIters) { why = "rigid_iters must be in [0, 16]"; return SW_EINVAL; }
     return SW_OK;
 }
 
@@ -224,6 +229,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.pcg_iters = s->cfg.pcg_iters;
     h.debug_iter = s->cfg.debug_iter;
     h.jac_dtype = s->cfg.jac_dtype;
+    h.rigid_iters = s->cfg.rigid_iters;
     h.edge_gate = s->cfg.edge_gate;
     h.dist2 = s->cfg.corr_dist * s->cfg.corr_dist;
     h.cosn = s->cfg.corr_normal;
@@ -465,7 +471,10 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
         ev_stage.push_back(stage);
     }
     switch (stage) {
-        case kStDepth: case kStWarp: case kStCorr: launch_frame_stage(stage, b, depth, ex.st); break;
+        case kStDepth: case kStWarp: case kStCorr:
+        case kStRigidWarp: case kStRigidSys: case kStRigidSolve: case kStRigidCompose:
+            launch_frame_stage(stage, b, depth, ex.st);
+            break;
         case kStAsmSeg: case kStAsmFold: launch_asm_stage(stage, b, ex.st); break;
         default: launch_solve_stage(stage, b, ex.stats_dev, ex.st); break;
     }
@@ -492,6 +501,26 @@ void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* 
     }
     std::vector<int> its(n, 0);
     run_stage(ex, kStDepth, ss, its, 0, &din, timing, ev);
+}
+
+// The rigid alignment of every stream whose config asks for it: rigid_iters
+// steps (warp into the index map, 6x6 sums, solve), then T composed into the
+// nodes. Runs after the depth preprocessing, before the first Gauss-Newton
+// iteration.
+void enqueue_rigid(Executor& ex, const std::vector<sw_stream>& ss, bool timing, std::vector<int>& ev) {
+    const int n = (int)ss.size();
+    int rmax = 0;
+    for (sw_stream s : ss) rmax = std::max(rmax, s->cfg.rigid_iters);
+    if (rmax == 0) return;
+    std::vector<int> its(n, -1);
+    for (int r = 0; r < rmax; ++r) {
+        for (int i = 0; i < n; ++i) its[i] = r < ss[i]->cfg.rigid_iters ? r : -1;
+        run_stage(ex, kStRigidWarp, ss, its, 0, nullptr, timing, ev);
+        run_stage(ex, kStRigidSys, ss, its, 0, nullptr, timing, ev);
+        run_stage(ex, kStRigidSolve, ss, its, 0, nullptr, timing, ev);
+    }
+    for (int i = 0; i < n; ++i) its[i] = ss[i]->cfg.rigid_iters > 0 ? 0 : -1;
+    run_stage(ex, kStRigidCompose, ss, its, 0, nullptr, timing, ev);
 }
 
 // One Gauss-Newton iteration for every stream with its[i] >= 0 (its[i] = the
@@ -567,13 +596,17 @@ sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const fl
         const char* slot = static_cast<const char*>(ex.stats_host) + (size_t)kStatsOutBytes * i;
         const IterStats* is = reinterpret_cast<const IterStats*>(slot);
         const int* flags = reinterpret_cast<const int*>(slot + sizeof(IterStats) * kMaxIters);
+        const RigidStats* rs = reinterpret_cast<const RigidStats*>(slot + sizeof(IterStats) * kMaxIters + 16);
         const int G = s->cfg.gn_iters;
+        const int Rg = s->cfg.rigid_iters;
         int64_t ncorr_total = 0;
         bool bad = (flags[0] | flags[1] | flags[2] | flags[3]) != 0;
         for (int it = 0; it < G; ++it) {
             ncorr_total += is[it].n_corr;
             if (!std::isfinite(is[it].e_data) || !std::isfinite(is[it].e_reg)) bad = true;
         }
+        for (int r = 0; r < Rg; ++r)
+            if (!std::isfinite(rs[r].e)) bad = true;
         if (stats) {
             sw_frame_stats& o = stats[i];
             std::memset(&o, 0, sizeof(o));
@@ -584,8 +617,13 @@ sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const fl
                 o.n_corr[it] = is[it].n_corr;
                 o.pcg_resid[it] = (float)is[it].pcg_resid;
             }
+            o.rigid_steps = Rg;
+            for (int r = 0; r < Rg; ++r) {
+                o.rigid_e[r] = (float)rs[r].e;
+                o.rigid_n[r] = rs[r].n;
+            }
             if (stage_us)
-                for (int k = 0; k < kNumStages && k < 12; ++k) o.stage_us[k] = stage_us[k];
+                for (int k = 0; k < 12; ++k) o.stage_us[k] = stage_us[k];
             o.alg_bytes = model_bytes(h, G, ncorr_total);
         }
         status[i] = SW_OK;
@@ -593,7 +631,7 @@ sw_status finish_frames(Executor& ex, const std::vector<sw_stream>& ss, const fl
             SWGN_HIP(hipMemcpyAsync(h.rq, h.rq_bak, sizeof(float4) * h.nn, hipMemcpyDeviceToDevice, st));
             SWGN_HIP(hipMemcpyAsync(h.tt, h.tt_bak, sizeof(float4) * h.nn, hipMemcpyDeviceToDevice, st));
             launch_tables_from_state(h.nn, h.pref, h.rq, h.tt, h.dq, h.cl, st);
-            s->err = "non-finite energy, node update or non-positive-definite diagonal block;"
+            s->err = "non-finite energy, node update, non-positive-definite diagonal block or rigid system;"
                      " node transforms restored";
             status[i] = SW_ENUMERIC;
             rc = SW_ENUMERIC;
@@ -619,6 +657,7 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
         any_capture |= ss[i]->cfg.debug_iter >= 0 && ss[i]->cfg.debug_iter < ss[i]->cfg.gn_iters;
     }
     enqueue_depth(ex, ss, depths, on_device, timing, ev);
+    enqueue_rigid(ex, ss, timing, ev);
     std::vector<char> captured(n, 0);
     std::vector<int> its(n, 0);
     auto body = [&]() {
@@ -659,14 +698,14 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
         body();
     }
     SWGN_HIP(hipGetLastError());
-    float stage_us[kNumStages] = {0.f};
+    float stage_us[12] = {0.f};
     if (timing) {
         SWGN_HIP(hipStreamSynchronize(ex.st));
         // events come in (start of a stage, end) pairs
         for (size_t a = 0; a + 1 < ev.size(); a += 2) {
             float ms = 0.f;
             SWGN_HIP(hipEventElapsedTime(&ms, ex.events[a], ex.events[a + 1]));
-            stage_us[ev[a]] += 1000.f * ms;
+            stage_us[stage_slot(ev[a])] += 1000.f * ms;
         }
     }
     const sw_status rc = finish_frames(ex, ss, timing ? stage_us : nullptr, stats, status);
@@ -698,6 +737,7 @@ void sw_config_default(sw_config* c) {
     c->dot_fp64 = 1;
     c->debug_iter = -1;
     c->stage_timing = 0;
+    c->rigid_iters = 0;
 }
 
 const char* sw_status_string(sw_status st) {

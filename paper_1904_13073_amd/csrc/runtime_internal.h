@@ -132,6 +132,7 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
                const DepthIn* depth, bool timing, std::vector<int>& ev_stage);
 void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths, int32_t on_device,
                    bool timing, std::vector<int>& ev);
+void enqueue_rigid(Executor& ex, const std::vector<sw_stream>& ss, bool timing, std::vector<int>& ev);
 void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std::vector<int>& its, bool timing,
                        std::vector<int>& ev, std::vector<char>& captured);
 void enqueue_collect(Executor& ex, const std::vector<sw_stream>& ss);

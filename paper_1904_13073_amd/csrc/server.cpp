@@ -206,6 +206,7 @@ void sw_server_s::run() {
                 }
                 if (!dev_s.empty()) enqueue_depth(exec, dev_s, dev_d.data(), 1, false, ev);
                 if (!host_s.empty()) enqueue_depth(exec, host_s, host_d.data(), 0, false, ev);
+                enqueue_rigid(exec, fresh, false, ev);
             }
             // one Gauss-Newton iteration of every frame in flight
             ss.clear();

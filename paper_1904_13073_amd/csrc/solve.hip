@@ -352,8 +352,11 @@ __global__ void __launch_bounds__(64) k_stats_out(Batch b, char* __restrict__ ou
     int* dst = reinterpret_cast<int*>(out + (size_t)at.s * kStatsOutBytes);
     const int* src = reinterpret_cast<const int*>(a.stats);
     constexpr int nw = (int)(sizeof(IterStats) * kMaxIters / 4);
+    constexpr int nr = (int)(sizeof(RigidStats) * kMaxIters / 4);
     for (int t = threadIdx.x; t < nw; t += 64) dst[t] = src[t];
     if (threadIdx.x < 4) dst[nw + threadIdx.x] = a.flags[threadIdx.x];
+    const int* rsrc = reinterpret_cast<const int*>(a.rig_stats);
+    for (int t = threadIdx.x; t < nr; t += 64) dst[nw + 4 + t] = rsrc[t];
 }
 
 }  // namespace

@@ -34,9 +34,20 @@ constexpr int kSpmvWaves = 4;         // product workgroup: 4 waves of 1 or 2 bl
 constexpr int kSolvePart = 32;
 constexpr int kSpmvPart = 4;
 constexpr int kNodeBlock = 256;
+constexpr int kRigidSurfels = 1024;   // surfels per rigid-system workgroup (4 per thread)
 
 constexpr int kSegLen = 128;          // surfels per segment at most (one node set)
 constexpr int kSegSlots = 400;        // per segment: 10 upper 6x6 blocks, J^T r (24), r^T r, pad
+
+// Per-step statistics of the rigid alignment.
+struct RigidStats {
+    double e;                     // sum of squared point-to-plane residuals
+    int n, pad;                   // correspondences
+};
+
+// Sums per tile of the rigid alignment: 21 entries of the upper 6x6 J^T J,
+// 6 of J^T r, r^T r and the correspondence count.
+constexpr int kRigidSums = 29;
 
 struct FrameDesc {
     // shapes
@@ -44,6 +55,7 @@ struct FrameDesc {
     int npack;                    // packs: consecutive whole segments, at most kCorrBlock surfels
     int pcg_iters, debug_iter;
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
+    int rigid_iters;              // rigid alignment steps before the non-rigid ones
     Cam cam;
     float edge_gate, dist2, cosn, lambda, mu, pad2;
     // resident: surfels sorted by node set; orig = caller's index
@@ -82,13 +94,22 @@ struct FrameDesc {
     int* part_n;
     float *x, *r, *z, *q, *p0, *p1;
     double *sc, *part_rho, *part_rr, *part_pq;
+    // rigid alignment: the transform (R row-major, t) as used by the warp
+    // kernels and in FP64 for the updates, per-tile partials of the 6x6
+    // system, per-step statistics
+    float* rig;                   // [12]
+    double* rig64;                // [12]
+    double* rig_part;             // [tiles][kRigidSums]
+    RigidStats* rig_stats;        // [kMaxIters]
 };
 
 // Tiles (workgroups) of each per-frame stage for one stream.
 enum Stage {
     kStDepth = 0, kStWarp, kStCorr, kStAsmSeg, kStPcgInit, kStSpmv, kStUpdate, kStNodeUpdate, kStAsmFold,
-    kStStatsOut, kNumStages
+    kStRigidWarp, kStRigidSys, kStRigidSolve, kStRigidCompose, kStStatsOut, kNumStages
 };
+// timing slot (sw_frame_stats.stage_us) of each stage
+inline int stage_slot(int stage) { return stage < kStRigidCompose ? stage : 11; }
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int corr_tiles(const FrameDesc& d) { return d.npack; }
@@ -116,6 +137,10 @@ inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
         case kStSpmv: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSpmvWaves : kSpmvWaves);
         case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolvePart : kSolvePart);
         case kStNodeUpdate: return cdiv(d.nn > d.npx ? d.nn : d.npx, kNodeBlock);
+        case kStRigidWarp: return cdiv(d.ns, kWarpBlock);
+        case kStRigidSys: return cdiv(d.ns, kRigidSurfels);
+        case kStRigidSolve: return cdiv(d.npx, kNodeBlock);
+        case kStRigidCompose: return cdiv(d.nn, kNodeBlock);
         case kStStatsOut: return 1;
         default: return 0;
     }
@@ -173,8 +198,8 @@ void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStre
 void launch_asm_stage(int stage, const Batch& b, hipStream_t st);
 void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t st);
 
-// Bytes per stream written by the statistics copy: kMaxIters IterStats, then
-// the failure flags.
-constexpr int kStatsOutBytes = (int)(sizeof(IterStats) * kMaxIters) + 16;
+// Bytes per stream written by the statistics copy: kMaxIters IterStats, the
+// failure flags, kMaxIters RigidStats.
+constexpr int kStatsOutBytes = (int)(sizeof(IterStats) * kMaxIters) + 16 + (int)(sizeof(RigidStats) * kMaxIters);
 
 }  // namespace swgn

@@ -26,19 +26,21 @@ class SwConfig(C.Structure):
                 ("lambda_reg", C.c_float), ("node_sigma", C.c_float), ("corr_dist", C.c_float),
                 ("corr_normal", C.c_float), ("edge_gate", C.c_float), ("damping", C.c_float),
                 ("jac_dtype", C.c_int32), ("dot_fp64", C.c_int32), ("debug_iter", C.c_int32),
-                ("stage_timing", C.c_int32)]
+                ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32)]
 
 
 class SwFrameStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("e_data", C.c_float * 16), ("e_reg", C.c_float * 16),
                 ("n_corr", C.c_int32 * 16), ("pcg_resid", C.c_float * 16),
-                ("stage_us", C.c_float * 12), ("alg_bytes", C.c_double)]
+                ("stage_us", C.c_float * 12), ("alg_bytes", C.c_double), ("rigid_steps", C.c_int32),
+                ("rigid_e", C.c_float * 16), ("rigid_n", C.c_int32 * 16)]
 
     def as_dict(self) -> dict:
-        n = self.iters
+        n, m = self.iters, self.rigid_steps
         return dict(iters=n, e_data=list(self.e_data[:n]), e_reg=list(self.e_reg[:n]),
                     n_corr=list(self.n_corr[:n]), pcg_resid=list(self.pcg_resid[:n]),
-                    stage_us=list(self.stage_us[:9]), alg_bytes=self.alg_bytes)
+                    stage_us=list(self.stage_us[:12]), alg_bytes=self.alg_bytes,
+                    rigid_e=list(self.rigid_e[:m]), rigid_n=list(self.rigid_n[:m]))
 
 
 class SwServerConfig(C.Structure):
@@ -487,7 +489,7 @@ def config_for(scene, **overrides) -> SwConfig:
                           fy=scene.cam.fy, cx=scene.cam.cx, cy=scene.cam.cy, gn_iters=p.gn_iters,
                           pcg_iters=p.pcg_iters, lambda_reg=p.lambda_reg, node_sigma=p.node_sigma,
                           corr_dist=p.corr_dist, corr_normal=p.corr_normal, edge_gate=p.edge_gate,
-                          damping=p.damping)
+                          damping=p.damping, rigid_iters=getattr(p, "rigid_iters", 0))
     for k, v in overrides.items():
         setattr(c, k, v)
     return c

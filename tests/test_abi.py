@@ -56,6 +56,7 @@ def test_defaults_and_status_strings():
     ("gn_iters", 17), ("gn_iters", -1), ("pcg_iters", 5000), ("lambda_reg", -1.0),
     ("node_sigma", 0.0), ("corr_dist", 0.0), ("corr_normal", 1.5), ("edge_gate", -0.1),
     ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
+    ("rigid_iters", 17), ("rigid_iters", -1),
 ])
 def test_create_rejects_bad_config(field, value):
     from paper_1904_13073_amd import swgn
