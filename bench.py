@@ -20,8 +20,6 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "asm_segments", "pcg_init", "pcg_spmv", "pcg_update",
            "node_update", "asm_fold"]
-SEG_LEN = 128     # surfels per segment at most (one node set)
-SEG_SLOTS = 400   # floats stored per segment
 
 
 def parse():
@@ -54,21 +52,24 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def kernel_bytes(ns, nn, nb, nseg, npx, pcg_iters):
-    """Algorithmic bytes per launch of each kernel (fp32 Jacobians): the data
-    each kernel must move at minimum, node tables counted once."""
+def kernel_bytes(ns, nn, nb, npx, lay):
+    """Algorithmic bytes per launch of each kernel (fp32): the data each kernel
+    must move at minimum, node tables counted once. `lay` = the stream's work
+    layout (segments, fold entries, Gram floats)."""
     return {
-        # depth in, normal map out, index map reset
+        # depth in, normal map out, index-map reset
         "depth_prep": 28.0 * npx,
         # per surfel: position 12, node ids 16, weights 16, index 4; atomic 8
         "warp_zbuf": 56.0 * ns + 32.0 * nn,
         # per surfel: position + normal 24, node ids 16, weights 16, index 4,
-        # index map 8, normal map 16; per segment 10 Gram sub-blocks, J^T r and
-        # r^T r out (385 floats); Jacobian rows stay on chip
-        "corr_jac": 84.0 * ns + 48.0 * nn + 1540.0 * nseg,
+        # index map 8, normal map 16, node positions 2; the segments' Gram
+        # sub-blocks, J^T r and r^T r out; Jacobian rows stay on chip
+        "corr_jac": 86.0 * ns + 48.0 * nn + 4.0 * lay["gram_floats"],
         "asm_segments": 0.0,
-        # per segment and block: entry, sub-block (and J^T r); blocks, gradient out
-        "asm_fold": 10.0 * nseg * (4.0 + 144.0) + 4 * 24.0 * nseg + 144.0 * nb + 28.0 * nn,
+        # per entry: sub-block 144 and its two offsets 8; per diagonal block its
+        # J^T r pieces (24 per entry, counted once per node); blocks out (upper
+        # and both explicit-row copies), gradient out
+        "asm_fold": 152.0 * lay["fold_entries"] + 24.0 * nn * 4 + 144.0 * (2 * nb - nn) + 144.0 * nn + 28.0 * nn,
         # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
         "pcg_init": 144.0 * nn + 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
         # upper blocks once (each is used for a row and, transposed, a column),
@@ -339,13 +340,7 @@ def main():
     elapsed = time.perf_counter() - t0
     fps = args.steps / elapsed
     _, _, nb = st.sizes()
-    idx4, _ = st.skinning()
-    srt = np.sort(idx4, axis=1).astype(np.int64)
-    key = ((srt[:, 0] * nn + srt[:, 1]) * nn + srt[:, 2]) * nn + srt[:, 3]
-    ks = np.sort(key, kind="stable")
-    nruns = int(np.count_nonzero(np.r_[True, ks[1:] != ks[:-1]]))   # node sets
-    starts = np.r_[True, ks[1:] != ks[:-1]] | (np.arange(ks.size) % SEG_LEN == 0)
-    nseg = int(np.count_nonzero(starts))                              # assembly segments
+    lay = st.layout()
     st.close()
     print(f"[bench] {args.steps} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
@@ -360,7 +355,7 @@ def main():
     per_frame_us = tot / reps
     G, Pi = p.gn_iters, p.pcg_iters
     launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G, G], dtype=float)
-    kb = kernel_bytes(ns, nn, nb, nseg, scene.cam.width * scene.cam.height, p.pcg_iters)
+    kb = kernel_bytes(ns, nn, nb, scene.cam.width * scene.cam.height, lay)
     px = swgn.Batch(hip_stream=hip_stream)
     replay = replay_us(px, [tst], Pi)
     px.close()
@@ -447,7 +442,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "640x480 depth (f=570), 3 spheres + bumpy plane, plain single stream",
-                   "surfels": ns, "nodes": nn, "blocks": nb, "node_sets": nruns, "segments": nseg, "gn_iters": p.gn_iters,
+                   "surfels": ns, "nodes": nn, "blocks": nb, "node_sets": lay["node_sets"],
+                   "segments": lay["segments"], "packs": lay["packs"], "gn_iters": p.gn_iters,
                    "pcg_iters": p.pcg_iters, "mode": "plain"},
         "latency_ms": {"p50": round(1000 * percentile(lat, 0.5), 4),
                        "p99": round(1000 * percentile(lat, 0.99), 4)},

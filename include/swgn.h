@@ -295,6 +295,18 @@ sw_status sw_get_sizes(sw_stream s, int64_t* n_surfels, int32_t* n_nodes, int32_
  * SW_ESTATE before sw_set_node_graph. */
 sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes);
 
+/* Work layout chosen at sw_set_node_graph: distinct node sets; segments (runs
+ * of surfels with at most 5 nodes in all, each summed into one Gram matrix);
+ * packs (runs of whole segments, at most 256 surfels, one workgroup each);
+ * the ELL width of the product's rows; the block fold's entries (one per
+ * node pair of a segment); the floats of all segments' Gram output. */
+typedef struct sw_layout {
+    int32_t node_sets, segments, packs, ell_width;
+    int64_t fold_entries, gram_floats;
+} sw_layout;
+
+sw_status sw_get_layout(sw_stream s, sw_layout* out);
+
 /* ---- parity and debug exports (host pointers, caller's surfel order) ---- */
 
 /* Skinning: idx4 (n_surfels x 4, nearest first) and weights w4 (n_surfels x 4). */

@@ -2,8 +2,9 @@
 //   H = sum_i J_i^T J_i + lambda sum_edges J_e^T J_e + mu I   (6x6 node-pair blocks)
 //   g = sum_i J_i^T r_i + lambda sum_edges J_e^T r_e
 // over the upper block pattern. The data term arrives as per-segment Gram
-// matrices (a segment = surfels sharing one node set; its 10 upper 6x6
-// sub-blocks and J^T r, written by the correspondence kernel); regulariser
+// matrices (a segment = a run of surfels with at most 5 nodes in all; the
+// 6x6 sub-blocks of its node pairs and J^T r, written by the correspondence
+// kernel, found through the block's entries); regulariser
 // rows (Sec. 7, E_regulation = sum_j sum_{m in N_j} |T_j p_j - T_m p_j|^2) are
 // formed here from the node state.
 //
@@ -36,11 +37,6 @@ __device__ __forceinline__ bool has_edge(const int* __restrict__ nbr, int j, int
     return e;
 }
 
-// slot of the upper sub-block (pa <= pb) among the 10 of a segment
-__device__ __forceinline__ int sub_block(int pa, int pb) {
-    const int first[4] = {0, 4, 7, 9};
-    return first[pa] + (pb - pa);
-}
 
 // One 16-lane group per block; diagonal blocks first (node order),
 // then the off-diagonal ones.
@@ -64,18 +60,16 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
     for (int t = 0; t < 6; ++t) gacc[t] = 0.f;
     const int e0 = active ? in.ent_ptr[b] : 0, e1 = active ? in.ent_ptr[b + 1] : 0;
     for (int e = e0 + g; e < e1; e += 16) {
-        const uint32_t v = in.ent[e];
-        const int seg = (int)(v >> 4), pa = (int)((v >> 2) & 3u), pb = (int)(v & 3u);
-        const float* base = in.part + (size_t)seg * kSegSlots;
-        const float4* blk = reinterpret_cast<const float4*>(base + sub_block(pa, pb) * 36);
+        const float4* blk = reinterpret_cast<const float4*>(in.part + in.ent_sub[e]);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const float4 t4 = blk[q];
             acc[4 * q] += t4.x; acc[4 * q + 1] += t4.y; acc[4 * q + 2] += t4.z; acc[4 * q + 3] += t4.w;
         }
         if (diag) {
+            const float* gp = in.part + in.ent_grad[e];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) gacc[c] += base[360 + 6 * pa + c];
+            for (int c = 0; c < 6; ++c) gacc[c] += gp[c];
         }
     }
     if (active && diag) {

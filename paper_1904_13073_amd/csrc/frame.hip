@@ -105,29 +105,26 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
 // Correspondence, residual, Jacobian and the segment Gram matrices.
 //
 // A tile is a pack of whole segments (consecutive surfels, at most 256; a
-// segment is at most 128 surfels sharing one node set). Each thread forms
-// its surfel's row [J | r | 0] (node blocks by position within the ascending
-// node set) in LDS; then each wave takes segments of the pack and sums the
-// 25 x 25 Gram matrix [J | r]^T [J | r] over the segment's surfels with the
-// 32x32x2 FP32 MFMA, the sum over surfels being the MFMA's k dimension (two
-// surfels per instruction; the A and B operands are the same register:
-// lane = component, half-wave = surfel). The Gram's 10 upper 6x6 sub-blocks,
-// J^T r and r^T r are stored per segment for the block fold. Jacobian rows
-// leave the chip only when an iteration is captured.
+// segment is a run of surfels whose nodes number at most 5 in all). Each
+// thread forms its surfel's row [J | r] in LDS: node block k at the position
+// of its node in the segment's ascending node list (pos4), r in column 30.
+// Then each wave takes segments of the pack and sums the 31 x 31 Gram matrix
+// [J | r]^T [J | r] over the segment's surfels with the 32x32x2 FP32 MFMA,
+// the sum over surfels being the MFMA's k dimension (two surfels per
+// instruction; the A and B operands are the same register: lane = component,
+// half-wave = surfel). The 6x6 sub-blocks of the node pairs that share a
+// surfel (seg_mask), J^T r and r^T r are stored for the block fold. Jacobian
+// rows leave the chip only when an iteration is captured.
 // ---------------------------------------------------------------------------
-// LDS row stride in floats: 25 entries (J, r), odd so that a row per lane is
-// conflict-free. The MFMA reads 32 columns per row; columns 25..31 run into
-// the next row (or the slack after the last one) and only feed Gram entries
-// with an index >= 25, which are discarded.
-constexpr int kRowPad = 25;
+// LDS row stride in floats: 31 entries (J at 5 node positions, r), odd so
+// that a row per lane is conflict-free. The MFMA reads 32 columns per row;
+// column 31 runs into the next row (or the slack after the last one) and
+// only feeds Gram entries with an index of 31, which are discarded.
+constexpr int kRowPad = 31;
+constexpr int kStageFloats = 288;    // per wave: the segment's output is staged in two halves
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// slot of the upper sub-block (pa <= pb) among the 10 of a segment
-__device__ __forceinline__ int sub_block(int pa, int pb) {
-    const int first[4] = {0, 4, 7, 9};
-    return first[pa] + (pb - pa);
-}
 
 // d r / d xi_k for the 4 nodes of a matched surfel: the closed form of
 // N^T dF/db(b; v) w_k s_k M(q_k, c_k). With P = N c_r, Q = N c_d, PV = P (0,v)
@@ -201,7 +198,7 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
     __shared__ float rows[kCorrBlock * kRowPad + 8];
-    __shared__ float4 stage4[kCorrBlock / kWave][kSegSlots / 4];
+    __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
@@ -247,9 +244,9 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
         }
     }
     {
-        // the row: node block k goes to position = rank of its id in the set
+        // the row: node block k at its node's position in the segment
         float* row = &rows[threadIdx.x * kRowPad];
-        const int ids[4] = {id.x, id.y, id.z, id.w};
+        const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
         const int jd = d.jac_dtype;          // uniform: one branch for the whole row
         if (jd != 0) {
 #pragma unroll
@@ -260,14 +257,23 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
                     Jt[k][c] = keep_jac(Jt[k][c], jd);
                 }
         }
+        int used = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
+            const int pos = (p4 >> (3 * k)) & 7;
+            used |= 1 << pos;
             float* o = row + pos * 6;
             o[0] = Jw[k][0]; o[1] = Jw[k][1]; o[2] = Jw[k][2];
             o[3] = Jt[k][0]; o[4] = Jt[k][1]; o[5] = Jt[k][2];
         }
-        row[24] = r;
+        // the segment's fifth node position, if the surfel does not touch it
+#pragma unroll
+        for (int pos = 0; pos < 5; ++pos)
+            if (!(used & (1 << pos))) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) row[pos * 6 + c] = 0.f;
+            }
+        row[30] = r;
         if (threadIdx.x == kCorrBlock - 1) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) rows[kCorrBlock * kRowPad + c] = 0.f;
@@ -297,27 +303,14 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
         const int nrow = min(kWave, p1 - p0 - base);
         for (int q = 0; q < kWave / 2; ++q) {
             const int rr = 2 * q + (lane >> 5), c = lane & 31;
-            if (rr < nrow) dst[rr * 32 + c] = c < 25 ? rows[(base + rr) * kRowPad + c] : 0.f;
+            if (rr < nrow) dst[rr * 32 + c] = c < 31 ? rows[(base + rr) * kRowPad + c] : 0.f;
         }
     }
     // segment Gram matrices, one wave per segment. Accumulator element t of
-    // lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4;
-    // its slot among the segment's 400 floats (-1: not stored) is fixed per lane
+    // lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4.
     const int comp = lane & 31, half = lane >> 5;
-    int slot[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int ii = (t >> 2) * 8 + half * 4 + (t & 3), j = comp;
-        int sl = -1;
-        if (ii < 24 && j < 24) {
-            const int pa = ii / 6, pb = j / 6;
-            if (pa <= pb) sl = sub_block(pa, pb) * 36 + (ii % 6) * 6 + (j % 6);
-        } else if (j == 24 && ii <= 24) {
-            sl = 360 + ii;                       // J^T r (ii < 24), r^T r (ii = 24)
-        }
-        slot[t] = sl;
-    }
     const int g0 = d.pack_seg[at.tile], g1 = d.pack_seg[at.tile + 1];
+    float* sg = reinterpret_cast<float*>(stage4[wave]);
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
         const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
         f32x16 acc;
@@ -333,19 +326,44 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
         }
-        // staged in LDS, stored as whole lines
-        float* sg = reinterpret_cast<float*>(stage4[wave]);
+        // output slot of each accumulator element: the rank of its node pair
+        // among the segment's pairs x 36 + position in the 6x6 sub-block;
+        // J^T r and r^T r after the sub-blocks
+        const uint32_t mask = d.seg_mask[seg];
+        const int npair = __builtin_popcount(mask);
+        const int size = 36 * npair + 32;
+        int slot[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-            if (slot[t] >= 0) sg[slot[t]] = acc[t];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float4* out = reinterpret_cast<float4*>(d.part + (size_t)seg * kSegSlots);
-        for (int q = lane; q < kSegSlots / 4; q += kWave) out[q] = stage4[wave][q];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int t = 0; t < 16; ++t) {
+            const int ii = (t >> 2) * 8 + half * 4 + (t & 3), j = comp;
+            int sl = -1;
+            if (ii < 30 && j < 30) {
+                const int pa = ii / 6, pb = j / 6;
+                if (pa <= pb) {
+                    const int bit = 5 * pa - (pa * (pa - 1)) / 2 + (pb - pa);
+                    if ((mask >> bit) & 1u)
+                        sl = 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (ii % 6) * 6 + (j % 6);
+                }
+            } else if (j == 30 && ii <= 30) {
+                sl = 36 * npair + ii;            // J^T r (ii < 30), r^T r (ii = 30)
+            }
+            slot[t] = sl;
+        }
+        float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
+        for (int h0 = 0; h0 < size; h0 += kStageFloats) {
+            // staged in LDS, stored as whole lines
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (slot[t] >= h0 && slot[t] < h0 + kStageFloats) sg[slot[t] - h0] = acc[t];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int n4 = min(kStageFloats, size - h0) / 4;
+            for (int q = lane; q < n4; q += kWave) out[h0 / 4 + q] = stage4[wave][q];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "runtime_internal.h"
+#include "segments.h"
 #include "swgn.h"
 #include "swgn_frame.h"
 #include "swgn_impl.h"
@@ -127,7 +128,7 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.stats, sizeof(IterStats) * kMaxIters);
     take(h.rq_bak, 16 * nn);
     take(h.tt_bak, 16 * nn);
-    take(h.part, 4 * (size_t)kSegSlots * (size_t)std::max(1, h.nseg));
+    take(h.part, 4 * (size_t)std::max<int64_t>(1, h.part_floats));
     take(h.H, 144 * (size_t)h.nb);
     take(h.Hf, 144 * nn * (size_t)h.ell_w);
     take(h.g, 24 * nn);
@@ -211,6 +212,65 @@ void publish_desc(sw_stream s) {
     SWGN_HIP(hipStreamSynchronize(s->exec.st));
 }
 
+// Segments, packs and the block fold's entries (host, once per node set).
+//
+// A segment is a run of consecutive surfels (sorted by node set), at most
+// kCorrBlock long, whose nodes together number at most 5: its Gram matrix
+// [J | r]^T [J | r] (30 Jacobian columns, node blocks by position in the
+// segment's ascending node list, r in column 30) fits one 32x32 MFMA tile.
+// It keeps the 6x6 sub-blocks of the node pairs that share a surfel (bit
+// first(pa) + pb - pa of its 15-bit mask, pa <= pb), then J^T r (30) and
+// r^T r: 36 x pairs + 32 floats from offset seg_off. A pack is a greedy run
+// of whole segments with at most kCorrBlock surfels. Each block's entries
+// list the float offsets of its sub-blocks (and, for a diagonal block, of the
+// matching J^T r piece) in segment order.
+void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int4* sidx, const int* row_ptr,
+                    const int* col_idx, Arena& G) {
+    hipStream_t st = s->exec.st;
+    const int ns = h.ns, nn = h.nn;
+    std::vector<uint64_t> hkey(ns);
+    std::vector<int32_t> hidx(4 * (size_t)ns);
+    std::vector<int> hrow(nn + 1), hcol(h.nb);
+    SWGN_HIP(hipMemcpyAsync(hkey.data(), key, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(hidx.data(), sidx, sizeof(int4) * ns, hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(hrow.data(), row_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(hcol.data(), col_idx, sizeof(int) * h.nb, hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipStreamSynchronize(st));
+    SegmentLayout L;
+    std::string why;
+    if (!segment_layout(ns, nn, h.nb, hkey.data(), hidx.data(), hrow.data(), hcol.data(), kCorrBlock, L, why))
+        throw HipFail{hipErrorInvalidValue, why};
+    const int nseg = (int)L.mask.size();
+    auto up = [&](auto* dst, const auto& v) {
+        SWGN_HIP(hipMemcpyAsync(dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice, st));
+    };
+    int* d_seg = G.alloc<int>(L.seg_start.size());
+    uint16_t* d_pos4 = G.alloc<uint16_t>(ns);
+    uint16_t* d_mask = G.alloc<uint16_t>(std::max(1, nseg));
+    uint32_t* d_off = G.alloc<uint32_t>(L.off.size());
+    int* d_ps = G.alloc<int>(L.pack_start.size());
+    int* d_pg = G.alloc<int>(L.pack_seg.size());
+    int* d_ep = G.alloc<int>(L.ent_ptr.size());
+    uint32_t* d_es = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_sub.size()));
+    uint32_t* d_eg = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_grad.size()));
+    up(d_seg, L.seg_start); up(d_pos4, L.pos4); up(d_mask, L.mask); up(d_off, L.off);
+    up(d_ps, L.pack_start); up(d_pg, L.pack_seg); up(d_ep, L.ent_ptr); up(d_es, L.ent_sub); up(d_eg, L.ent_grad);
+    SWGN_HIP(hipStreamSynchronize(st));
+    h.nseg = nseg;
+    h.npack = (int)L.pack_start.size() - 1;
+    h.part_floats = (int64_t)L.total;
+    h.seg_start = d_seg;
+    h.pos4 = d_pos4;
+    h.seg_mask = d_mask;
+    h.seg_off = d_off;
+    h.pack_start = d_ps;
+    h.pack_seg = d_pg;
+    h.ent_ptr = d_ep;
+    h.ent_sub = d_es;
+    h.ent_grad = d_eg;
+    s->nent = (int64_t)L.ent_sub.size();
+}
+
 void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_se3, int32_t on_device) {
     hipStream_t st = s->exec.st;
     s->graph_mem.release();
@@ -262,7 +322,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     launch_node_graph(nn, pref, nbr, st);
     h.nbr = nbr;
 
-    // order surfels by node set; segments = ranges of one node set, at most kSegLen long
+    // order surfels by node set
     const int npad = pow2_at_least(ns, 1024);
     uint64_t* key = tmp.alloc<uint64_t>(npad);
     uint32_t* val = tmp.alloc<uint32_t>(npad);
@@ -279,44 +339,18 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     int* flag = tmp.alloc<int>(ns + 1);
     int* fpos = tmp.alloc<int>(ns + 1);
     int* scan_tmp = tmp.alloc<int>(scan_tmp_size(std::max(10 * ns, 64 * nn) + 16));
-    launch_permute_surfels(ns, kSegLen, key, val, s->in_pos, s->in_nrm, idx_in, w_in, spx, spy, spz, snx, sny, snz,
+    launch_permute_surfels(ns, 0, key, val, s->in_pos, s->in_nrm, idx_in, w_in, spx, spy, spz, snx, sny, snz,
                            sidx, sw, sorig, flag, st);
     exclusive_scan(flag, fpos, ns, scan_tmp, st);
-    h.nseg = read_scalar(fpos + ns, st);
-    int* seg_start = G.alloc<int>(h.nseg + 1);
-    launch_run_starts(ns, flag, fpos, seg_start, st);
-    h.seg_start = seg_start;
-    {
-        // packs for the correspondence kernel: greedy runs of whole segments
-        // with at most kCorrBlock surfels
-        std::vector<int> hs(h.nseg + 1), ps, pg;
-        SWGN_HIP(hipMemcpyAsync(hs.data(), seg_start, sizeof(int) * (h.nseg + 1), hipMemcpyDeviceToHost, st));
-        SWGN_HIP(hipStreamSynchronize(st));
-        ps.push_back(0);
-        pg.push_back(0);
-        for (int g = 0; g < h.nseg; ++g) {
-            if (hs[g + 1] - ps.back() > kCorrBlock) {
-                ps.push_back(hs[g]);
-                pg.push_back(g);
-            }
-        }
-        ps.push_back(ns);
-        pg.push_back(h.nseg);
-        h.npack = (int)ps.size() - 1;
-        int* pack_start = G.alloc<int>(ps.size());
-        int* pack_seg = G.alloc<int>(pg.size());
-        SWGN_HIP(hipMemcpyAsync(pack_start, ps.data(), sizeof(int) * ps.size(), hipMemcpyHostToDevice, st));
-        SWGN_HIP(hipMemcpyAsync(pack_seg, pg.data(), sizeof(int) * pg.size(), hipMemcpyHostToDevice, st));
-        SWGN_HIP(hipStreamSynchronize(st));
-        h.pack_start = pack_start;
-        h.pack_seg = pack_seg;
-    }
+    s->nsets = read_scalar(fpos + ns, st);
+    int* set_start = tmp.alloc<int>(s->nsets + 1);      // runs of one node set
+    launch_run_starts(ns, flag, fpos, set_start, st);
 
-    // upper block pattern
+    // upper block pattern: every pair of a surfel's node set, every graph edge
     const int words = (nn + 31) / 32;
     uint32_t* bm = tmp.alloc<uint32_t>((size_t)nn * words);
     launch_fill_i32(reinterpret_cast<int*>(bm), nn * words, 0, st);
-    launch_pattern(h.nseg, key, seg_start, nn, nbr, bm, words, st);
+    launch_pattern(s->nsets, key, set_start, nn, nbr, bm, words, st);
     int* rcnt = tmp.alloc<int>(nn);
     launch_row_counts(nn, bm, words, rcnt, st);
     int* row_ptr = G.alloc<int>(nn + 1);
@@ -327,24 +361,11 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     int* blk_row = G.alloc<int>(h.nb);
     launch_row_fill(nn, bm, words, row_ptr, col_idx, blk_row, st);
     h.row_ptr = row_ptr; h.col_idx = col_idx; h.blk_row = blk_row;
-
-    // per-block segment entries
-    const int ne = 10 * h.nseg;
-    const int npad_e = pow2_at_least(ne, 1024);
-    uint64_t* ekey = tmp.alloc<uint64_t>(npad_e);
-    uint32_t* eval = tmp.alloc<uint32_t>(npad_e);
-    int* ecount = tmp.alloc<int>(h.nb);
-    launch_fill_i32(ecount, h.nb, 0, st);
-    launch_run_entries(h.nseg, npad_e, key, seg_start, row_ptr, col_idx, ekey, eval, ecount, st);
-    sort_pairs(ekey, eval, npad_e, st);
-    int* ent_ptr = G.alloc<int>(h.nb + 1);
-    int* scan_tmp_b = tmp.alloc<int>(scan_tmp_size(std::max(h.nb, ne) + 16) + 16);
-    exclusive_scan(ecount, ent_ptr, h.nb, scan_tmp_b, st);
-    uint32_t* ent = G.alloc<uint32_t>(ne);
-    launch_entries_store(ne, ekey, ent, st);
     int* offlist = G.alloc<int>(std::max(1, h.noff));
     launch_offlist(h.nb, blk_row, col_idx, offlist, st);
-    h.ent_ptr = ent_ptr; h.ent = ent; h.offlist = offlist;
+    h.offlist = offlist;
+
+    build_segments(s, h, key, sidx, row_ptr, col_idx, G);
 
     // in-edges of every node (j with the node in N_j), ascending j
     const int npad_i = pow2_at_least(8 * (int64_t)nn, 1024);
@@ -428,7 +449,7 @@ double model_bytes(const FrameDesc& h, int gn_iters, int64_t n_corr_total) {
     double per_iter = 0.0;
     per_iter += 48.0 * ns + 8.0 * ns + 8.0 * npx;                 // warp + z-buffer (+ clear)
     per_iter += 60.0 * ns + 8.0 * ns + 16.0 * ns;                  // correspondence + J (in LDS)
-    per_iter += 2.0 * kSegSlots * 4.0 * h.nseg + 144.0 * nb + 24.0 * nn;  // segment Grams + blocks
+    per_iter += 2.0 * 4.0 * (double)h.part_floats + 144.0 * nb + 24.0 * nn;  // segment Grams + blocks
     per_iter += 144.0 * nn + 288.0 * nn;                          // block-Jacobi
     per_iter += h.pcg_iters * (144.0 * nb + 7.0 * 24.0 * nn);     // PCG
     (void)n_corr_total;
@@ -882,6 +903,19 @@ sw_status sw_get_sizes(sw_stream s, int64_t* n_surfels, int32_t* n_nodes, int32_
     return SW_OK;
 }
 
+sw_status sw_get_layout(sw_stream s, sw_layout* out) {
+    if (!s || !out) return SW_EINVAL;
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
+    std::memset(out, 0, sizeof(*out));
+    out->node_sets = s->nsets;
+    out->segments = s->h.nseg;
+    out->packs = s->h.npack;
+    out->ell_width = s->h.ell_w;
+    out->fold_entries = s->nent;
+    out->gram_floats = s->h.part_floats;
+    return SW_OK;
+}
+
 sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes) {
     if (!s) return SW_EINVAL;
     if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
@@ -987,20 +1021,19 @@ sw_status sw_get_last_jacobian(sw_stream s, float* r, float* J) {
         hipStream_t st = s->exec.st;
         const size_t ns = (size_t)s->ns, P = (size_t)s->h.pitch;
         std::vector<float> hJ(32 * P);
-        std::vector<int4> idx(ns);
+        std::vector<uint16_t> pos4(ns);
         std::vector<int> orig(ns);
         SWGN_HIP(hipMemcpyAsync(hJ.data(), s->dbg_J, sizeof(float) * 32 * P, hipMemcpyDeviceToHost, st));
-        SWGN_HIP(hipMemcpyAsync(idx.data(), s->h.idx, sizeof(int4) * ns, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(pos4.data(), s->h.pos4, sizeof(uint16_t) * ns, hipMemcpyDeviceToHost, st));
         SWGN_HIP(hipMemcpyAsync(orig.data(), s->h.orig, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
         SWGN_HIP(hipStreamSynchronize(st));
         for (size_t i = 0; i < ns; ++i) {
             const size_t o = (size_t)orig[i];
             const float* row = hJ.data() + 32 * i;
-            if (r) r[o] = row[24];
+            if (r) r[o] = row[30];
             if (J) {
-                const int ids[4] = {idx[i].x, idx[i].y, idx[i].z, idx[i].w};
                 for (int k = 0; k < 4; ++k) {
-                    const int pos = (ids[0] < ids[k]) + (ids[1] < ids[k]) + (ids[2] < ids[k]) + (ids[3] < ids[k]);
+                    const int pos = (pos4[i] >> (3 * k)) & 7;
                     for (int c = 0; c < 6; ++c) J[24 * o + 6 * k + c] = row[pos * 6 + c];
                 }
             }

@@ -115,6 +115,8 @@ struct sw_stream_s {
     swgn::FrameDesc* h_pinned = nullptr;
     swgn::FrameDesc* d_desc = nullptr;
     size_t ws_bytes = 0;
+    int nsets = 0;                        // distinct node sets
+    int64_t nent = 0;                     // block-fold entries
 
     // captured iteration (allocated only when the config asks for a capture)
     int* dbg_index = nullptr;

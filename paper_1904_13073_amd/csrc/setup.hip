@@ -270,8 +270,8 @@ __global__ void k_permute_surfels(int ns, int seg_len, const uint64_t* __restric
     oidx[i] = iidx[o];
     ow[i] = iw[o];
     orig[i] = o;
-    // segment starts: a new node set, or every seg_len-th surfel
-    flag[i] = (i == 0 || key[i] != key[i - 1] || (i % seg_len) == 0) ? 1 : 0;
+    // run starts: a new node set (or, with seg_len > 0, every seg_len-th surfel)
+    flag[i] = (i == 0 || key[i] != key[i - 1] || (seg_len > 0 && (i % seg_len) == 0)) ? 1 : 0;
 }
 
 __global__ void k_run_starts(int ns, const int* __restrict__ flag, const int* __restrict__ pos,

@@ -36,8 +36,6 @@ constexpr int kSpmvPart = 4;
 constexpr int kNodeBlock = 256;
 constexpr int kRigidSurfels = 1024;   // surfels per rigid-system workgroup (4 per thread)
 
-constexpr int kSegLen = 128;          // surfels per segment at most (one node set)
-constexpr int kSegSlots = 400;        // per segment: 10 upper 6x6 blocks, J^T r (24), r^T r, pad
 
 // Per-step statistics of the rigid alignment.
 struct RigidStats {
@@ -53,6 +51,7 @@ struct FrameDesc {
     // shapes
     int ns, nn, nb, noff, nseg, pitch, npx, ell_w;
     int npack;                    // packs: consecutive whole segments, at most kCorrBlock surfels
+    int64_t part_floats;          // floats of all segments' Gram sub-blocks
     int pcg_iters, debug_iter;
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
     int rigid_iters;              // rigid alignment steps before the non-rigid ones
@@ -70,7 +69,10 @@ struct FrameDesc {
     // resident: upper block pattern and the assembly / product work lists
     const int *row_ptr, *col_idx, *blk_row, *offlist, *seg_start, *ent_ptr;
     const int *pack_start, *pack_seg;   // [npack + 1] first surfel / first segment of each pack
-    const uint32_t* ent;
+    const uint16_t* pos4;         // [ns] positions (3 bits each) of a surfel's 4 nodes in its segment
+    const uint16_t* seg_mask;     // [nseg] node pairs of the segment that share a surfel
+    const uint32_t* seg_off;      // [nseg + 1] float offset of each segment's Gram sub-blocks
+    const uint32_t *ent_sub, *ent_grad;   // per entry: float offset of the sub-block / J^T r piece
     const int *in_ptr, *in_list;
     const uint32_t* ell_blk;      // [nn][ell_w] upper block id (bit 31: used transposed), ~0 = padding
     const int* ell_col;           // [nn][ell_w] column node
@@ -78,7 +80,7 @@ struct FrameDesc {
     // resident: capture of one iteration (null unless requested)
     int* dbg_corr;
     float* dbg_live;
-    float* J;                     // [pitch][32]: 24 Jacobian entries, r, zero padding
+    float* J;                     // [pitch][32]: 30 Jacobian entries (5 node positions), r, zero
     // workspace of a frame in flight
     float* depth;                 // copy of a host depth image
     float4* nmap;                 // (normal, depth) per pixel
@@ -86,7 +88,7 @@ struct FrameDesc {
     int* flags;                   // [4] failure bits of the frame
     IterStats* stats;             // [kMaxIters]
     float4 *rq_bak, *tt_bak;      // node state at the start of the frame
-    float* part;                  // [nseg][kSegSlots] segment Gram sub-blocks
+    float* part;                  // [part_floats] segment Gram sub-blocks, J^T r, r^T r
     float *H, *g, *ereg;          // H: upper blocks (the diagonal always, all when captured)
     float* Hf;                    // [nn][ell_w][36] full rows of J^T J + mu I, transposes written out
     double* Minv;                 // [nn][36] block-Jacobi inverses

@@ -61,6 +61,11 @@ class SwServerInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class SwLayout(C.Structure):
+    _fields_ = [("node_sets", C.c_int32), ("segments", C.c_int32), ("packs", C.c_int32),
+                ("ell_width", C.c_int32), ("fold_entries", C.c_int64), ("gram_floats", C.c_int64)]
+
+
 class SwError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -77,7 +82,7 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
            "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
-           "sw_batch_autotune"]
+           "sw_batch_autotune", "sw_get_layout"]
 
 SW_EPENDING = 1
 
@@ -129,6 +134,7 @@ def lib() -> C.CDLL:
         "sw_server_counters": (i32, [vp, C.POINTER(SwServerInfo)]),
         "sw_get_footprint": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "sw_batch_autotune": (i32, [vp, C.POINTER(vp), i32, i32, C.POINTER(i32)]),
+        "sw_get_layout": (i32, [vp, C.POINTER(SwLayout)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -458,6 +464,11 @@ class Stream:
 
     def sizes(self):
         return sw_get_sizes(self.h)
+
+    def layout(self) -> dict:
+        out = SwLayout()
+        _check(self.h, lib().sw_get_layout(self.h, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in out._fields_}
 
     def footprint(self):
         """(resident bytes, workspace bytes of one frame in flight)."""
