@@ -18,8 +18,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "asm_segments", "pcg_init", "pcg_spmv", "pcg_update",
+# stage_us slots 0..8 (slot 3 holds the fused PCG steps)
+KERNELS = ["depth_prep", "warp_zbuf", "corr_jac", "pcg_step", "pcg_init", "pcg_spmv", "pcg_update",
            "node_update", "asm_fold"]
+STAGE_ID = {k: i for i, k in enumerate(KERNELS)}
+STAGE_ID["pcg_step"] = 13
 
 
 def parse():
@@ -65,7 +68,10 @@ def kernel_bytes(ns, nn, nb, npx, lay):
         # index map 8, normal map 16, node positions 2; the segments' Gram
         # sub-blocks, J^T r and r^T r out; Jacobian rows stay on chip
         "corr_jac": 86.0 * ns + 48.0 * nn + 4.0 * lay["gram_floats"],
-        "asm_segments": 0.0,
+        # fused PCG step: the finish of one iteration for every node and the
+        # products of the next (blocks once; per node the FP64 inverse, six
+        # vectors in and six out: z, p_prev, u, v, r, x / x, r, z, p, u, v)
+        "pcg_step": 144.0 * nb + 288.0 * nn + 12 * 24.0 * nn,
         # per entry: sub-block 144 and its two offsets 8; per diagonal block its
         # J^T r pieces (24 per entry, counted once per node); blocks out (upper
         # and both explicit-row copies), gradient out
@@ -73,10 +79,10 @@ def kernel_bytes(ns, nn, nb, npx, lay):
         # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
         "pcg_init": 144.0 * nn + 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
         # upper blocks once (each is used for a row and, transposed, a column),
-        # z and p_old in, p and q out
+        # z and p_prev in, u = A z and v = A p_prev out
         "pcg_spmv": 144.0 * nb + 4 * 24.0 * nn,
-        # x, r, q, p and the inverses in; x, r, z out
-        "pcg_update": 4 * 24.0 * nn + 288.0 * nn + 3 * 24.0 * nn,
+        # PCG finish: z, p_prev, u, v, r, x and the inverses in; x, r, z, p out
+        "pcg_update": 6 * 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
         # twist in; node state and tables out; index map reset
         "node_update": 24.0 * nn + 32.0 * nn + 96.0 * nn + 8.0 * npx,
     }
@@ -86,12 +92,20 @@ def replay_us(bx, streams, pcg_iters, reps=200):
     """Mean time per launch of every replayable stage, each launched `reps`
     times back to back between two HIP events on the solve's stream."""
     out = {}
-    for i, k in enumerate(KERNELS):
-        if k in ("depth_prep", "node_update", "asm_segments"):
+    for k in KERNELS:
+        if k in ("depth_prep", "node_update") or (k == "pcg_step" and pcg_iters < 2):
             continue
-        pit = min(1, max(0, pcg_iters - 1)) if k in ("pcg_spmv", "pcg_update") else 0
-        out[k] = bx.profile_stage(streams, i, reps=reps, pcg_it=pit)
+        pit = min(1, max(0, pcg_iters - 1)) if k in ("pcg_spmv", "pcg_update", "pcg_step") else 0
+        out[k] = bx.profile_stage(streams, STAGE_ID[k], reps=reps, pcg_it=pit)
     return out
+
+
+def launches_per_frame(G, P, fused):
+    """Launches of each kernel per frame: one fused step per PCG iteration
+    after the first products, or a product and a finish launch."""
+    import numpy as np
+    return np.array([1, G, G, G * P if fused else 0, G, G if fused else G * P, 0 if fused else G * P, G, G],
+                    dtype=float)
 
 
 def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):
@@ -100,7 +114,7 @@ def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):
     share of the frame."""
     import numpy as np
     rates = {k: scale * kb[k] / (us * 1e-6) / 1e9 for k, us in replay.items() if us > 0}
-    share = {k: per_frame_us[i] for i, k in enumerate(KERNELS) if k in replay}
+    share = {k: per_frame_us[i] for i, k in enumerate(KERNELS) if k in replay and launches[i] > 0}
     name = max(share, key=share.get)
     achieved = rates[name]
     traffic = measured_traffic(name, streams)
@@ -237,7 +251,7 @@ def measured_traffic(kernel, streams):
                 table[(parts[1], int(parts[2]))] = float(parts[3])
     if src != kernel_source_hash():
         return None
-    name = {"corr_jac": "corr_gram"}.get(kernel, kernel)
+    name = {"corr_jac": "corr_gram", "pcg_update": "pcg_finish"}.get(kernel, kernel)
     return table.get((name, streams))
 
 
@@ -354,7 +368,8 @@ def main():
         tot += np.array(stats["stage_us"][:len(KERNELS)])
     per_frame_us = tot / reps
     G, Pi = p.gn_iters, p.pcg_iters
-    launches = np.array([1, G, G, G, G, G * Pi, G * Pi, G, G], dtype=float)
+    fused = bool(per_frame_us[KERNELS.index("pcg_step")] > 0)    # the schedule the plain solve took
+    launches = launches_per_frame(G, Pi, fused)
     kb = kernel_bytes(ns, nn, nb, scene.cam.width * scene.cam.height, lay)
     px = swgn.Batch(hip_stream=hip_stream)
     replay = replay_us(px, [tst], Pi)
@@ -399,7 +414,9 @@ def main():
         tb.close()
         for t in sts:
             t.close()
-        b_roof, b_rates = stage_roofline(btot / breps, launches, kb, b_replay, scale=B, streams=B)
+        b_fused = bool(orders[5] & 4)
+        b_roof, b_rates = stage_roofline(btot / breps, launches_per_frame(G, Pi, b_fused), kb, b_replay,
+                                         scale=B, streams=B)
         batched = {"streams": B, "value": round(B * nbs / bel, 2), "unit": "frames/s",
                    "ms_per_batch": round(1000.0 * bel / nbs, 3),
                    "latency_ms": {"p50": round(1000 * percentile(blat, 0.5), 4),
@@ -407,9 +424,11 @@ def main():
                    "kernel_us_per_batch_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, btot / breps)},
                    "kernel_us_per_launch": {k: round(v, 3) for k, v in b_replay.items()},
                    "kernel_gbs": b_rates, "roofline": b_roof, "identical_results": bool(same),
-                   "launch_variant": {k: ("xcd" if orders[i] & 1 else "linear") + ("+wide" if orders[i] & 2 else "")
-                                      for i, k in enumerate(KERNELS)
-                                      if k not in ("depth_prep", "node_update", "asm_segments")}}
+                   "pcg_schedule": "fused" if b_fused else "split",
+                   "launch_variant": {k: ("xcd" if orders[STAGE_ID[k]] & 1 else "linear") +
+                                      ("+wide" if orders[STAGE_ID[k]] & 2 else "")
+                                      for k in KERNELS if k not in ("depth_prep", "node_update")
+                                      and STAGE_ID[k] < len(orders)}}
         print(f"[bench] batched x{B}: {batched['value']} frames/s", file=sys.stderr, flush=True)
 
     served = None
@@ -447,6 +466,7 @@ def main():
                    "pcg_iters": p.pcg_iters, "mode": "plain"},
         "latency_ms": {"p50": round(1000 * percentile(lat, 0.5), 4),
                        "p99": round(1000 * percentile(lat, 0.99), 4)},
+        "pcg_schedule": "fused" if fused else "split",
         "kernel_us_per_frame": {k: round(float(v), 2) for k, v in zip(KERNELS, per_frame_us)},
         "kernel_us_per_launch": {k: round(v, 3) for k, v in replay.items()},
         "roofline": roofline,

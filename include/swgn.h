@@ -75,8 +75,9 @@ typedef struct sw_frame_stats {
     float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
                                   over the frame: [0] depth preprocessing, [1] warp +
                                   index map, [2] correspondence + Jacobians +
-                                  segment Gram matrices, [3] unused, [4] block-Jacobi +
-                                  PCG start, [5] PCG products, [6] PCG updates,
+                                  segment Gram matrices, [3] fused PCG steps,
+                                  [4] block-Jacobi + PCG start, [5] PCG
+                                  products, [6] PCG finishes,
                                   [7] node update, [8] assembly of the blocks,
                                   [9] rigid warp + index map, [10] rigid 6x6 sums,
                                   [11] rigid solve + composition; measured with HIP
@@ -150,6 +151,8 @@ typedef struct sw_batch_s* sw_batch;
 
 #define SW_BATCH_TIMING 1   /* time every launch with HIP events into stage_us */
 #define SW_BATCH_GRAPH  2   /* replay a batch's Gauss-Newton iterations as one HIP graph */
+#define SW_BATCH_PCG_SPLIT 4   /* every PCG iteration as a product and a finish launch */
+#define SW_BATCH_PCG_FUSED 8   /* every PCG iteration as one fused step launch */
 
 /* Create an executor. hip_stream as in sw_create_stream; flags: 0,
  * SW_BATCH_TIMING (then every stream's stage_us holds the times of the
@@ -160,7 +163,10 @@ typedef struct sw_batch_s* sw_batch;
  * buffers are unchanged (a new batch, or sw_set_reference_surfels /
  * sw_set_node_graph on a member, captures anew). Results are identical to
  * the launch-by-launch path. Not combinable with SW_BATCH_TIMING (EINVAL);
- * streams that capture an iteration (debug_iter) run launch by launch. */
+ * streams that capture an iteration (debug_iter) run launch by launch.
+ * SW_BATCH_PCG_SPLIT or SW_BATCH_PCG_FUSED (not both) fix the PCG schedule,
+ * which is otherwise chosen per batch shape (the autotuner's choice, else
+ * fused steps up to 8192 nodes in all); both give identical results. */
 sw_status sw_create_batch(void* hip_stream, int32_t flags, sw_batch* out);
 
 /* Destroy an executor (NULL is a no-op). Streams are not affected. */
@@ -187,24 +193,30 @@ sw_status sw_solve_batch(sw_batch b, const sw_stream* streams, int32_t n,
  * overwritten (their warp fields are not); use after a solve, so that the
  * stage's inputs hold a real frame. stage numbers as in stage_us: 1 warp +
  * index map, 2 correspondence + Jacobians + segment Gram matrices,
- * 4 block-Jacobi + PCG start, 5 PCG product, 6 PCG update, 8 block fold;
- * others give SW_EINVAL. pcg_it selects the PCG iteration for 5 and 6. */
+ * 4 block-Jacobi + PCG start, 5 PCG products (u = A z, v = A p_prev),
+ * 6 PCG finish (scalars, x, r, z, p), 8 block fold, 13 fused PCG step
+ * (finish of iteration pcg_it - 1 and products of pcg_it in one launch,
+ * pcg_it >= 1); others give SW_EINVAL. pcg_it selects the PCG iteration for
+ * 5, 6 and 13. */
 sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int32_t stage,
                            int32_t pcg_it, int32_t reps, float* us_per_launch);
 
 /* Autotuner: for the shape bucket of this batch (stream count and the
  * powers of two of its total surfels and nodes) time each per-frame stage
- * (1 warp, 2 correspondence, 8 fold, 4 PCG start, 5 product, 6 update) reps
- * times back to back in each launch variant and keep the fastest for later
- * solves of batches in that bucket on this executor. Variants: the tile
- * order — linear, or XCD-contiguous (the workgroups an XCD runs take one
- * contiguous range of tiles, keeping a stream's data in few L2 caches) — and,
- * for the product and the update, 1 or 2 block rows per wave / nodes per lane
- * group. Every variant computes the same tiles with the same reductions, so
- * results do not change. Use after a solve of the batch (the stages replay
- * its last frame; workspaces are overwritten, warp fields are not). variants
- * (NULL or 12 entries, indexed like stage_us) receives the choices: bit 0 =
- * XCD-contiguous order, bit 1 = 2 rows / nodes. */
+ * (1 warp, 2 correspondence, 8 fold, 4 PCG start, 5 product, 6 finish,
+ * 13 fused step) reps times back to back in each launch variant and keep the
+ * fastest for later solves of batches in that bucket on this executor.
+ * Variants: the tile order — linear, or XCD-contiguous (the workgroups an XCD
+ * runs take one contiguous range of tiles, keeping a stream's data in few L2
+ * caches) — and, for the product and the finish, 1 or 2 block rows per wave
+ * / nodes per lane group; then the PCG schedule — one fused step per
+ * iteration, or a product and a finish launch — by the faster sum. Every
+ * variant computes the same tiles with the same reductions, so results do
+ * not change. Use after a solve of the batch (the stages replay its last
+ * frame; workspaces are overwritten, warp fields are not). variants (NULL or
+ * 12 entries, indexed like stage_us) receives the choices: bit 0 =
+ * XCD-contiguous order, bit 1 = 2 rows / nodes, bit 2 (entry 5) = fused PCG
+ * steps. */
 sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int32_t reps,
                             int32_t* variants);
 

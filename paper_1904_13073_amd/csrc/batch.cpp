@@ -26,14 +26,16 @@ extern "C" {
 sw_status sw_create_batch(void* hip_stream, int32_t flags, sw_batch* out) {
     if (!out) return SW_EINVAL;
     *out = nullptr;
-    if (flags & ~(SW_BATCH_TIMING | SW_BATCH_GRAPH)) return SW_EINVAL;
+    if (flags & ~(SW_BATCH_TIMING | SW_BATCH_GRAPH | SW_BATCH_PCG_SPLIT | SW_BATCH_PCG_FUSED)) return SW_EINVAL;
     if ((flags & SW_BATCH_TIMING) && (flags & SW_BATCH_GRAPH)) return SW_EINVAL;
+    if ((flags & SW_BATCH_PCG_SPLIT) && (flags & SW_BATCH_PCG_FUSED)) return SW_EINVAL;
     sw_batch_s* b = new (std::nothrow) sw_batch_s();
     if (!b) return SW_ENOMEM;
     const sw_status rc = guarded(b->err, [&]() -> sw_status {
         b->flags = flags;
         b->exec.init(hip_stream);
         b->exec.graphs = (flags & SW_BATCH_GRAPH) != 0;
+        b->exec.pcg_mode = (flags & SW_BATCH_PCG_SPLIT) ? kPcgSplit : (flags & SW_BATCH_PCG_FUSED) ? kPcgFused : kPcgAuto;
         return SW_OK;
     });
     if (rc != SW_OK) {
@@ -85,7 +87,7 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
     if (n < 1 || n > kMaxBatch) return fail(b->err, SW_EINVAL, "batch size must be in [1, 64]");
     if (reps < 1 || reps > 100000) return fail(b->err, SW_EINVAL, "reps must be in [1, 100000]");
     const bool replayable = stage == kStWarp || stage == kStCorr || stage == kStAsmFold ||
-                            stage == kStPcgInit || stage == kStSpmv || stage == kStUpdate;
+                            stage == kStPcgInit || stage == kStSpmv || stage == kStUpdate || stage == kStPcgStep;
     if (!replayable) return fail(b->err, SW_EINVAL, "stage cannot be replayed (it reads input or moves nodes)");
     std::vector<sw_stream> ss(streams, streams + n);
     for (int i = 0; i < n; ++i) {
@@ -94,6 +96,7 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
         if (ss[i]->server) return fail(b->err, SW_ESTATE, "a stream in the batch is attached to a server");
         if (pcg_it < 0 || pcg_it >= std::max(1, ss[i]->h.pcg_iters))
             return fail(b->err, SW_EINVAL, "pcg_it out of range");
+        if (stage == kStPcgStep && pcg_it < 1) return fail(b->err, SW_EINVAL, "a fused step needs pcg_it >= 1");
     }
     return guarded(b->err, [&]() -> sw_status {
         std::vector<int> its(n, 0), ev;
@@ -126,10 +129,14 @@ sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int
         Executor& ex = b->exec;
         const uint64_t key = shape_bucket(ss);
         std::vector<int> choice(kNumStages, 0);
-        const int stages[] = {kStWarp, kStCorr, kStAsmFold, kStPcgInit, kStSpmv, kStUpdate};
+        int pmax = 0;
+        for (sw_stream s : ss) pmax = std::max(pmax, s->h.pcg_iters);
+        const int stages[] = {kStWarp, kStCorr, kStAsmFold, kStPcgInit, kStSpmv, kStUpdate, kStPcgStep};
+        float best_ms[kNumStages] = {0.f};
         std::vector<int> its(n, 0), ev;
         for (int stage : stages) {
             const bool has_wide = stage == kStSpmv || stage == kStUpdate;
+            if (stage == kStPcgStep && pmax < 2) continue;
             float best = 0.f;
             bool first = true;
             for (int variant = 0; variant < (has_wide ? 4 : 2); ++variant) {
@@ -138,7 +145,7 @@ sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int
                 trial[stage] = variant;
                 ex.tuned[key] = trial;
                 ex.bucket = key;
-                const int pit = has_wide ? 1 : 0;
+                const int pit = (has_wide || stage == kStPcgStep) ? 1 : 0;
                 run_stage(ex, stage, ss, its, pit, nullptr, false, ev);
                 hipEvent_t e0 = ex.event(0), e1 = ex.event(1);
                 SWGN_HIP(hipEventRecord(e0, ex.st));
@@ -153,7 +160,10 @@ sw_status sw_batch_autotune(sw_batch b, const sw_stream* streams, int32_t n, int
                     first = false;
                 }
             }
+            best_ms[stage] = best;
         }
+        // one fused step per PCG iteration, or a product and a finish launch
+        if (pmax >= 2 && best_ms[kStPcgStep] < best_ms[kStSpmv] + best_ms[kStUpdate]) choice[kStSpmv] |= kVarFused;
         ex.tuned[key] = choice;
         ex.tune_epoch += 1;
         if (variants)

@@ -81,8 +81,10 @@ int Executor::variant_of(int stage, int64_t rows) const {
     // untuned: the wide geometries only when the launch still has two
     // workgroups per CU with them
     const bool wide = (stage == kStSpmv && rows >= 256 * 2 * 2 * kSpmvWaves) ||
-                      (stage == kStUpdate && rows >= 256 * 2 * 2 * kSolvePart);
-    return wide ? kVarWide : 0;
+                      (stage == kStUpdate && rows >= 256 * 2 * 2 * kSolveNodes);
+    // fused PCG steps while the product launch is too small to fill the chip
+    const bool fused = stage == kStSpmv && rows <= kFusedRows;
+    return (wide ? kVarWide : 0) | (fused ? kVarFused : 0);
 }
 
 // Shape bucket of a batch: the stream count and the powers of two of its total
@@ -137,15 +139,17 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.part_e, 8 * ncor);
     take(h.part_n, 4 * ncor);
     take(h.x, 24 * nn);
-    take(h.r, 24 * nn);
-    take(h.z, 24 * nn);
-    take(h.q, 24 * nn);
-    take(h.p0, 24 * nn);
-    take(h.p1, 24 * nn);
+    for (int q = 0; q < 2; ++q) {
+        take(h.r[q], 24 * nn);
+        take(h.z[q], 24 * nn);
+        take(h.p[q], 24 * nn);
+        take(h.u[q], 24 * nn);
+        take(h.v[q], 24 * nn);
+        take(h.part_rho[q], 8 * nsol);
+        take(h.part_rr[q], 8 * nsol);
+        take(h.part_c[q], 3 * 8 * nspm);
+    }
     take(h.sc, 16);
-    take(h.part_rho, 8 * nsol);
-    take(h.part_rr, 8 * nsol);
-    take(h.part_pq, 8 * nspm);
     take(h.rig, 12 * 4);
     take(h.rig64, 12 * 8);
     take(h.rig_part, 8 * (size_t)kRigidSums * (size_t)cdiv(h.ns, kRigidSurfels));
@@ -238,7 +242,7 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int4* 
     SWGN_HIP(hipStreamSynchronize(st));
     SegmentLayout L;
     std::string why;
-    if (!segment_layout(ns, nn, h.nb, hkey.data(), hidx.data(), hrow.data(), hcol.data(), kCorrBlock, L, why))
+    if (!segment_layout(ns, nn, h.nb, hkey.data(), hidx.data(), hrow.data(), hcol.data(), kCorrPack, L, why))
         throw HipFail{hipErrorInvalidValue, why};
     const int nseg = (int)L.mask.size();
     auto up = [&](auto* dst, const auto& v) {
@@ -482,7 +486,9 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
         b.it[i] = (int8_t)its[i];
         int t = stage_tiles(stage, h, variant);
         if (its[i] < 0) t = 0;
+        // products of iteration pcg_it, finish of pcg_it, fused finish of pcg_it - 1 + products
         if ((stage == kStSpmv || stage == kStUpdate) && pcg_it >= h.pcg_iters) t = 0;
+        if (stage == kStPcgStep && (pcg_it < 1 || pcg_it > h.pcg_iters)) t = 0;
         off += t;
     }
     b.off[b.n] = off;
@@ -574,9 +580,20 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
         SWGN_HIP(hipMemcpyAsync(s->dbg_g, h.g, sizeof(float) * 6 * h.nn, hipMemcpyDeviceToDevice, st));
     }
     run_stage(ex, kStPcgInit, ss, its, 0, nullptr, timing, ev);
-    for (int pit = 0; pit < pmax; ++pit) {
-        run_stage(ex, kStSpmv, ss, its, pit, nullptr, timing, ev);
-        run_stage(ex, kStUpdate, ss, its, pit, nullptr, timing, ev);
+    int64_t rows = 0;
+    for (int i = 0; i < n; ++i)
+        if (its[i] >= 0) rows += ss[i]->h.nn;
+    const bool fused = ex.pcg_mode == kPcgFused ||
+                       (ex.pcg_mode == kPcgAuto && (ex.variant_of(kStSpmv, rows) & kVarFused) != 0);
+    if (pmax > 0) run_stage(ex, kStSpmv, ss, its, 0, nullptr, timing, ev);
+    for (int pit = 1; pit <= pmax; ++pit) {
+        if (fused) {
+            // finish of pit - 1 and, for streams with more iterations, products of pit
+            run_stage(ex, kStPcgStep, ss, its, pit, nullptr, timing, ev);
+        } else {
+            run_stage(ex, kStUpdate, ss, its, pit - 1, nullptr, timing, ev);
+            if (pit < pmax) run_stage(ex, kStSpmv, ss, its, pit, nullptr, timing, ev);
+        }
     }
     run_stage(ex, kStNodeUpdate, ss, its, 0, nullptr, timing, ev);
     for (int i = 0; i < n; ++i) {

@@ -16,6 +16,10 @@ namespace swgn {
 namespace rt {
 
 constexpr int kMaxNodes = 32768;
+// Untuned batches take fused PCG steps up to this many rows in all (where one
+// launch per iteration beats two; above it the products' re-reads cost more).
+constexpr int64_t kFusedRows = 8192;
+constexpr int kPcgAuto = 0, kPcgSplit = 1, kPcgFused = 2;
 constexpr int64_t kMaxSurfels = (int64_t)1 << 28;
 
 struct HipFail {
@@ -63,6 +67,7 @@ struct Executor {
     int variant_of(int stage, int64_t rows) const;
     // replay of a batch's iterations as one HIP graph
     bool graphs = false;
+    int pcg_mode = 0;                     // kPcgAuto, kPcgSplit, kPcgFused
     hipGraphExec_t graph_exec = nullptr;
     std::vector<std::pair<sw_stream, uint64_t>> graph_key;   // (stream, generation) it was captured for
     ~Executor();

@@ -2,19 +2,28 @@
 //
 //   pcg_init     block-Jacobi preconditioner (FP64 inverses of H_kk + mu I) and
 //                the start of preconditioned conjugate gradients on
-//                (J^T J + mu I) delta = -g: r = -g, z = M r, p = z, x = 0
-//   pcg_spmv     q = A p with p = z + beta p_old formed on the fly (one wave per
-//                block row; the row's blocks, transposes written out, in ELL
-//                layout)
-//   pcg_update   x += alpha p, r -= alpha q, z = M r (8 lanes per node)
+//                (J^T J + mu I) delta = -g: r_0 = -g, z_0 = M r_0, x = 0
+//   pcg_spmv     products of iteration i: u_i = A z_i and v_i = A p_{i-1} (one
+//                wave per block row; the row's blocks, transposes written out,
+//                in ELL layout) and the partial sums that give p_i.q_i once
+//                beta_i is known
+//   pcg_finish   finish of iteration i: beta_i, alpha_i, p_i = z_i + beta_i p_{i-1},
+//                x += alpha p_i, r -= alpha (u_i + beta_i v_i), z = M r
+//                (8 lanes per node)
+//   pcg_step     finish of iteration i - 1 and products of iteration i in one
+//                launch: the products re-form their columns' z_i and p_{i-1}
 //   node_update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
 //                the reset of the index map for the next iteration and the
 //                iteration's energy statistics
 //
-// PCG runs a fixed number of iterations and stops early only if rho = r^T z is
-// exactly 0. Its scalars never leave the device: every workgroup sums the same
-// per-workgroup partials (FP64) in the same order, so all workgroups take
-// identical decisions and a solve is bit-reproducible.
+// This is standard preconditioned CG (the same iterates in exact arithmetic)
+// with the application of beta deferred: the product kernel needs only
+// vectors of the previous finish, so a finish and the next products can share
+// a launch. PCG runs a fixed number of iterations and stops early only if
+// rho = r^T z is exactly 0. Its scalars never leave the device: every
+// workgroup sums the same partials (FP64) in the same order, so all workgroups
+// take identical decisions and a solve is bit-reproducible, with fused steps
+// or without.
 #include <algorithm>
 
 #include "swgn_frame.h"
@@ -24,6 +33,14 @@
 namespace swgn {
 
 namespace {
+
+// One of a pair of buffers kept by iteration parity. (A select of the two
+// pointers: indexing the descriptor's arrays with a run-time value would put
+// the descriptor copy in scratch memory.)
+template <class T>
+__device__ __forceinline__ T* by_parity(T* const (&pair)[2], int q) {
+    return (q & 1) ? pair[1] : pair[0];
+}
 
 __device__ void update_node(const FrameDesc& a, int k) {
     const float* x = a.x + 6 * k;
@@ -62,13 +79,14 @@ __device__ void update_node(const FrameDesc& a, int k) {
 // 8 lanes per node: lane a < 6 holds row a of [H_kk + mu I | I]; FP64
 // Gauss-Jordan elimination leaves row a of the inverse. Without pivoting the
 // pivots of a symmetric matrix are all positive exactly when it is positive
-// definite, which is checked.
+// definite, which is checked. Then r_0 = -g, z_0 = M r_0, x = 0 and the
+// direction before the first, p_{-1} = 0.
 __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
-    __shared__ double sh[40];
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
     const int gid = at.tile * kSolveBlock + threadIdx.x;
     const int k = gid >> 3, row = gid & 7, base = threadIdx.x & ~7;
+    const int lane = threadIdx.x % kWave;
     const bool on = (k < a.nn) && (row < 6);
     double m[12];
     const float* A = a.H + (size_t)(k < a.nn ? a.row_ptr[k] : 0) * 36;
@@ -104,66 +122,21 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     if (on) {
         const float zf = (float)zc;
         const int t = 6 * k + row;
-        a.r[t] = rc;
-        a.z[t] = zf;
-        a.p0[t] = zf;
+        a.r[0][t] = rc;
+        a.z[0][t] = zf;
+        a.p[1][t] = 0.f;
         a.x[t] = 0.f;
         rho = (double)rc * (double)zf;
         rr = (double)rc * (double)rc;
     }
-    rho = block_sum(rho, sh);
-    rr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        a.part_rho[at.tile] = rho;
-        a.part_rr[at.tile] = rr;
+    // partials per 8 nodes: one wave's sums
+    rho = wave_sum(rho);
+    rr = wave_sum(rr);
+    const int part = gid / kWave;
+    if (lane == 0 && part < solve_parts(a)) {
+        a.part_rho[0][part] = rho;
+        a.part_rr[0][part] = rr;
     }
-}
-
-// Products of one block row with z and with p_old: 8-lane group fl takes the
-// row's slots fl, fl + 8, ...; lane sub < 6 holds row sub of the slot's block
-// (one 24-byte line) and element sub of the column's z and p_old, which the
-// group shares by shuffles. The row's products with z and with p_{it-1} are
-// accumulated separately, so the matrix loads run before beta (a grid-wide
-// sum) is known.
-struct RowAcc {
-    float az, ap;
-};
-
-__device__ __forceinline__ RowAcc row_products(const FrameDesc& a, const float* __restrict__ pold, int k, int lane) {
-    const int sub = lane & 7, fl = lane >> 3;
-    float az = 0.f, ap = 0.f;
-    if (k < a.nn) {
-        const uint32_t* eb = a.ell_blk + (size_t)k * a.ell_w;
-        const int* ec = a.ell_col + (size_t)k * a.ell_w;
-        const int base = lane & ~7;
-        const int sl = sub < 6 ? sub : 0;
-#pragma unroll 2
-        for (int f = fl; f < a.ell_w; f += 8) {
-            const uint32_t bb = eb[f];
-            if (bb == 0xffffffffu) break;
-            const int col = ec[f];
-            const float2* B = reinterpret_cast<const float2*>(a.Hf + ((size_t)k * a.ell_w + f) * 36 + sl * 6);
-            const float2 h01 = B[0], h23 = B[1], h45 = B[2];
-            const float h[6] = {h01.x, h01.y, h23.x, h23.y, h45.x, h45.y};
-            const float zv = a.z[6 * col + sl];
-            const float pv = pold[6 * col + sl];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const float zc = __shfl(zv, base + c, kWave);
-                const float pc = __shfl(pv, base + c, kWave);
-                az = fmaf(h[c], zc, az);
-                ap = fmaf(h[c], pc, ap);
-            }
-        }
-        if (sub >= 6) { az = 0.f; ap = 0.f; }
-    }
-    az += __shfl_xor(az, 8, kWave);
-    az += __shfl_xor(az, 16, kWave);
-    az += __shfl_xor(az, 32, kWave);
-    ap += __shfl_xor(ap, 8, kWave);
-    ap += __shfl_xor(ap, 16, kWave);
-    ap += __shfl_xor(ap, 32, kWave);
-    return RowAcc{az, ap};
 }
 
 // Sum of n partials in the fixed shape of a 256-thread reduction (thread t
@@ -188,132 +161,411 @@ __device__ __forceinline__ double reduce_parts256(const double* __restrict__ par
     return r;
 }
 
-// q = A p_it with p_it = z + beta p_{it-1} (beta = 0 and p_0 = z at it = 0);
-// one workgroup = 4 waves of RPW block rows each.
-template <int RPW>
-__global__ void __launch_bounds__(64 * kSpmvWaves) k_pcg_spmv(Batch b) {
-    __shared__ double sh[40];
-    __shared__ double rs[8];
-    const Where at = locate(b);
-    const FrameDesc a = *b.d[at.s];
-    const int it = b.pcg_it;
-    float* const pbuf[2] = {a.p0, a.p1};
-    const float* pold = it > 0 ? pbuf[(it - 1) & 1] : pbuf[0];
-    float* pcur = pbuf[it & 1];
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int k0 = at.tile * kSpmvWaves * RPW + RPW * wave;
-    RowAcc ra[RPW];
-#pragma unroll
-    for (int u = 0; u < RPW; ++u) ra[u] = row_products(a, pold, k0 + u, lane);
-    const double rho = reduce_parts256(a.part_rho, solve_parts(a), sh);
-    const bool stop = (rho == 0.0);
-    const float beta = (it > 0 && !stop) ? (float)(rho / a.sc[(it - 1) & 1]) : 0.f;
-    if (at.tile == 0 && threadIdx.x == 0) a.sc[it & 1] = rho;   // read by this iteration's update
-#pragma unroll
-    for (int u = 0; u < RPW; ++u) {
-        const int k = k0 + u;
-        double pq = 0.0;
-        if (!stop && k < a.nn && lane < 6) {
-            const int t = 6 * k + lane;
-            const float pk = it > 0 ? a.z[t] + beta * pold[t] : pold[t];
-            const float qv = ra[u].az + beta * ra[u].ap;
-            if (it > 0) pcur[t] = pk;
-            a.q[t] = qv;
-            pq = (double)pk * (double)qv;
+// Scalars that finish PCG iteration k (rho_k = r_k.z_k from the node partials,
+// p_k.q_k from the three row products, rho_{k-1} from the ring):
+//   beta_k = rho_k / rho_{k-1} (0 at k = 0), p_k = z_k + beta_k p_{k-1},
+//   q_k = A p_k = u_k + beta_k v_k,
+//   p_k.q_k = z.u + beta (z.v + p.u) + beta^2 p.v,   alpha_k = rho_k / p_k.q_k.
+// rho_k = 0 stops the iteration: alpha = beta = 0 leave x, r and z as they are.
+// Every workgroup sums the same partials in the same order, so all take the
+// same scalars; workgroup 0 of the stream keeps rho_k for the next finish.
+struct PcgScalars {
+    float alpha, beta;
+};
+
+// Four sums of partials at once, each in the fixed shape of reduce_parts256
+// (thread t adds its strided partials, then the wave sums, then the 4 waves
+// in order): one pass of loads and one exchange instead of four.
+struct Sum4 {
+    double s[4];
+};
+
+__device__ __forceinline__ Sum4 reduce4_parts256(const double* __restrict__ p0, int n0,
+                                                 const double* __restrict__ p123, int n123, double* sh) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (threadIdx.x < 256) {
+        for (int i = threadIdx.x; i < n0; i += 256) v[0] += p0[i];
+        for (int i = threadIdx.x; i < n123; i += 256) {
+            v[1] += p123[i];
+            v[2] += p123[n123 + i];
+            v[3] += p123[2 * n123 + i];
         }
-        pq = wave_sum(pq);
-        if (lane == 0) rs[RPW * wave + u] = pq;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0 && w < 4) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sh[4 * w + m] = v[m];
     }
     __syncthreads();
-    // partials per 4 rows, each the in-order sum of its rows' wave sums
-    if (threadIdx.x < RPW) {
-        const int quad = at.tile * RPW + threadIdx.x;
-        if (quad < spmv_parts(a)) {
-            double t = 0.0;
-            for (int q = 0; q < 4; ++q) t += rs[4 * threadIdx.x + q];
-            a.part_pq[quad] = t;
+    Sum4 r;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double t = 0.0;
+        for (int q = 0; q < 4; ++q) t += sh[4 * q + m];
+        r.s[m] = t;
+    }
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ PcgScalars pcg_scalars(const FrameDesc& a, int k, bool keep, double* sh) {
+    const int par = k & 1, nsp = spmv_parts(a);
+    const Sum4 t = reduce4_parts256(by_parity(a.part_rho, par), solve_parts(a), by_parity(a.part_c, par), nsp, sh);
+    const double rho = t.s[0], c1 = t.s[1], c2 = t.s[2], c3 = t.s[3];
+    const bool stop = (rho == 0.0);
+    const float beta = (k > 0 && !stop) ? (float)(rho / a.sc[(k - 1) & 1]) : 0.f;
+    const double bd = (double)beta;
+    const double pq = (c1 + bd * c2) + (bd * bd) * c3;
+    const float alpha = stop ? 0.f : (float)(rho / pq);
+    if (keep && threadIdx.x == 0) a.sc[par] = rho;
+    return PcgScalars{alpha, beta};
+}
+
+// The finish of iteration k for one component of one node (8 lanes per node,
+// component c = lane & 7 < 6, lanes 6 and 7 carry zeros): p_k, r_{k+1},
+// z_{k+1} = M r_{k+1} (FP64 sum of the node's 6 entries, read by shuffles
+// within the lane group) and x_{k+1}. A fused step repeats the same
+// operations for the nodes of its rows' columns, so both agree bit for bit.
+struct Finished {
+    float p, r, z, x;
+};
+
+__device__ __forceinline__ Finished finish_lane(float zk, float pprev, float uk, float vk, float rk, float xk,
+                                                const double (&mrow)[6], PcgScalars s, int base) {
+    Finished f;
+    f.p = zk + s.beta * pprev;
+    const float q = uk + s.beta * vk;
+    f.x = xk + s.alpha * f.p;
+    f.r = rk - s.alpha * q;
+    double zc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) zc += mrow[j] * (double)__shfl(f.r, base + j, kWave);
+    f.z = (float)zc;
+    return f;
+}
+
+// Finish of iteration k = b.pcg_it: x_{k+1}, r_{k+1}, z_{k+1}, p_k; partials
+// of rho_{k+1} and r_{k+1}.r_{k+1}. NPG nodes per lane group (k, k + 32, ...
+// of the workgroup's 32 NPG); each wave's 8 nodes give one partial.
+template <int NPG>
+__global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
+    __shared__ double sh[40];
+    const Where at = locate(b);
+    const FrameDesc& a = *b.d[at.s];
+    const int k = b.pcg_it, cur = k & 1, nxt = cur ^ 1;
+    const int c = threadIdx.x & 7, base = threadIdx.x & ~7;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    float zc[NPG], pc[NPG], uc[NPG], vc[NPG], rc[NPG], xc[NPG];
+    double mrow[NPG][6];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        const int n = at.tile * NPG * kSolveNodes + g * kSolveNodes + (threadIdx.x >> 3);
+        const bool on = (n < a.nn) && (c < 6);
+        const int t = 6 * n + c;
+        zc[g] = pc[g] = uc[g] = vc[g] = rc[g] = xc[g] = 0.f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) mrow[g][j] = 0.0;
+        if (on) {
+            zc[g] = by_parity(a.z, cur)[t]; pc[g] = by_parity(a.p, nxt)[t]; uc[g] = by_parity(a.u, cur)[t]; vc[g] = by_parity(a.v, cur)[t];
+            rc[g] = by_parity(a.r, cur)[t]; xc[g] = a.x[t];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) mrow[g][j] = a.Minv[(size_t)n * 36 + c * 6 + j];
+        }
+    }
+    const PcgScalars s = pcg_scalars(a, k, at.tile == 0, sh);
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        const int n = at.tile * NPG * kSolveNodes + g * kSolveNodes + (threadIdx.x >> 3);
+        const bool on = (n < a.nn) && (c < 6);
+        const int t = 6 * n + c;
+        const Finished f = finish_lane(zc[g], pc[g], uc[g], vc[g], rc[g], xc[g], mrow[g], s, base);
+        double rz = 0.0, rr = 0.0;
+        if (on) {
+            a.x[t] = f.x;
+            by_parity(a.r, nxt)[t] = f.r;
+            by_parity(a.z, nxt)[t] = f.z;
+            by_parity(a.p, cur)[t] = f.p;
+            rz = (double)f.r * (double)f.z;
+            rr = (double)f.r * (double)f.r;
+        }
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
+        const int part = (at.tile * NPG * kSolveNodes + g * kSolveNodes) / kSolvePart + wave;
+        if (lane == 0 && part < solve_parts(a)) {
+            by_parity(a.part_rho, nxt)[part] = rz;
+            by_parity(a.part_rr, nxt)[part] = rr;
         }
     }
 }
 
-// x += alpha p, r -= alpha q, z = M r: 8 lanes per node, NPG nodes per lane
-// group (k, k + 32, ... of the workgroup's 32 NPG).
-template <int NPG>
-__global__ void __launch_bounds__(kSolveBlock) k_pcg_update(Batch b) {
-    __shared__ double sh[40];
-    __shared__ double ws[NPG][2][4];
-    const Where at = locate(b);
-    const FrameDesc a = *b.d[at.s];
-    const int it = b.pcg_it;
-    const float* p = (it & 1) ? a.p1 : a.p0;
-    const int c = threadIdx.x & 7;
-    const int base = (threadIdx.x & ~7);
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    float rc[NPG], xc[NPG], pc[NPG], qc[NPG];
-    double mrow[NPG][6];
+// Products of one block row with z_i and with p_{i-1} (u_i and v_i of the
+// row): 8-lane group fl takes the row's slots fl, fl + 8, ...; lane sub < 6
+// holds row sub of the slot's block (one 24-byte line) and element sub of the
+// column's vectors, which the group shares by shuffles. With FUSED, the
+// column's z_i and p_{i-1} are formed here from its iteration-(i-1) state by
+// the finish operations (same order, same rounding) instead of being read.
+// The first two slots of each group are loaded by row_prefetch (which a fused
+// step issues before its scalars are known); row_products goes on from there.
+struct RowAcc {
+    float u, v;
+};
+
+struct SlotData {
+    int n;                        // slots loaded: 0, 1 or 2 (slots fl and fl + 8)
+    float h[2][6];                // the block's row sub
+    float c[2][5];                // column: z_{i-1}, p_{i-2}, u_{i-1}, v_{i-1}, r_{i-1} (FUSED), else z_i, p_{i-1}
+    double m[2][6];               // FUSED: row sub of the column's inverse
+};
+
+template <bool FUSED>
+__device__ __forceinline__ void load_slot(const FrameDesc& a, int i, int row, int f, int col, int sub, float (&h)[6],
+                                          float (&cv)[5], double (&m)[6]) {
+    const int cur = i & 1, prv = cur ^ 1;
+    const int sl = sub < 6 ? sub : 0;
+    const float2* B = reinterpret_cast<const float2*>(a.Hf + ((size_t)row * a.ell_w + f) * 36 + sl * 6);
+    const float2 h01 = B[0], h23 = B[1], h45 = B[2];
+    h[0] = h01.x; h[1] = h01.y; h[2] = h23.x; h[3] = h23.y; h[4] = h45.x; h[5] = h45.y;
+    const int t = 6 * col + sl;
+    if (FUSED) {
+        cv[0] = by_parity(a.z, prv)[t];
+        cv[1] = by_parity(a.p, cur)[t];
+        cv[2] = by_parity(a.u, prv)[t];
+        cv[3] = by_parity(a.v, prv)[t];
+        cv[4] = by_parity(a.r, prv)[t];
 #pragma unroll
-    for (int u = 0; u < NPG; ++u) {
-        const int k = at.tile * NPG * kSolvePart + u * kSolvePart + (threadIdx.x >> 3);
-        const bool on = (k < a.nn) && (c < 6);
-        const int t = 6 * k + c;
-        rc[u] = xc[u] = pc[u] = qc[u] = 0.f;
-        if (on) {
-            rc[u] = a.r[t]; xc[u] = a.x[t]; pc[u] = p[t]; qc[u] = a.q[t];
+        for (int j = 0; j < 6; ++j) m[j] = a.Minv[(size_t)col * 36 + sl * 6 + j];
+    } else {
+        cv[0] = by_parity(a.z, cur)[t];
+        cv[1] = by_parity(a.p, prv)[t];
+    }
+}
+
+template <bool FUSED>
+__device__ __forceinline__ void row_prefetch(const FrameDesc& a, int i, int row, int lane, SlotData& sd) {
+    const int sub = lane & 7, fl = lane >> 3;
+    sd.n = 0;
+    if (row >= a.nn) return;
+    const uint32_t* eb = a.ell_blk + (size_t)row * a.ell_w;
+    const int* ec = a.ell_col + (size_t)row * a.ell_w;
 #pragma unroll
-            for (int j = 0; j < 6; ++j) mrow[u][j] = a.Minv[(size_t)k * 36 + c * 6 + j];
-        } else {
+    for (int q = 0; q < 2; ++q) {
+        const int f = fl + 8 * q;
+        if (f >= a.ell_w || eb[f] == 0xffffffffu) break;
+        load_slot<FUSED>(a, i, row, f, ec[f], sub, sd.h[q], sd.c[q], sd.m[q]);
+        sd.n = q + 1;
+    }
+}
+
+// the column's z and p of one slot (FUSED: its finish of iteration i - 1)
+template <bool FUSED>
+__device__ __forceinline__ void slot_vectors(const float (&cv)[5], const double (&m)[6], int sub, int base,
+                                             PcgScalars s, float& zv, float& pv) {
+    if (FUSED) {
+        double mr[6];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) mrow[u][j] = 0.0;
+        for (int j = 0; j < 6; ++j) mr[j] = sub < 6 ? m[j] : 0.0;
+        const bool on = sub < 6;
+        const Finished fin = finish_lane(on ? cv[0] : 0.f, on ? cv[1] : 0.f, on ? cv[2] : 0.f, on ? cv[3] : 0.f,
+                                         on ? cv[4] : 0.f, 0.f, mr, s, base);
+        zv = fin.z;
+        pv = fin.p;
+    } else {
+        zv = cv[0];
+        pv = cv[1];
+    }
+}
+
+__device__ __forceinline__ void slot_products(const float (&h)[6], float zv, float pv, int base, float& au,
+                                              float& av) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float zc = __shfl(zv, base + c, kWave);
+        const float pc = __shfl(pv, base + c, kWave);
+        au = fmaf(h[c], zc, au);
+        av = fmaf(h[c], pc, av);
+    }
+}
+
+template <bool FUSED>
+__device__ __forceinline__ RowAcc row_products(const FrameDesc& a, int i, int row, int lane, PcgScalars s,
+                                               const SlotData& sd) {
+    const int sub = lane & 7, fl = lane >> 3;
+    const int base = lane & ~7;
+    float au = 0.f, av = 0.f;
+    if (row < a.nn) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q >= sd.n) break;
+            float zv, pv;
+            slot_vectors<FUSED>(sd.c[q], sd.m[q], sub, base, s, zv, pv);
+            slot_products(sd.h[q], zv, pv, base, au, av);
+        }
+        if (sd.n == 2) {
+            const uint32_t* eb = a.ell_blk + (size_t)row * a.ell_w;
+            const int* ec = a.ell_col + (size_t)row * a.ell_w;
+            for (int f = fl + 16; f < a.ell_w; f += 8) {
+                if (eb[f] == 0xffffffffu) break;
+                float h[6], cv[5];
+                double m[6];
+                load_slot<FUSED>(a, i, row, f, ec[f], sub, h, cv, m);
+                float zv, pv;
+                slot_vectors<FUSED>(cv, m, sub, base, s, zv, pv);
+                slot_products(h, zv, pv, base, au, av);
+            }
+        }
+        if (sub >= 6) { au = 0.f; av = 0.f; }
+    }
+    au += __shfl_xor(au, 8, kWave);
+    au += __shfl_xor(au, 16, kWave);
+    au += __shfl_xor(au, 32, kWave);
+    av += __shfl_xor(av, 8, kWave);
+    av += __shfl_xor(av, 16, kWave);
+    av += __shfl_xor(av, 32, kWave);
+    return RowAcc{au, av};
+}
+
+// Stores u_i, v_i of a row and returns the row's three products
+// (z.u, z.v + p.u, p.v over its 6 entries, summed over the wave).
+struct RowProducts {
+    double c1, c2, c3;
+};
+
+__device__ __forceinline__ RowProducts store_row(const FrameDesc& a, int i, int row, int lane, RowAcc ra,
+                                                 float zo, float po) {
+    double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    if (row < a.nn && lane < 6) {
+        const int t = 6 * row + lane;
+        by_parity(a.u, i & 1)[t] = ra.u;
+        by_parity(a.v, i & 1)[t] = ra.v;
+        c1 = (double)zo * (double)ra.u;
+        c2 = (double)zo * (double)ra.v + (double)po * (double)ra.u;
+        c3 = (double)po * (double)ra.v;
+    }
+    return RowProducts{wave_sum(c1), wave_sum(c2), wave_sum(c3)};
+}
+
+// Partials per 4 rows, each the in-order sum of its rows' products.
+__device__ __forceinline__ void store_row_parts(const FrameDesc& a, int i, int quad0, int nquads,
+                                                const double (*rs)[3]) {
+    if ((int)threadIdx.x < 3 * nquads) {
+        const int q = threadIdx.x / 3, m = threadIdx.x % 3;
+        const int quad = quad0 + q;
+        if (quad < spmv_parts(a)) {
+            double t = 0.0;
+            for (int w = 0; w < 4; ++w) t += rs[4 * q + w][m];
+            by_parity(a.part_c, i & 1)[m * spmv_parts(a) + quad] = t;
         }
     }
-    const double rho = a.sc[it & 1];
-    const bool stop = (rho == 0.0);
-    const double pq = reduce_parts256(a.part_pq, spmv_parts(a), sh);
+}
+
+// Products of iteration i = b.pcg_it from z_i and p_{i-1} as stored; one
+// workgroup = 4 waves of RPW block rows each.
+template <int RPW>
+__global__ void __launch_bounds__(64 * kSpmvWaves) k_pcg_spmv(Batch b) {
+    __shared__ double rs[kSpmvWaves * RPW][3];
+    const Where at = locate(b);
+    const FrameDesc& a = *b.d[at.s];
+    const int i = b.pcg_it;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int k0 = at.tile * kSpmvWaves * RPW + RPW * wave;
+    RowAcc ra[RPW];
 #pragma unroll
-    for (int u = 0; u < NPG; ++u) {
-        const int k = at.tile * NPG * kSolvePart + u * kSolvePart + (threadIdx.x >> 3);
-        const bool on = (k < a.nn) && (c < 6);
-        const int t = 6 * k + c;
-        double rz = 0.0, rr = 0.0;
-        float r1 = rc[u];
-        if (!stop) {
-            const float alpha = (float)(rho / pq);
-            const float x1 = xc[u] + alpha * pc[u];
-            r1 = rc[u] - alpha * qc[u];
-            if (on) {
-                a.x[t] = x1;
-                a.r[t] = r1;
-            }
-            // z_c = sum_j M[c][j] r_j: the node's 6 residual entries from its lanes
-            double zc = 0.0;
+    for (int g = 0; g < RPW; ++g) {
+        SlotData sd;
+        row_prefetch<false>(a, i, k0 + g, lane, sd);
+        ra[g] = row_products<false>(a, i, k0 + g, lane, PcgScalars{0.f, 0.f}, sd);
+    }
 #pragma unroll
-            for (int j = 0; j < 6; ++j) zc += mrow[u][j] * (double)__shfl(r1, base + j, kWave);
-            if (on) {
-                const float zf = (float)zc;
-                a.z[t] = zf;
-                rz = (double)r1 * (double)zf;
-            }
+    for (int g = 0; g < RPW; ++g) {
+        const int row = k0 + g;
+        float zo = 0.f, po = 0.f;
+        if (row < a.nn && lane < 6) {
+            zo = by_parity(a.z, i & 1)[6 * row + lane];
+            po = by_parity(a.p, (i & 1) ^ 1)[6 * row + lane];
         }
-        if (on) rr = (double)r1 * (double)r1;
-        rz = wave_sum(rz);
-        rr = wave_sum(rr);
+        const RowProducts rp = store_row(a, i, row, lane, ra[g], zo, po);
         if (lane == 0) {
-            ws[u][0][wave] = rz;
-            ws[u][1][wave] = rr;
+            rs[RPW * wave + g][0] = rp.c1;
+            rs[RPW * wave + g][1] = rp.c2;
+            rs[RPW * wave + g][2] = rp.c3;
         }
     }
     __syncthreads();
-    // partials per 32 nodes, in-order sums of 4 wave sums
-    if (threadIdx.x < NPG) {
-        const int u = threadIdx.x;
-        const int part = at.tile * NPG + u;
-        if (part < solve_parts(a)) {
-            double tz = 0.0, tr = 0.0;
-            for (int q = 0; q < 4; ++q) { tz += ws[u][0][q]; tr += ws[u][1][q]; }
-            a.part_rho[part] = tz;
-            a.part_rr[part] = tr;
+    store_row_parts(a, i, at.tile * RPW, RPW, rs);
+}
+
+// One fused PCG step i = b.pcg_it >= 1 over 8 nodes: wave 0 finishes iteration
+// i - 1 for them (as k_pcg_finish), then, if i < pcg_iters, wave w forms the
+// products of iteration i for row 8 tile + w, computing the columns' z_i and
+// p_{i-1} itself (row_products<true>). One launch per PCG iteration instead of
+// two, at the cost of re-reading each column's state and inverse.
+__global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
+    __shared__ double sh[40];
+    __shared__ double rs[kStepNodes][3];
+    __shared__ float own_z[kStepNodes * 8], own_p[kStepNodes * 8];
+    const Where at = locate(b);
+    const FrameDesc& a = *b.d[at.s];
+    const int i = b.pcg_it, k = i - 1, cur = k & 1, nxt = cur ^ 1;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int n0 = at.tile * kStepNodes;
+    const bool prod = i < a.pcg_iters;     // uniform: false at this stream's last finish
+    // loads first (they do not depend on the scalars): the finishing wave's
+    // own nodes, every wave's first two slots of its row
+    const int c = lane & 7, base = lane & ~7;
+    const int n = n0 + (lane >> 3);
+    const bool on = (wave == 0) && (n < a.nn) && (c < 6);
+    const int t = 6 * n + c;
+    float zk = 0.f, pp = 0.f, uk = 0.f, vk = 0.f, rk = 0.f, xk = 0.f;
+    double mrow[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) mrow[j] = 0.0;
+    if (on) {
+        zk = by_parity(a.z, cur)[t]; pp = by_parity(a.p, nxt)[t]; uk = by_parity(a.u, cur)[t];
+        vk = by_parity(a.v, cur)[t]; rk = by_parity(a.r, cur)[t];
+        xk = a.x[t];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) mrow[j] = a.Minv[(size_t)n * 36 + c * 6 + j];
+    }
+    const int row = n0 + wave;
+    SlotData sd;
+    sd.n = 0;
+    if (prod) row_prefetch<true>(a, i, row, lane, sd);
+    const PcgScalars s = pcg_scalars(a, k, at.tile == 0, sh);
+    if (wave == 0) {
+        const Finished f = finish_lane(zk, pp, uk, vk, rk, xk, mrow, s, base);
+        double rz = 0.0, rr = 0.0;
+        if (on) {
+            a.x[t] = f.x;
+            by_parity(a.r, nxt)[t] = f.r;
+            by_parity(a.z, nxt)[t] = f.z;
+            by_parity(a.p, cur)[t] = f.p;
+            rz = (double)f.r * (double)f.z;
+            rr = (double)f.r * (double)f.r;
+        }
+        own_z[lane] = on ? f.z : 0.f;
+        own_p[lane] = on ? f.p : 0.f;
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
+        if (lane == 0 && n0 / kSolvePart < solve_parts(a)) {
+            by_parity(a.part_rho, nxt)[n0 / kSolvePart] = rz;
+            by_parity(a.part_rr, nxt)[n0 / kSolvePart] = rr;
         }
     }
+    if (!prod) return;
+    __syncthreads();
+    const RowAcc ra = row_products<true>(a, i, row, lane, s, sd);
+    const float zo = lane < 6 ? own_z[wave * 8 + lane] : 0.f;
+    const float po = lane < 6 ? own_p[wave * 8 + lane] : 0.f;
+    const RowProducts rp = store_row(a, i, row, lane, ra, zo, po);
+    if (lane == 0) {
+        rs[wave][0] = rp.c1;
+        rs[wave][1] = rp.c2;
+        rs[wave][2] = rp.c3;
+    }
+    __syncthreads();
+    store_row_parts(a, i, n0 / kSpmvPart, kStepNodes / kSpmvPart, rs);
 }
 
 __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
@@ -326,7 +578,7 @@ __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
     if (at.tile == 0) {
         const int nparts = corr_tiles(a);
         IterStats* stats = a.stats + b.it[at.s];
-        const double rr = reduce_partials(a.part_rr, solve_parts(a), sh);
+        const double rr = reduce_partials(by_parity(a.part_rr, a.pcg_iters & 1), solve_parts(a), sh);   // of r_{pcg_iters}
         // energies at this iteration's linearisation point
         double e = 0.0, n = 0.0, er = 0.0;
         for (int t = threadIdx.x; t < nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
@@ -371,9 +623,10 @@ void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t 
             else hipLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(64 * kSpmvWaves), 0, st, b);
             break;
         case kStUpdate:
-            if (b.wide) hipLaunchKernelGGL(k_pcg_update<2>, dim3(grid), dim3(kSolveBlock), 0, st, b);
-            else hipLaunchKernelGGL(k_pcg_update<1>, dim3(grid), dim3(kSolveBlock), 0, st, b);
+            if (b.wide) hipLaunchKernelGGL(k_pcg_finish<2>, dim3(grid), dim3(kSolveBlock), 0, st, b);
+            else hipLaunchKernelGGL(k_pcg_finish<1>, dim3(grid), dim3(kSolveBlock), 0, st, b);
             break;
+        case kStPcgStep: hipLaunchKernelGGL(k_pcg_step, dim3(grid), dim3(kStepBlock), 0, st, b); break;
         case kStNodeUpdate: hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
         case kStStatsOut:
             hipLaunchKernelGGL(k_stats_out, dim3(grid), dim3(64), 0, st, b, static_cast<char*>(stats_out));

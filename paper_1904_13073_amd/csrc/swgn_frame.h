@@ -25,13 +25,20 @@ constexpr int kMaxPcg = 4096;
 constexpr int kDepthTile = 16;        // 16 x 16 pixels per workgroup
 constexpr int kWarpBlock = 256;       // surfels per workgroup
 constexpr int kCorrBlock = 256;
+// Surfels per correspondence pack (and at most per segment): small enough that
+// the pack's Jacobian rows and output staging stay under 32 KB of LDS, so five
+// workgroups share a CU.
+constexpr int kCorrPack = 232;
 constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
-constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes; the update may take 2 nodes per lane group
+constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes; the finish may take 2 nodes per lane group
+constexpr int kSolveNodes = 32;       // nodes per initialisation / finishing workgroup
 constexpr int kSpmvWaves = 4;         // product workgroup: 4 waves of 1 or 2 block rows each
-// Partial sums of the PCG dot products are taken per 32 nodes (r.z, r.r) and
-// per 4 block rows (p.q), whatever the launch geometry, so every reduction
-// has one fixed shape.
-constexpr int kSolvePart = 32;
+constexpr int kStepNodes = 8;         // fused PCG step: 8 nodes (one finishing wave) and their 8 rows
+constexpr int kStepBlock = 64 * kStepNodes;
+// Partial sums of the PCG dot products are taken per 8 nodes (r.z, r.r: one
+// wave's sum) and per 4 block rows (the three products that give p.q),
+// whatever the launch geometry, so every reduction has one fixed shape.
+constexpr int kSolvePart = 8;
 constexpr int kSpmvPart = 4;
 constexpr int kNodeBlock = 256;
 constexpr int kRigidSurfels = 1024;   // surfels per rigid-system workgroup (4 per thread)
@@ -50,7 +57,7 @@ constexpr int kRigidSums = 29;
 struct FrameDesc {
     // shapes
     int ns, nn, nb, noff, nseg, pitch, npx, ell_w;
-    int npack;                    // packs: consecutive whole segments, at most kCorrBlock surfels
+    int npack;                    // packs: consecutive whole segments, at most kCorrPack surfels
     int64_t part_floats;          // floats of all segments' Gram sub-blocks
     int pcg_iters, debug_iter;
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
@@ -94,8 +101,15 @@ struct FrameDesc {
     double* Minv;                 // [nn][36] block-Jacobi inverses
     double* part_e;               // correspondence pass partials
     int* part_n;
-    float *x, *r, *z, *q, *p0, *p1;
-    double *sc, *part_rho, *part_rr, *part_pq;
+    // PCG: the step x; residual r, preconditioned residual z, direction p and
+    // the products u = A z, v = A p_prev, each in two buffers by iteration
+    // parity (a fused step reads one while it writes the other); FP64 partial
+    // sums, also by parity: r.z and r.r per 8 nodes, z.u, z.v + p.u and p.v
+    // per 4 rows; sc = rho of the last two iterations
+    float* x;
+    float *r[2], *z[2], *p[2], *u[2], *v[2];
+    double* sc;
+    double *part_rho[2], *part_rr[2], *part_c[2];
     // rigid alignment: the transform (R row-major, t) as used by the warp
     // kernels and in FP64 for the updates, per-tile partials of the 6x6
     // system, per-step statistics
@@ -106,23 +120,30 @@ struct FrameDesc {
 };
 
 // Tiles (workgroups) of each per-frame stage for one stream.
+// kStSpmv forms the products of a PCG iteration, kStUpdate finishes one,
+// kStPcgStep does both in one launch (finish of iteration i - 1, products of i).
 enum Stage {
     kStDepth = 0, kStWarp, kStCorr, kStAsmSeg, kStPcgInit, kStSpmv, kStUpdate, kStNodeUpdate, kStAsmFold,
-    kStRigidWarp, kStRigidSys, kStRigidSolve, kStRigidCompose, kStStatsOut, kNumStages
+    kStRigidWarp, kStRigidSys, kStRigidSolve, kStRigidCompose, kStPcgStep, kStStatsOut, kNumStages
 };
-// timing slot (sw_frame_stats.stage_us) of each stage
-inline int stage_slot(int stage) { return stage < kStRigidCompose ? stage : 11; }
+// timing slot (sw_frame_stats.stage_us) of each stage; fused PCG steps take
+// slot 3 (the segment stage has no launch of its own)
+inline int stage_slot(int stage) { return stage == kStPcgStep ? kStAsmSeg : stage < kStRigidCompose ? stage : 11; }
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int corr_tiles(const FrameDesc& d) { return d.npack; }
 __host__ __device__ inline int solve_parts(const FrameDesc& d) { return cdiv(d.nn, kSolvePart); }
+__host__ __device__ inline int solve_tiles(const FrameDesc& d) { return cdiv(d.nn, kSolveNodes); }
 __host__ __device__ inline int spmv_parts(const FrameDesc& d) { return cdiv(d.nn, kSpmvPart); }
 
 // Launch variant of a stage: bit 0 = tile order (kOrderXcd), bit 1 = the
 // wider geometry of the stage where it has one (2 block rows per product
-// wave, 2 nodes per update lane group). No variant changes any arithmetic.
+// wave, 2 nodes per finishing lane group), bit 2 (on kStSpmv) = PCG iterations
+// as fused steps instead of product + finish launches. No variant changes any
+// arithmetic.
 constexpr int kVarXcd = 1;
 constexpr int kVarWide = 2;
+constexpr int kVarFused = 4;
 
 inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
     switch (stage) {
@@ -135,9 +156,10 @@ inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
         case kStCorr: return corr_tiles(d);
         case kStAsmSeg: return 0;     // the segment Gram matrices are formed by the correspondence kernel
         case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
-        case kStPcgInit: return cdiv(d.nn, kSolvePart);
+        case kStPcgInit: return solve_tiles(d);
         case kStSpmv: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSpmvWaves : kSpmvWaves);
-        case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolvePart : kSolvePart);
+        case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolveNodes : kSolveNodes);
+        case kStPcgStep: return cdiv(d.nn, kStepNodes);
         case kStNodeUpdate: return cdiv(d.nn > d.npx ? d.nn : d.npx, kNodeBlock);
         case kStRigidWarp: return cdiv(d.ns, kWarpBlock);
         case kStRigidSys: return cdiv(d.ns, kRigidSurfels);
@@ -151,7 +173,8 @@ inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
 // Work list of one launch, passed by value as a kernel argument.
 struct Batch {
     int n;                        // streams
-    int pcg_it;                   // PCG iteration of this launch
+    int pcg_it;                   // PCG iteration of this launch (products of it; finish of it, or of
+                                  // it - 1 in a fused step)
     int order;                    // kOrderXcd: tiles in XCD-contiguous order
     int wide;                     // the stage's wider geometry (kVarWide)
     int off[kMaxBatch + 1];       // stream s owns tiles [off[s], off[s+1])

@@ -88,6 +88,8 @@ SW_EPENDING = 1
 
 SW_BATCH_TIMING = 1
 SW_BATCH_GRAPH = 2
+SW_BATCH_PCG_SPLIT = 4
+SW_BATCH_PCG_FUSED = 8
 
 
 def lib() -> C.CDLL:
@@ -255,8 +257,15 @@ def sw_solve_batch(b, handles, depths, with_stats: bool = True, raise_numeric: b
 class Batch:
     """A batch executor: solves one frame for each of several Streams per call."""
 
-    def __init__(self, hip_stream: Optional[int] = None, timing: bool = False, graph: bool = False):
-        self.h = sw_create_batch(hip_stream, (SW_BATCH_TIMING if timing else 0) | (SW_BATCH_GRAPH if graph else 0))
+    def __init__(self, hip_stream: Optional[int] = None, timing: bool = False, graph: bool = False,
+                 pcg: str = "auto"):
+        """pcg: "auto" (chosen per batch shape), "split" (a product and a finish
+        launch per PCG iteration) or "fused" (one fused step per iteration)."""
+        modes = {"auto": 0, "split": SW_BATCH_PCG_SPLIT, "fused": SW_BATCH_PCG_FUSED}
+        if pcg not in modes:
+            raise ValueError(f"pcg must be one of {sorted(modes)}")
+        self.h = sw_create_batch(hip_stream, (SW_BATCH_TIMING if timing else 0) | (SW_BATCH_GRAPH if graph else 0)
+                                 | modes[pcg])
 
     def close(self):
         if self.h:
@@ -274,7 +283,8 @@ class Batch:
 
     def autotune(self, streams, reps: int = 20):
         """Pick each stage's launch variant for this batch's shape bucket; returns the 12
-        choices (bit 0: XCD-contiguous tile order, bit 1: 2 rows / nodes per wave or group)."""
+        choices (bit 0: XCD-contiguous tile order, bit 1: 2 rows / nodes per wave or group,
+        bit 2 of entry 5: fused PCG steps)."""
         n = len(streams)
         hs = (C.c_void_p * n)(*[s.h.value for s in streams])
         out = (C.c_int32 * 12)()

@@ -71,8 +71,10 @@ def test_batch_entry_points_validate_on_the_host():
     from paper_1904_13073_amd import swgn
     L = swgn.lib()
     h = C.c_void_p()
-    assert L.sw_create_batch(None, 4, C.byref(h)) == swgn.SW_EINVAL and not h.value
+    assert L.sw_create_batch(None, 16, C.byref(h)) == swgn.SW_EINVAL and not h.value
     both = swgn.SW_BATCH_TIMING | swgn.SW_BATCH_GRAPH       # timing and graph replay exclude each other
+    assert L.sw_create_batch(None, both, C.byref(h)) == swgn.SW_EINVAL and not h.value
+    both = swgn.SW_BATCH_PCG_SPLIT | swgn.SW_BATCH_PCG_FUSED   # one PCG schedule or the other
     assert L.sw_create_batch(None, both, C.byref(h)) == swgn.SW_EINVAL and not h.value
     assert L.sw_create_batch(None, 0, None) == swgn.SW_EINVAL
     assert L.sw_destroy_batch(None) == 0

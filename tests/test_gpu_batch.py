@@ -198,3 +198,31 @@ def test_autotuned_tile_order_changes_no_result(swgn, scene_cache):
     for st in sts:
         st.close()
     b.close()
+
+
+def test_fused_and_split_pcg_schedules_agree_bit_for_bit(swgn, scene_cache):
+    """One fused launch per PCG iteration (finish of i - 1 + products of i,
+    columns' z and p formed in place) and a product + finish launch per
+    iteration run the same operations: results are identical, with uneven
+    PCG counts (a stream's last finish rides along with others' steps) and
+    the 0 and 1 iteration cases."""
+    scenes = _scenes(scene_cache, MIX[:4])
+    cfgs = [dict(pcg_iters=7), dict(pcg_iters=10), dict(pcg_iters=1), dict(gn_iters=3, pcg_iters=0)]
+    frames = [[s.depth for s in scenes]] * 2
+    out = {}
+    for mode in ("split", "fused"):
+        sts = [stream_for(swgn, sc, **cfgs[i]) for i, sc in enumerate(scenes)]
+        b = swgn.Batch(pcg=mode)
+        stats = [[] for _ in scenes]
+        for depths in frames:
+            res, status = b.solve(sts, depths)
+            assert status == [swgn.SW_OK] * len(sts), mode
+            for i in range(len(sts)):
+                stats[i].append(res[i])
+        out[mode] = ([st.node_se3() for st in sts], stats)
+        for st in sts:
+            st.close()
+        b.close()
+    _assert_same(*out["split"], *out["fused"])
+    solo = _solo(swgn, scenes, frames, cfgs)
+    _assert_same(*solo, *out["split"])
