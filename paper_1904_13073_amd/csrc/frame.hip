@@ -121,7 +121,36 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
 // column 31 runs into the next row (or the slack after the last one) and
 // only feeds Gram entries with an index of 31, which are discarded.
 constexpr int kRowPad = 31;
-constexpr int kStageFloats = 288;    // per wave: the segment's output is staged in two halves
+constexpr int kStageFloats = 576;    // per wave: a segment's whole output (at most 36 x 15 + 32 floats)
+
+// Code of accumulator element t of lane l in a segment's Gram tile (element
+// G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4): for a node-pair
+// block (i, j < 30, pa = i / 6 <= pb = j / 6) its pair bit
+// 5 pa - pa (pa - 1) / 2 + pb - pa (bits 0-3) and its position
+// (i % 6) * 6 + j % 6 in the 6x6 sub-block (bits 4-9); for J^T r and r^T r
+// (j = 30, i <= 30) bit field 15 and i; 0xffff for elements not kept.
+struct GramCodes {
+    uint16_t c[kWave][16];
+};
+
+constexpr GramCodes make_gram_codes() {
+    GramCodes g{};
+    for (int l = 0; l < kWave; ++l)
+        for (int t = 0; t < 16; ++t) {
+            const int i = (t / 4) * 8 + (l / 32) * 4 + t % 4, j = l % 32;
+            uint16_t code = 0xffff;
+            if (i < 30 && j < 30) {
+                const int pa = i / 6, pb = j / 6;
+                if (pa <= pb) code = (uint16_t)((5 * pa - pa * (pa - 1) / 2 + pb - pa) | (((i % 6) * 6 + j % 6) << 4));
+            } else if (j == 30 && i <= 30) {
+                code = (uint16_t)(15 | (i << 4));
+            }
+            g.c[l][t] = code;
+        }
+    return g;
+}
+
+__constant__ GramCodes kGramCodes = make_gram_codes();
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -194,10 +223,10 @@ __device__ __forceinline__ float keep_jac(float v, int dtype) {
     return v;
 }
 
-__global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
+__global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
-    __shared__ float rows[kCorrBlock * kRowPad + 8];
+    __shared__ float rows[kCorrPack * kRowPad + 8];
     __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
@@ -243,8 +272,9 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
             }
         }
     }
-    {
+    if (threadIdx.x < kCorrPack) {
         // the row: node block k at its node's position in the segment
+        // (threads past the pack capacity are never live and keep no row)
         float* row = &rows[threadIdx.x * kRowPad];
         const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
         const int jd = d.jac_dtype;          // uniform: one branch for the whole row
@@ -274,10 +304,11 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
                 for (int c = 0; c < 6; ++c) row[pos * 6 + c] = 0.f;
             }
         row[30] = r;
-        if (threadIdx.x == kCorrBlock - 1) {
+    }
+    if (threadIdx.x == kCorrBlock - 1) {
+        // read (as column 31, whose products are dropped) past the last row
 #pragma unroll
-            for (int c = 0; c < 8; ++c) rows[kCorrBlock * kRowPad + c] = 0.f;
-        }
+        for (int c = 0; c < 8; ++c) rows[kCorrPack * kRowPad + c] = 0.f;
     }
     if (live && capture) {
         float nanv = __int_as_float(0x7fc00000);
@@ -311,6 +342,7 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
     const int comp = lane & 31, half = lane >> 5;
     const int g0 = d.pack_seg[at.tile], g1 = d.pack_seg[at.tile + 1];
     float* sg = reinterpret_cast<float*>(stage4[wave]);
+    const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
         const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
         f32x16 acc;
@@ -328,42 +360,31 @@ __global__ void __launch_bounds__(kCorrBlock) k_corr_gram(Batch b) {
         }
         // output slot of each accumulator element: the rank of its node pair
         // among the segment's pairs x 36 + position in the 6x6 sub-block;
-        // J^T r and r^T r after the sub-blocks
+        // J^T r and r^T r after the sub-blocks. The whole output is staged in
+        // LDS and stored as whole lines.
         const uint32_t mask = d.seg_mask[seg];
         const int npair = __builtin_popcount(mask);
         const int size = 36 * npair + 32;
-        int slot[16];
+        const uint4 q0 = codes[0], q1 = codes[1];
+        const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            const int ii = (t >> 2) * 8 + half * 4 + (t & 3), j = comp;
-            int sl = -1;
-            if (ii < 30 && j < 30) {
-                const int pa = ii / 6, pb = j / 6;
-                if (pa <= pb) {
-                    const int bit = 5 * pa - (pa * (pa - 1)) / 2 + (pb - pa);
-                    if ((mask >> bit) & 1u)
-                        sl = 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (ii % 6) * 6 + (j % 6);
-                }
-            } else if (j == 30 && ii <= 30) {
-                sl = 36 * npair + ii;            // J^T r (ii < 30), r^T r (ii = 30)
-            }
-            slot[t] = sl;
+            const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+            const uint32_t bit = code & 15u, off = code >> 4;
+            const bool tail = bit == 15u;
+            const bool keep = code != 0xffffu && (tail || ((mask >> bit) & 1u));
+            const int sl = tail ? 36 * npair + (int)off
+                                : 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (int)off;
+            if (keep) sg[sl] = acc[t];
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
-        for (int h0 = 0; h0 < size; h0 += kStageFloats) {
-            // staged in LDS, stored as whole lines
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (slot[t] >= h0 && slot[t] < h0 + kStageFloats) sg[slot[t] - h0] = acc[t];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int n4 = min(kStageFloats, size - h0) / 4;
-            for (int q = lane; q < n4; q += kWave) out[h0 / 4 + q] = stage4[wave][q];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
+        for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
