@@ -79,12 +79,28 @@ def warp_surfels(pb: Problem, R: np.ndarray, t: np.ndarray):
     return dict(r=r, d=d, c=c, b=b, s=s, v=v, n=n, valid=valid)
 
 
-def linearize(pb: Problem, R: np.ndarray, t: np.ndarray) -> Dict:
+def linearize(pb: Problem, R: np.ndarray, t: np.ndarray, corr_map: Optional[np.ndarray] = None) -> Dict:
     """Residuals, Jacobians and energies at the current transforms, with the
-    association re-done at this state."""
+    association re-done at this state.
+
+    corr_map (H,W; surfel index or -1), when given, supplies the
+    correspondences instead: surfel i is matched to the pixel that holds i.
+    This is for comparing arithmetic with an implementation whose FP32
+    decisions fell the other way at a near-tie (a projection on a pixel
+    boundary, a gate at its threshold); the association itself is the one
+    decided here."""
     ws = warp_surfels(pb, R, t)
     I, m, ux, uy = assoc.associate(ws["v"], ws["n"], ws["valid"], pb.frame, pb.cam,
                                    pb.corr_dist, pb.corr_normal)
+    if corr_map is not None:
+        cm = np.asarray(corr_map).ravel()
+        pix = np.flatnonzero(cm >= 0)
+        m = np.zeros_like(m)
+        ux, uy = ux.copy(), uy.copy()
+        W = pb.cam.width
+        m[cm[pix]] = True
+        ux[cm[pix]] = pix % W
+        uy[cm[pix]] = pix // W
     ci = np.flatnonzero(m)
     Vd = pb.V64[uy[ci], ux[ci]]
     Nd = pb.N64[uy[ci], ux[ci]]
@@ -198,21 +214,22 @@ def update_nodes(node_pos: np.ndarray, R: np.ndarray, t: np.ndarray, delta: np.n
 
 def gn_solve(pb: Problem, se3_init: np.ndarray, gn_iters: int, pcg_iters: Optional[int] = 10,
              linear: str = "pcg", final_energy: bool = False, keep: Optional[List[int]] = None,
-             rigid_iters: int = 0):
+             rigid_iters: int = 0, corr_maps: Optional[List[np.ndarray]] = None):
     """Run exactly gn_iters Gauss-Newton iterations from se3_init (after
     rigid_iters steps of rigid alignment composed into the nodes, see rigid.py).
 
     linear = "chol" solves each step exactly (dense Cholesky), "pcg" runs
     block-Jacobi PCG for pcg_iters iterations. Returns the final (Nn,12) [R|t]
     and a trace with the energies, correspondence counts and, for iterations
-    listed in `keep`, the full linearisation."""
+    listed in `keep`, the full linearisation. corr_maps[it], when given,
+    supplies iteration it's correspondences (see linearize)."""
     R, t = se3_to_rt(se3_init)
     trace: Dict = dict(e_data=[], e_reg=[], n_corr=[], pcg_resid=[], lin={}, steps=[])
     if rigid_iters > 0:
         Rc, tc, trace["rigid"] = rigid.rigid_align(pb, warp_surfels(pb, R, t), rigid_iters, pb.damping)
         R, t = rigid.compose(R, t, Rc, tc)
     for it in range(gn_iters):
-        lin = linearize(pb, R, t)
+        lin = linearize(pb, R, t, None if corr_maps is None else corr_maps[it])
         trace["e_data"].append(lin["e_data"])
         trace["e_reg"].append(lin["e_reg"])
         trace["n_corr"].append(int(lin["corr_idx"].size))

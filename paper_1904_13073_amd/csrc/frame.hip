@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ float rows[kCorrPack * kRowPad + 8];
     __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
-    const FrameDesc d = *b.d[at.s];
+    const FrameDesc& d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
     const int p0 = d.pack_start[at.tile], p1 = d.pack_start[at.tile + 1];
     const int i = p0 + (int)threadIdx.x;
@@ -241,36 +241,32 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) { Jw[k][c] = 0.f; Jt[k][c] = 0.f; }
-    bool matched = false;
-    int4 id = make_int4(0, 1, 2, 3);
-    int pix = 0, org = 0;
-    Warp wp;
-    wp.ok = false;
-    if (live) {
-        id = d.idx[i];
-        org = d.orig[i];
-        const float4 w4 = d.w[i];
-        float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
-        float3 n = make_float3(d.nx[i], d.ny[i], d.nz[i]);
-        wp = warp_surfel(id, w4, v, n, d.dq);
-        int ux, uy;
-        if (wp.ok && project(d.cam, wp.v, ux, uy)) {
-            pix = uy * d.cam.W + ux;
-            if (d.zbuf[pix] == zkey(wp.v.z, org)) {
-                float4 nm = d.nmap[pix];
-                if (nm.w > 0.f) {
-                    float3 V = backproject(d.cam, ux, uy, nm.w);
-                    float3 dv = sub3(wp.v, V);
-                    float d2 = (dv.x * dv.x + dv.y * dv.y) + dv.z * dv.z;
-                    float3 N = make_float3(nm.x, nm.y, nm.z);
-                    if (d2 < d.dist2 && dot3(wp.n, N) > d.cosn) {
-                        matched = true;
-                        r = dot3(N, dv);
-                        jacobian_rows(d, id, w4, v, N, wp, Jw, Jt);
-                    }
-                }
-            }
-        }
+    // the match decisions as one predicate (no nested branches, so the zero
+    // rows of unmatched lanes are formed once); lanes past the pack take its
+    // last surfel and are masked, lanes that fail early read pixel 0
+    const int ic = live ? i : p1 - 1;
+    const int4 id = d.idx[ic];
+    const int org = d.orig[ic];
+    const float4 w4 = d.w[ic];
+    const float3 v = make_float3(d.px[ic], d.py[ic], d.pz[ic]);
+    const float3 n = make_float3(d.nx[ic], d.ny[ic], d.nz[ic]);
+    const Warp wp = warp_surfel(id, w4, v, n, d.dq);
+    int ux, uy;
+    const bool in = project(d.cam, wp.v, ux, uy);
+    bool ok = live & wp.ok & in;
+    const int pix = ok ? uy * d.cam.W + ux : 0;
+    const unsigned long long zb = d.zbuf[pix];
+    ok = ok & (zb == zkey(wp.v.z, org));
+    const float4 nm = d.nmap[pix];
+    ok = ok & (nm.w > 0.f);
+    const float3 V = backproject(d.cam, ux, uy, nm.w);
+    const float3 dv = sub3(wp.v, V);
+    const float d2 = (dv.x * dv.x + dv.y * dv.y) + dv.z * dv.z;
+    const float3 N = make_float3(nm.x, nm.y, nm.z);
+    const bool matched = ok & (d2 < d.dist2) & (dot3(wp.n, N) > d.cosn);
+    if (matched) {
+        r = dot3(N, dv);
+        jacobian_rows(d, id, w4, v, N, wp, Jw, Jt);
     }
     if (threadIdx.x < kCorrPack) {
         // the row: node block k at its node's position in the segment

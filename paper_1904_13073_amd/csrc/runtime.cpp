@@ -80,7 +80,7 @@ int Executor::variant_of(int stage, int64_t rows) const {
     if (it != tuned.end()) return it->second[stage];
     // untuned: the wide geometries only when the launch still has two
     // workgroups per CU with them
-    const bool wide = (stage == kStSpmv && rows >= 256 * 2 * 2 * kSpmvWaves) ||
+    const bool wide = (stage == kStSpmv && rows >= 256 * 2 * kSpmvRows) ||
                       (stage == kStUpdate && rows >= 256 * 2 * 2 * kSolveNodes);
     // fused PCG steps while the product launch is too small to fill the chip
     const bool fused = stage == kStSpmv && rows <= kFusedRows;
@@ -140,14 +140,15 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.part_n, 4 * ncor);
     take(h.x, 24 * nn);
     for (int q = 0; q < 2; ++q) {
-        take(h.r[q], 24 * nn);
-        take(h.z[q], 24 * nn);
-        take(h.p[q], 24 * nn);
-        take(h.u[q], 24 * nn);
-        take(h.v[q], 24 * nn);
-        take(h.part_rho[q], 8 * nsol);
-        take(h.part_rr[q], 8 * nsol);
-        take(h.part_c[q], 3 * 8 * nspm);
+        auto half = [q](auto& pp) -> auto& { return q ? pp.b1 : pp.b0; };
+        take(half(h.r), 24 * nn);
+        take(half(h.z), 24 * nn);
+        take(half(h.p), 24 * nn);
+        take(half(h.u), 24 * nn);
+        take(half(h.v), 24 * nn);
+        take(half(h.part_rho), 8 * nsol);
+        take(half(h.part_rr), 8 * nsol);
+        take(half(h.part_c), 3 * 8 * nspm);
     }
     take(h.sc, 16);
     take(h.rig, 12 * 4);

@@ -34,13 +34,6 @@ namespace swgn {
 
 namespace {
 
-// One of a pair of buffers kept by iteration parity. (A select of the two
-// pointers: indexing the descriptor's arrays with a run-time value would put
-// the descriptor copy in scratch memory.)
-template <class T>
-__device__ __forceinline__ T* by_parity(T* const (&pair)[2], int q) {
-    return (q & 1) ? pair[1] : pair[0];
-}
 
 __device__ void update_node(const FrameDesc& a, int k) {
     const float* x = a.x + 6 * k;
@@ -122,9 +115,9 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     if (on) {
         const float zf = (float)zc;
         const int t = 6 * k + row;
-        a.r[0][t] = rc;
-        a.z[0][t] = zf;
-        a.p[1][t] = 0.f;
+        a.r.b0[t] = rc;
+        a.z.b0[t] = zf;
+        a.p.b1[t] = 0.f;
         a.x[t] = 0.f;
         rho = (double)rc * (double)zf;
         rr = (double)rc * (double)rc;
@@ -134,8 +127,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     rr = wave_sum(rr);
     const int part = gid / kWave;
     if (lane == 0 && part < solve_parts(a)) {
-        a.part_rho[0][part] = rho;
-        a.part_rr[0][part] = rr;
+        a.part_rho.b0[part] = rho;
+        a.part_rr.b0[part] = rr;
     }
 }
 
@@ -253,7 +246,7 @@ template <int NPG>
 __global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
     __shared__ double sh[40];
     const Where at = locate(b);
-    const FrameDesc& a = *b.d[at.s];
+    const FrameDesc a = *b.d[at.s];
     const int k = b.pcg_it, cur = k & 1, nxt = cur ^ 1;
     const int c = threadIdx.x & 7, base = threadIdx.x & ~7;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -446,30 +439,27 @@ __device__ __forceinline__ RowProducts store_row(const FrameDesc& a, int i, int 
     return RowProducts{wave_sum(c1), wave_sum(c2), wave_sum(c3)};
 }
 
-// Partials per 4 rows, each the in-order sum of its rows' products.
-__device__ __forceinline__ void store_row_parts(const FrameDesc& a, int i, int quad0, int nquads,
-                                                const double (*rs)[3]) {
-    if ((int)threadIdx.x < 3 * nquads) {
-        const int q = threadIdx.x / 3, m = threadIdx.x % 3;
-        const int quad = quad0 + q;
-        if (quad < spmv_parts(a)) {
-            double t = 0.0;
-            for (int w = 0; w < 4; ++w) t += rs[4 * q + w][m];
-            by_parity(a.part_c, i & 1)[m * spmv_parts(a) + quad] = t;
-        }
+// Partial of a workgroup's 8 rows (kSpmvPart): the in-order sum of its rows'
+// products, one value for each of the three.
+__device__ __forceinline__ void store_row_parts(const FrameDesc& a, int i, int part, const double (*rs)[3]) {
+    if (threadIdx.x < 3 && part < spmv_parts(a)) {
+        const int m = threadIdx.x;
+        double t = 0.0;
+        for (int w = 0; w < kSpmvPart; ++w) t += rs[w][m];
+        by_parity(a.part_c, i & 1)[m * spmv_parts(a) + part] = t;
     }
 }
 
 // Products of iteration i = b.pcg_it from z_i and p_{i-1} as stored; one
-// workgroup = 4 waves of RPW block rows each.
+// workgroup = 8 block rows, 8 / RPW waves of RPW rows each.
 template <int RPW>
-__global__ void __launch_bounds__(64 * kSpmvWaves) k_pcg_spmv(Batch b) {
-    __shared__ double rs[kSpmvWaves * RPW][3];
+__global__ void __launch_bounds__(64 * kSpmvRows / RPW) k_pcg_spmv(Batch b) {
+    __shared__ double rs[kSpmvRows][3];
     const Where at = locate(b);
-    const FrameDesc& a = *b.d[at.s];
+    const FrameDesc a = *b.d[at.s];
     const int i = b.pcg_it;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int k0 = at.tile * kSpmvWaves * RPW + RPW * wave;
+    const int k0 = at.tile * kSpmvRows + RPW * wave;
     RowAcc ra[RPW];
 #pragma unroll
     for (int g = 0; g < RPW; ++g) {
@@ -493,7 +483,7 @@ __global__ void __launch_bounds__(64 * kSpmvWaves) k_pcg_spmv(Batch b) {
         }
     }
     __syncthreads();
-    store_row_parts(a, i, at.tile * RPW, RPW, rs);
+    store_row_parts(a, i, at.tile, rs);
 }
 
 // One fused PCG step i = b.pcg_it >= 1 over 8 nodes: wave 0 finishes iteration
@@ -506,7 +496,7 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
     __shared__ double rs[kStepNodes][3];
     __shared__ float own_z[kStepNodes * 8], own_p[kStepNodes * 8];
     const Where at = locate(b);
-    const FrameDesc& a = *b.d[at.s];
+    const FrameDesc a = *b.d[at.s];
     const int i = b.pcg_it, k = i - 1, cur = k & 1, nxt = cur ^ 1;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int n0 = at.tile * kStepNodes;
@@ -565,27 +555,43 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
         rs[wave][2] = rp.c3;
     }
     __syncthreads();
-    store_row_parts(a, i, n0 / kSpmvPart, kStepNodes / kSpmvPart, rs);
+    store_row_parts(a, i, n0 / kSpmvPart, rs);
 }
 
 __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
-    __shared__ double sh[40];
+    __shared__ double sh[4 * (kNodeBlock / kWave)];
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
     const int gid = at.tile * kNodeBlock + threadIdx.x;
     if (gid < a.nn) update_node(a, gid);
     if (gid < a.npx) a.zbuf[gid] = ~0ull;     // index map of the next iteration
     if (at.tile == 0) {
+        // energies at this iteration's linearisation point and |r| of the
+        // last PCG residual: each a strided per-thread sum, then the wave
+        // sums, then the 4 waves in order, all four in one pass
         const int nparts = corr_tiles(a);
         IterStats* stats = a.stats + b.it[at.s];
-        const double rr = reduce_partials(by_parity(a.part_rr, a.pcg_iters & 1), solve_parts(a), sh);   // of r_{pcg_iters}
-        // energies at this iteration's linearisation point
-        double e = 0.0, n = 0.0, er = 0.0;
-        for (int t = threadIdx.x; t < nparts; t += blockDim.x) { e += a.part_e[t]; n += (double)a.part_n[t]; }
-        for (int t = threadIdx.x; t < a.nn; t += blockDim.x) er += (double)a.ereg[t];
-        e = block_sum(e, sh);
-        n = block_sum(n, sh);
-        er = block_sum(er, sh);
+        const double* prr = by_parity(a.part_rr, a.pcg_iters & 1);
+        double v[4] = {0.0, 0.0, 0.0, 0.0};     // e, n, e_reg, r.r
+#pragma unroll 4
+        for (int t = threadIdx.x; t < nparts; t += kNodeBlock) { v[0] += a.part_e[t]; v[1] += (double)a.part_n[t]; }
+#pragma unroll 4
+        for (int t = threadIdx.x; t < a.nn; t += kNodeBlock) v[2] += (double)a.ereg[t];
+#pragma unroll 4
+        for (int t = threadIdx.x; t < solve_parts(a); t += kNodeBlock) v[3] += prr[t];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
+        const int w = threadIdx.x / kWave;
+        if ((threadIdx.x % kWave) == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) sh[4 * w + m] = v[m];
+        }
+        __syncthreads();
+        double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        if (threadIdx.x == 0)
+            for (int q = 0; q < kNodeBlock / kWave; ++q)
+                for (int m = 0; m < 4; ++m) tot[m] += sh[4 * q + m];
+        const double e = tot[0], n = tot[1], er = tot[2], rr = tot[3];
         if (threadIdx.x == 0) {
             stats->pcg_resid = sqrt(rr);
             stats->e_data = e;
@@ -619,8 +625,8 @@ void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t 
     switch (stage) {
         case kStPcgInit: hipLaunchKernelGGL(k_pcg_init, dim3(grid), dim3(kSolveBlock), 0, st, b); break;
         case kStSpmv:
-            if (b.wide) hipLaunchKernelGGL(k_pcg_spmv<2>, dim3(grid), dim3(64 * kSpmvWaves), 0, st, b);
-            else hipLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(64 * kSpmvWaves), 0, st, b);
+            if (b.wide) hipLaunchKernelGGL(k_pcg_spmv<2>, dim3(grid), dim3(64 * kSpmvRows / 2), 0, st, b);
+            else hipLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(64 * kSpmvRows), 0, st, b);
             break;
         case kStUpdate:
             if (b.wide) hipLaunchKernelGGL(k_pcg_finish<2>, dim3(grid), dim3(kSolveBlock), 0, st, b);

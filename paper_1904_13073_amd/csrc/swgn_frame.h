@@ -32,14 +32,16 @@ constexpr int kCorrPack = 232;
 constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
 constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes; the finish may take 2 nodes per lane group
 constexpr int kSolveNodes = 32;       // nodes per initialisation / finishing workgroup
-constexpr int kSpmvWaves = 4;         // product workgroup: 4 waves of 1 or 2 block rows each
+constexpr int kSpmvRows = 8;          // product workgroup: 8 block rows, 8 waves of 1 or 4 waves of 2
 constexpr int kStepNodes = 8;         // fused PCG step: 8 nodes (one finishing wave) and their 8 rows
 constexpr int kStepBlock = 64 * kStepNodes;
 // Partial sums of the PCG dot products are taken per 8 nodes (r.z, r.r: one
-// wave's sum) and per 4 block rows (the three products that give p.q),
+// wave's sum) and per 8 block rows (the three products that give p.q),
 // whatever the launch geometry, so every reduction has one fixed shape.
 constexpr int kSolvePart = 8;
-constexpr int kSpmvPart = 4;
+constexpr int kSpmvPart = 8;
+static_assert(kSpmvRows == kSpmvPart && kStepNodes == kSpmvPart && kStepNodes == kSolvePart,
+              "a product or fused-step workgroup writes exactly one partial of each kind");
 constexpr int kNodeBlock = 256;
 constexpr int kRigidSurfels = 1024;   // surfels per rigid-system workgroup (4 per thread)
 
@@ -53,6 +55,24 @@ struct RigidStats {
 // Sums per tile of the rigid alignment: 21 entries of the upper 6x6 J^T J,
 // 6 of J^T r, r^T r and the correspondence count.
 constexpr int kRigidSums = 29;
+
+// Two buffers used by iteration parity. Named members rather than an array:
+// a kernel's copy of the descriptor then stays in scalar registers when the
+// parity is a run-time value (a select, not an indexed load).
+template <class T>
+struct ParityPair {
+    T* b0;
+    T* b1;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ T* by_parity(const ParityPair<T>& pp, int q) {
+    // both pointers are read, then one is chosen by a mask (no address select
+    // into the descriptor)
+    const uintptr_t x0 = reinterpret_cast<uintptr_t>(pp.b0), x1 = reinterpret_cast<uintptr_t>(pp.b1);
+    const uintptr_t m = uintptr_t(0) - uintptr_t(q & 1);
+    return reinterpret_cast<T*>((x0 & ~m) | (x1 & m));
+}
 
 struct FrameDesc {
     // shapes
@@ -107,9 +127,9 @@ struct FrameDesc {
     // sums, also by parity: r.z and r.r per 8 nodes, z.u, z.v + p.u and p.v
     // per 4 rows; sc = rho of the last two iterations
     float* x;
-    float *r[2], *z[2], *p[2], *u[2], *v[2];
+    ParityPair<float> r, z, p, u, v;
     double* sc;
-    double *part_rho[2], *part_rr[2], *part_c[2];
+    ParityPair<double> part_rho, part_rr, part_c;
     // rigid alignment: the transform (R row-major, t) as used by the warp
     // kernels and in FP64 for the updates, per-tile partials of the 6x6
     // system, per-step statistics
@@ -157,7 +177,7 @@ inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
         case kStAsmSeg: return 0;     // the segment Gram matrices are formed by the correspondence kernel
         case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
         case kStPcgInit: return solve_tiles(d);
-        case kStSpmv: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSpmvWaves : kSpmvWaves);
+        case kStSpmv: return cdiv(d.nn, kSpmvRows);
         case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolveNodes : kSolveNodes);
         case kStPcgStep: return cdiv(d.nn, kStepNodes);
         case kStNodeUpdate: return cdiv(d.nn > d.npx ? d.nn : d.npx, kNodeBlock);

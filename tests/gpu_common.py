@@ -55,3 +55,28 @@ def expected_pattern(idx, nbr, nn):
         cols.extend(cs)
         row_ptr[k + 1] = row_ptr[k] + len(cs)
     return row_ptr, np.asarray(cols)
+
+
+def solve_with_maps(swgn, scene, **cfg):
+    """One frame solve of a fresh stream, plus the correspondence map of each
+    Gauss-Newton iteration (one captured rerun per iteration, each checked to
+    end where the solve did: capturing does not change a solve)."""
+    st = stream_for(swgn, scene, **cfg)
+    stats = st.solve_frame(scene.depth)
+    got = st.node_se3()
+    st.close()
+    maps = []
+    for k in range(cfg.get("gn_iters", scene.params.gn_iters)):
+        st = stream_for(swgn, scene, debug_iter=k, **cfg)
+        st.solve_frame(scene.depth)
+        maps.append(st.last_maps()[1])
+        assert np.array_equal(st.node_se3(), got), "a captured solve ended elsewhere"
+        st.close()
+    return got, stats, maps
+
+
+def map_flips(maps, trace):
+    """Pixels where each iteration's correspondence map differs from the
+    oracle's own association (a correspondence that moved by a pixel counts
+    twice)."""
+    return [int(np.count_nonzero(m != trace["lin"][k]["corr_map"])) for k, m in enumerate(maps)]

@@ -9,7 +9,7 @@ from FP32 arithmetic; node transforms after a whole frame within 1e-4 rad and
 import numpy as np
 import pytest
 
-from gpu_common import expected_pattern, gpu_lib, se3_errors, stream_for
+from gpu_common import expected_pattern, gpu_lib, map_flips, se3_errors, solve_with_maps, stream_for
 from oracle import replica32 as R32
 from oracle import skin
 from oracle import solve as S
@@ -150,15 +150,27 @@ def test_jacobian_and_system_at_non_identity_state(tiny_gt_case):
 
 @pytest.mark.parametrize("name", ["tiny", "c1"])
 def test_frame_solve_matches_oracle_pcg(swgn, scene_cache, name):
+    """A whole frame against the FP64 oracle with the same 10-iteration PCG.
+    Association is discrete: the GPU's FP32 decisions may fall the other way
+    at a near-tie (a live point on a pixel boundary or a gate at its
+    threshold), and a weakly held node then moves visibly. So the GPU's
+    correspondences at every iteration may differ from the oracle's own in at
+    most 4 pixels (2 surfels), and the arithmetic is compared strictly with
+    the oracle run on the GPU's correspondences."""
     s = scene_cache(name)
-    st = stream_for(swgn, s)
-    stats = st.solve_frame(s.depth)
-    got = st.node_se3()
-    st.close()
-    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg")
+    G = s.params.gn_iters
+    got, stats, maps = solve_with_maps(swgn, s)
+    _, own = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
+                            keep=list(range(G)))
+    flips = map_flips(maps, own)
+    assert max(flips) <= 4, flips
+    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
+                              corr_maps=maps)
     ang, dpos = se3_errors(got, want, s.node_pos)
-    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max(), flips)
     e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
     e_ref = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
     assert np.allclose(e_gpu, e_ref, rtol=1e-4)
-    assert abs(stats["n_corr"][0] - tr["n_corr"][0]) <= 2
+    assert list(stats["n_corr"][:G]) == tr["n_corr"]
+    e_own = np.array(own["e_data"]) + s.params.lambda_reg * np.array(own["e_reg"])
+    assert np.allclose(e_gpu, e_own, rtol=1e-4)

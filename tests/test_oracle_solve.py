@@ -181,3 +181,35 @@ def test_energy_decreases_c1(scene_cache):
     err = np.abs(np.sum(nrm * (np.einsum("nij,nj->ni", R, p) + t - gt), axis=1))
     err0 = np.abs(np.sum(nrm * (p - gt), axis=1))
     assert np.median(err) < 0.3 * np.median(err0)
+
+
+def test_given_correspondences_reproduce_and_move_the_association(scene_cache):
+    """linearize with a supplied correspondence map: its own map gives the same
+    linearisation bit for bit; moving one correspondence to a neighbouring
+    pixel changes that surfel's residual only (its V and N are read there)."""
+    s = scene_cache("tiny")
+    pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
+    R, t = Q.se3_to_rt(s.gt_se3.astype(np.float64))
+    lin = S.linearize(pb, R, t)
+    same = S.linearize(pb, R, t, corr_map=lin["corr_map"])
+    for k in ("corr_idx", "r_data", "J_data", "corr_map"):
+        assert np.array_equal(same[k], lin[k]), k
+    cm = lin["corr_map"].copy()
+    H, W = cm.shape
+    nvalid = pb.frame.nvalid
+    moved = None
+    for p in np.flatnonzero(cm.ravel() >= 0):
+        y, x = divmod(int(p), W)
+        if 0 < x < W - 1 and cm[y, x + 1] < 0 and nvalid[y, x + 1]:
+            moved = (y, x, int(cm[y, x]))
+            cm[y, x + 1], cm[y, x] = cm[y, x], -1
+            break
+    assert moved is not None
+    y, x, i = moved
+    alt = S.linearize(pb, R, t, corr_map=cm)
+    assert np.array_equal(alt["corr_idx"], lin["corr_idx"])
+    k = int(np.flatnonzero(lin["corr_idx"] == i)[0])
+    d = np.flatnonzero(alt["r_data"] != lin["r_data"])
+    assert d.tolist() == [k]
+    v = lin["ws"]["v"][i]
+    assert np.isclose(alt["r_data"][k], pb.N64[y, x + 1] @ (v - pb.V64[y, x + 1]), rtol=1e-12, atol=1e-15)
