@@ -377,6 +377,23 @@ def main():
     tst.close()
     roofline, rates = stage_roofline(per_frame_us, launches, kb, replay)
 
+    # depth-map fusion after the frame's solve (one call: depth preprocessing,
+    # the 4x super-sampled index map, match and fuse; it ends in a sync)
+    fst = make_stream()
+    fst.solve_frame(depth, with_stats=False)
+    fst.fuse_frame(depth, t_now=1)
+    torch.cuda.synchronize()
+    flat = []
+    for k in range(max(5, min(50, args.steps))):
+        a = time.perf_counter()
+        fstats = fst.fuse_frame(depth, t_now=2 + k)
+        flat.append(time.perf_counter() - a)
+    fst.close()
+    fusion = {"us_per_frame": {"p50": round(1e6 * percentile(flat, 0.5), 1),
+                               "mean": round(1e6 * float(np.mean(flat)), 1)},
+              "n_fused": fstats["n_fused"], "n_candidates": fstats["n_candidates"]}
+    print(f"[bench] fusion: {fusion}", file=sys.stderr, flush=True)
+
     batched = None
     if args.batch > 0:
         B = min(args.batch, 64)
@@ -472,6 +489,7 @@ def main():
         "roofline": roofline,
         "kernel_gbs": rates,
         "n_corr": stats["n_corr"][-1],
+        "fusion": fusion,
     }
     if batched is not None:
         out["batched"] = batched

@@ -63,7 +63,21 @@ typedef struct sw_config {
                                   as in KinectFusion): projective point-to-plane ICP of one
                                   rigid transform applied after the warp field, then
                                   composed into every node; 0 = none (default), <= 16 */
+    int32_t visibility;        /* surfels rendered into the solver's index map (Sec. 7):
+                                  0 = all (default), 1 = only stable ones (confidence >
+                                  stable_conf) or recently observed ones (t_now - t_observed
+                                  <= recent_frames); unsized points either way */
+    float stable_conf;         /* delta_stable, 10 (Table 1) */
+    int32_t recent_frames;     /* delta_recent, 2 (Table 1) */
+    float fusion_dist;         /* depth fusion distance gate delta_distance, 0.001 m (Table 1) */
+    float fusion_normal;       /* depth fusion normal gate delta_normal, 0.85 (Table 1) */
 } sw_config;
+
+/* Statistics of one depth-map fusion (sw_fuse_frame). */
+typedef struct sw_fusion_stats {
+    int32_t n_fused;           /* depth surfels fused into a live surfel */
+    int32_t n_candidates;      /* pixels with a normal that found no surfel (append candidates) */
+} sw_fusion_stats;
 
 /* Per-frame statistics, one entry per Gauss-Newton iteration (<= 16). */
 typedef struct sw_frame_stats {
@@ -137,6 +151,50 @@ sw_status sw_set_node_se3(sw_stream s, const float* node_se3, int32_t n, int32_t
  * SW_ENUMERIC the transforms keep their values from before the call. */
 sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
                          sw_frame_stats* stats);
+
+/* ---- surfel attributes and depth-map fusion (Sec. 5, Sec. 6.1, Sec. 6.4) ---- */
+
+/* Radius (m), confidence and last observed frame of every surfel, in the
+ * caller's surfel order (n = the count given to sw_set_reference_surfels);
+ * any pointer may be NULL to keep that attribute. Defaults after
+ * sw_set_reference_surfels: radius 0, confidence 1, t_observed 0. Setting
+ * surfels again resets them. The data is copied. */
+sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, const float* confidence,
+                                   const int32_t* t_observed, int32_t on_device);
+
+/* Read the attributes (caller order, host arrays of n entries; NULL skips). */
+sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed);
+
+/* Read the reference surfels (n x 3 positions and normals, caller order, host):
+ * the ones given, as updated by sw_fuse_frame. */
+sw_status sw_get_reference_surfels(sw_stream s, float* pos, float* nrm);
+
+/* Current frame time t_now, used by visibility = 1 (recently observed
+ * surfels). sw_fuse_frame also sets it. */
+sw_status sw_set_frame_time(sw_stream s, int32_t t_now);
+
+/* Fuse a depth image into the surfels at the current warp field (call after
+ * sw_solve_frame on the same depth). Every pixel with a normal gives a depth
+ * surfel: position V(u), normal N(u), confidence exp(-gamma^2 / (2 * 0.6^2)),
+ * gamma = |u - c| / |c| (c the principal point), radius
+ * sqrt(2) d / (fx max(|n_z|, cos 75 deg)). The live surfels are rendered as
+ * points into an index map super-sampled 4 x 4 (nearest z, then lower
+ * index); each pixel takes the surfels of its 4 x 4 block that lie within
+ * fusion_dist of V(u) with n . N(u) >= fusion_normal, and the one with the
+ * highest confidence, then the closest, then the lowest index, receives the
+ * depth surfel: confidence adds, t_observed = t_now, position, normal
+ * (renormalised) and radius become confidence-weighted means. Fused surfels
+ * return to the reference frame through the inverse of their blended
+ * transform (skinning kept). Synchronous. stats may be NULL. SW_ESTATE
+ * without a node graph or while attached to a server. */
+sw_status sw_fuse_frame(sw_stream s, const float* depth, int32_t on_device, int32_t t_now,
+                        sw_fusion_stats* stats);
+
+/* Parity export of the last fusion: per pixel the caller index of the surfel
+ * fused there or -1 (H x W), and the live positions and normals the match
+ * used (n x 3 each, caller order; NaN positions for surfels without a valid
+ * blend). Any pointer may be NULL. SW_ESTATE before the first fusion. */
+sw_status sw_get_last_fusion(sw_stream s, int32_t* match_map, float* live_pos, float* live_nrm);
 
 /* ---- batches: frames of several streams solved together ----
  *

@@ -49,10 +49,20 @@ class Problem:
     damping: float
     corr_dist: float
     corr_normal: float
+    visible: Optional[np.ndarray] = None     # surfels rendered into the index map (None: all)
+
+
+def visible_surfels(conf: np.ndarray, t_observed: np.ndarray, t_now: int, stable_conf: float,
+                    recent_frames: int) -> np.ndarray:
+    """Sec. 7: only stable surfels (confidence > delta_stable) and surfels
+    observed within the last delta_recent frames are rendered (FP32
+    confidence comparison)."""
+    c = np.asarray(conf, np.float32)
+    return (c > np.float32(stable_conf)) | (int(t_now) - np.asarray(t_observed, np.int64) <= int(recent_frames))
 
 
 def make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
-                 idx=None, w=None, nbr=None) -> Problem:
+                 idx=None, w=None, nbr=None, visible=None) -> Problem:
     if idx is None or w is None:
         idx, w = skin.skinning(surfel_pos, node_pos, params.node_sigma)
     if nbr is None:
@@ -62,7 +72,8 @@ def make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
                    np.asarray(node_pos, np.float32), idx, w, nbr, frame,
                    depthmod.vertex_map(depth, cam), depthmod.normal_map(depth, cam),
                    float(params.lambda_reg), float(params.damping),
-                   float(params.corr_dist), float(params.corr_normal))
+                   float(params.corr_dist), float(params.corr_normal),
+                   None if visible is None else np.asarray(visible, bool))
 
 
 def node_tables(node_pos: np.ndarray, R: np.ndarray, t: np.ndarray):
@@ -76,6 +87,8 @@ def warp_surfels(pb: Problem, R: np.ndarray, t: np.ndarray):
     r, d, c = node_tables(pb.node_pos, R, t)
     b, s = blend(pb.idx, pb.w, r, d)
     v, n, valid = apply_blend(b, pb.surfel_pos, pb.surfel_nrm)
+    if pb.visible is not None:
+        valid = valid & pb.visible          # not rendered: in no index map, matched nowhere
     return dict(r=r, d=d, c=c, b=b, s=s, v=v, n=n, valid=valid)
 
 
@@ -253,9 +266,9 @@ def gn_solve(pb: Problem, se3_init: np.ndarray, gn_iters: int, pcg_iters: Option
 
 
 def oracle_solve(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
-                 se3_init=None, linear: str = "pcg", **kw):
+                 se3_init=None, linear: str = "pcg", visible=None, **kw):
     """One frame solve from a scene's inputs (skinning and graph included)."""
-    pb = make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params)
+    pb = make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params, visible=visible)
     if se3_init is None:
         se3_init = identity_se3(node_pos.shape[0])
     kw.setdefault("rigid_iters", getattr(params, "rigid_iters", 0))

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const int i = at.tile * kWarpBlock + threadIdx.x;
-    if (i >= d.ns) return;
+    if (i >= d.ns || !visible(d, i)) return;     // (the correspondence test needs the surfel in the map)
     float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
     Warp wp = warp_surfel(d.idx[i], d.w[i], v, make_float3(0.f, 0.f, 0.f), d.dq);
     if (!wp.ok) return;
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(kWarpBlock) k_rigid_warp(Batch b) {
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const int i = at.tile * kWarpBlock + threadIdx.x;
-    if (i >= d.ns) return;
+    if (i >= d.ns || !visible(d, i)) return;
     float T[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) T[q] = d.rig[q];

@@ -24,6 +24,7 @@
 
 #include "runtime_internal.h"
 #include "segments.h"
+#include "swgn_fusion.h"
 #include "swgn.h"
 #include "swgn_frame.h"
 #include "swgn_impl.h"
@@ -194,6 +195,13 @@ sw_status check_config(const sw_config* c, std::string& why) {
     if (c->debug_iter < -1 || c->debug_iter >= kMaxIters) { why = "debug_iter out of range"; return SW_EINVAL; }
     if (c->stage_timing != 0 && c->stage_timing != 1) { why = "stage_timing must be 0 or 1"; return SW_EINVAL; }
     if (c->rigid_iters < 0 || c->rigid_iters > kMaxIters) { why = "rigid_iters must be in [0, 16]"; return SW_EINVAL; }
+    if (c->visibility != 0 && c->visibility != 1) { why = "visibility must be 0 or 1"; return SW_EINVAL; }
+    if (!finite(c->stable_conf)) { why = "stable_conf must be finite"; return SW_EINVAL; }
+    if (c->recent_frames < 0) { why = "recent_frames must be >= 0"; return SW_EINVAL; }
+    if (!(finite(c->fusion_dist) && c->fusion_dist > 0)) { why = "fusion_dist must be > 0"; return SW_EINVAL; }
+    if (!(finite(c->fusion_normal) && c->fusion_normal >= -1 && c->fusion_normal <= 1)) {
+        why = "fusion_normal must be in [-1, 1]"; return SW_EINVAL;
+    }
     return SW_OK;
 }
 
@@ -300,6 +308,13 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.cosn = s->cfg.corr_normal;
     h.lambda = s->cfg.lambda_reg;
     h.mu = s->cfg.damping;
+    h.vis_mode = s->cfg.visibility;
+    h.stable_conf = s->cfg.stable_conf;
+    h.recent = s->cfg.recent_frames;
+    h.t_now = s->t_now;
+    s->fuse_mem.release();
+    s->fz4 = nullptr;
+    s->fused = false;
 
     // nodes
     float* pos_in = tmp.alloc<float>(3 * (size_t)nn);
@@ -341,11 +356,17 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     int* sorig = G.alloc<int>(h.pitch);
     h.px = spx; h.py = spy; h.pz = spz; h.nx = snx; h.ny = sny; h.nz = snz;
     h.idx = sidx; h.w = sw; h.orig = sorig;
+    h.radius = G.alloc<float>(h.pitch);
+    h.conf = G.alloc<float>(h.pitch);
+    h.t_obs = G.alloc<int>(h.pitch);
+    int* sinv = G.alloc<int>(std::max(1, ns));
+    h.inv = sinv;
     int* flag = tmp.alloc<int>(ns + 1);
     int* fpos = tmp.alloc<int>(ns + 1);
     int* scan_tmp = tmp.alloc<int>(scan_tmp_size(std::max(10 * ns, 64 * nn) + 16));
     launch_permute_surfels(ns, 0, key, val, s->in_pos, s->in_nrm, idx_in, w_in, spx, spy, spz, snx, sny, snz,
                            sidx, sw, sorig, flag, st);
+    launch_fuse_gather(ns, sorig, s->in_rad, s->in_conf, s->in_tobs, h.radius, h.conf, h.t_obs, sinv, st);
     exclusive_scan(flag, fpos, ns, scan_tmp, st);
     s->nsets = read_scalar(fpos + ns, st);
     int* set_start = tmp.alloc<int>(s->nsets + 1);      // runs of one node set
@@ -777,6 +798,11 @@ void sw_config_default(sw_config* c) {
     c->debug_iter = -1;
     c->stage_timing = 0;
     c->rigid_iters = 0;
+    c->visibility = 0;
+    c->stable_conf = 10.0f;
+    c->recent_frames = 2;
+    c->fusion_dist = 0.001f;
+    c->fusion_normal = 0.85f;
 }
 
 const char* sw_status_string(sw_status st) {
@@ -842,10 +868,20 @@ sw_status sw_set_reference_surfels(sw_stream s, int64_t n, const float* pos, con
         s->surf_mem.release();
         s->surfels_set = false;
         s->ns = n;
+        s->fuse_mem.release();
+        s->fz4 = nullptr;
+        s->fused = false;
         s->in_pos = s->surf_mem.alloc<float>(3 * (size_t)n);
         s->in_nrm = s->surf_mem.alloc<float>(3 * (size_t)n);
         copy_in(s->in_pos, pos, sizeof(float) * 3 * n, on_device, s->exec.st);
         copy_in(s->in_nrm, nrm, sizeof(float) * 3 * n, on_device, s->exec.st);
+        // attributes: radius 0, confidence 1, last observed frame 0
+        s->in_rad = s->surf_mem.alloc<float>(n);
+        s->in_conf = s->surf_mem.alloc<float>(n);
+        s->in_tobs = s->surf_mem.alloc<int>(n);
+        launch_fill_i32(reinterpret_cast<int*>(s->in_rad), (int)n, 0, s->exec.st);
+        launch_fill_i32(reinterpret_cast<int*>(s->in_conf), (int)n, 0x3f800000, s->exec.st);
+        launch_fill_i32(s->in_tobs, (int)n, 0, s->exec.st);
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
         s->surfels_set = true;
         return SW_OK;
@@ -909,6 +945,156 @@ sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity) {
         launch_node_se3_out(nn, s->h.rq, s->h.tt, d, s->exec.st);
         SWGN_HIP(hipMemcpyAsync(out, d, sizeof(float) * 12 * nn, hipMemcpyDeviceToHost, s->exec.st));
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
+        return SW_OK;
+    });
+}
+
+// ---- surfel attributes and depth-map fusion ----
+
+sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, const float* confidence,
+                                   const int32_t* t_observed, int32_t on_device) {
+    if (!s) return SW_EINVAL;
+    if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
+    if (!s->surfels_set) return fail(s->err, SW_ESTATE, "surfels must be set first");
+    if (n != s->ns) return fail(s->err, SW_EINVAL, "n must equal the surfel count");
+    if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        if (radius) copy_in(s->in_rad, radius, sizeof(float) * n, on_device, st);
+        if (confidence) copy_in(s->in_conf, confidence, sizeof(float) * n, on_device, st);
+        if (t_observed) copy_in(s->in_tobs, t_observed, sizeof(int32_t) * n, on_device, st);
+        if (s->graph_set)
+            launch_fuse_gather((int)s->ns, s->h.orig, s->in_rad, s->in_conf, s->in_tobs, s->h.radius, s->h.conf,
+                               s->h.t_obs, const_cast<int*>(s->h.inv), st);
+        SWGN_HIP(hipGetLastError());
+        SWGN_HIP(hipStreamSynchronize(st));
+        return SW_OK;
+    });
+}
+
+sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed) {
+    if (!s) return SW_EINVAL;
+    if (s->server) server_quiesce(s->server, s);
+    if (!s->surfels_set) return fail(s->err, SW_ESTATE, "surfels not set");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const size_t n = (size_t)s->ns;
+        if (radius) SWGN_HIP(hipMemcpyAsync(radius, s->in_rad, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+        if (confidence) SWGN_HIP(hipMemcpyAsync(confidence, s->in_conf, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+        if (t_observed) SWGN_HIP(hipMemcpyAsync(t_observed, s->in_tobs, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        return SW_OK;
+    });
+}
+
+sw_status sw_get_reference_surfels(sw_stream s, float* pos, float* nrm) {
+    if (!s) return SW_EINVAL;
+    if (s->server) server_quiesce(s->server, s);
+    if (!s->surfels_set) return fail(s->err, SW_ESTATE, "surfels not set");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const size_t n = (size_t)s->ns;
+        if (pos) SWGN_HIP(hipMemcpyAsync(pos, s->in_pos, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, st));
+        if (nrm) SWGN_HIP(hipMemcpyAsync(nrm, s->in_nrm, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        return SW_OK;
+    });
+}
+
+sw_status sw_set_frame_time(sw_stream s, int32_t t_now) {
+    if (!s) return SW_EINVAL;
+    if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
+    return guarded(s->err, [&]() -> sw_status {
+        s->t_now = t_now;
+        if (s->graph_set) {
+            s->h.t_now = t_now;
+            publish_desc(s);
+        }
+        return SW_OK;
+    });
+}
+
+sw_status sw_fuse_frame(sw_stream s, const float* depth, int32_t on_device, int32_t t_now, sw_fusion_stats* stats) {
+    if (!s) return SW_EINVAL;
+    if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "surfels and node graph must be set before fusing");
+    if (!depth) return fail(s->err, SW_EINVAL, "depth must not be NULL");
+    if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        FrameDesc& h = s->h;
+        if (!s->fz4) {
+            s->fuse_mem.release();
+            s->fz4 = s->fuse_mem.alloc<unsigned long long>((size_t)16 * h.npx);
+            s->flive = s->fuse_mem.alloc<float>(6 * (size_t)h.pitch);
+            s->fmatch = s->fuse_mem.alloc<int>(h.npx);
+            s->fcount = s->fuse_mem.alloc<int>(2);
+            if (!s->fcount_host) SWGN_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->fcount_host), 2 * sizeof(int)));
+        }
+        s->t_now = t_now;
+        h.t_now = t_now;
+        publish_desc(s);
+        // the frame's normal map (the same preprocessing as a solve)
+        std::vector<sw_stream> one{s};
+        std::vector<int> ev;
+        enqueue_depth(s->exec, one, &depth, on_device, false, ev);
+        launch_fill_i32(s->fcount, 2, 0, st);
+        FuseArgs a{};
+        a.ns = (int)s->ns;
+        a.t_now = t_now;
+        a.cam = h.cam;
+        const float dd = s->cfg.fusion_dist;
+        a.dist2 = dd * dd;
+        a.cosn = s->cfg.fusion_normal;
+        a.cos_max = 0.258819045f;              // cos 75 deg
+        a.idx = h.idx; a.w = h.w; a.dq = h.dq; a.orig = h.orig; a.inv = h.inv;
+        a.px = const_cast<float*>(h.px); a.py = const_cast<float*>(h.py); a.pz = const_cast<float*>(h.pz);
+        a.nx = const_cast<float*>(h.nx); a.ny = const_cast<float*>(h.ny); a.nz = const_cast<float*>(h.nz);
+        a.radius = h.radius; a.conf = h.conf; a.t_obs = h.t_obs;
+        a.nmap = h.nmap;
+        a.zmap4 = s->fz4;
+        const size_t P = (size_t)h.pitch;
+        a.lx = s->flive; a.ly = s->flive + P; a.lz = s->flive + 2 * P;
+        a.lnx = s->flive + 3 * P; a.lny = s->flive + 4 * P; a.lnz = s->flive + 5 * P;
+        a.match = s->fmatch;
+        a.counts = s->fcount;
+        a.cpos = s->in_pos; a.cnrm = s->in_nrm; a.crad = s->in_rad; a.cconf = s->in_conf; a.ctobs = s->in_tobs;
+        launch_fuse(a, st);
+        SWGN_HIP(hipGetLastError());
+        SWGN_HIP(hipMemcpyAsync(s->fcount_host, s->fcount, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        s->fused = true;
+        if (stats) {
+            stats->n_fused = s->fcount_host[0];
+            stats->n_candidates = s->fcount_host[1];
+        }
+        return SW_OK;
+    });
+}
+
+sw_status sw_get_last_fusion(sw_stream s, int32_t* match_map, float* live_pos, float* live_nrm) {
+    if (!s) return SW_EINVAL;
+    if (s->server) server_quiesce(s->server, s);
+    if (!s->fused || !s->graph_set) return fail(s->err, SW_ESTATE, "no fusion has run on this node graph");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const FrameDesc& h = s->h;
+        if (match_map)
+            SWGN_HIP(hipMemcpyAsync(match_map, s->fmatch, sizeof(int) * h.npx, hipMemcpyDeviceToHost, st));
+        if (live_pos || live_nrm) {
+            const size_t P = (size_t)h.pitch, n = (size_t)h.ns;
+            std::vector<float> lv(6 * P);
+            std::vector<int> org(n);
+            SWGN_HIP(hipMemcpyAsync(lv.data(), s->flive, sizeof(float) * 6 * P, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipMemcpyAsync(org.data(), h.orig, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipStreamSynchronize(st));
+            for (size_t i = 0; i < n; ++i)
+                for (int c = 0; c < 3; ++c) {
+                    if (live_pos) live_pos[3 * (size_t)org[i] + c] = lv[c * P + i];
+                    if (live_nrm) live_nrm[3 * (size_t)org[i] + c] = lv[(3 + c) * P + i];
+                }
+        }
+        SWGN_HIP(hipStreamSynchronize(st));
         return SW_OK;
     });
 }

@@ -111,6 +111,19 @@ struct sw_stream_s {
     int64_t ns = 0;
     float* in_pos = nullptr;
     float* in_nrm = nullptr;
+    float* in_rad = nullptr;              // attributes, caller order (kept current by fusion)
+    float* in_conf = nullptr;
+    int* in_tobs = nullptr;
+    int t_now = 0;                        // frame time (visibility of recent surfels)
+
+    // depth-map fusion workspace, allocated on first use
+    swgn::rt::Arena fuse_mem;
+    unsigned long long* fz4 = nullptr;    // 4x super-sampled index map
+    float* flive = nullptr;               // [6][pitch] live positions and normals of the last fusion
+    int* fmatch = nullptr;                // [npx]
+    int* fcount = nullptr;                // [2]
+    int* fcount_host = nullptr;           // pinned
+    bool fused = false;
     bool surfels_set = false;
     bool graph_set = false;
     sw_server server = nullptr;           // set while attached to a serving loop
@@ -130,6 +143,7 @@ struct sw_stream_s {
 
     ~sw_stream_s() {
         if (h_pinned) (void)hipHostFree(h_pinned);
+        if (fcount_host) (void)hipHostFree(fcount_host);
     }
 };
 

@@ -82,6 +82,9 @@ struct FrameDesc {
     int pcg_iters, debug_iter;
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
     int rigid_iters;              // rigid alignment steps before the non-rigid ones
+    int vis_mode;                 // 1: only stable or recently observed surfels are rendered
+    float stable_conf;            // delta_stable
+    int recent, t_now;            // delta_recent, current frame time
     Cam cam;
     float edge_gate, dist2, cosn, lambda, mu, pad2;
     // resident: surfels sorted by node set; orig = caller's index
@@ -89,6 +92,9 @@ struct FrameDesc {
     const int4* idx;
     const float4* w;
     const int* orig;
+    float *radius, *conf;         // surfel attributes (radius, confidence, last observed frame)
+    int* t_obs;
+    const int* inv;               // caller index -> sorted position
     // resident: nodes
     const float4* pref;
     float4 *rq, *tt, *dq, *cl;
@@ -138,6 +144,12 @@ struct FrameDesc {
     double* rig_part;             // [tiles][kRigidSums]
     RigidStats* rig_stats;        // [kMaxIters]
 };
+
+// Whether sorted surfel i is rendered into the solver's index map (Sec. 7:
+// stable surfels, or recently observed ones, when the stream asks for it).
+__device__ __forceinline__ bool visible(const FrameDesc& d, int i) {
+    return d.vis_mode == 0 || d.conf[i] > d.stable_conf || d.t_now - d.t_obs[i] <= d.recent;
+}
 
 // Tiles (workgroups) of each per-frame stage for one stream.
 // kStSpmv forms the products of a PCG iteration, kStUpdate finishes one,

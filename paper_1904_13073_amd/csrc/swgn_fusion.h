@@ -1,0 +1,47 @@
+// Arguments of the depth-map fusion kernels of one stream (see fusion.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swgn_impl.h"
+
+namespace swgn {
+
+constexpr float kFusePhi = 0.6f;      // depth-surfel confidence exp(-gamma^2 / (2 phi^2))
+
+struct FuseArgs {
+    int ns;
+    int t_now;
+    Cam cam;
+    float dist2;                  // (float)delta_d * (float)delta_d
+    float cosn;                   // delta_n
+    float cos_max;                // cos 75 deg: the radius clamp
+    // resident, sorted by node set (orig = caller index, inv its inverse)
+    const int4* idx;
+    const float4* w;
+    const float4* dq;
+    const int* orig;
+    const int* inv;
+    float *px, *py, *pz, *nx, *ny, *nz;     // reference surfels, updated where fused
+    float *radius, *conf;
+    int* t_obs;
+    // frame
+    const float4* nmap;           // (normal, depth) per pixel; depth 0 = no normal
+    unsigned long long* zmap4;    // [4H][4W] index map
+    float *lx, *ly, *lz, *lnx, *lny, *lnz;  // live surfels before fusion
+    int* match;                   // [H][W] caller index fused at the pixel, -1
+    int* counts;                  // [0] fused, [1] append candidates
+    // caller-order copies kept current (the inputs a later node graph sorts from)
+    float *cpos, *cnrm, *crad, *cconf;
+    int* ctobs;
+};
+
+void launch_fuse(const FuseArgs& a, hipStream_t st);
+
+// Sorted copies of the caller-order attributes (sorted i takes caller
+// orig[i]) and the inverse permutation inv[orig[i]] = i.
+void launch_fuse_gather(int ns, const int* orig, const float* crad, const float* cconf, const int* ctobs,
+                        float* rad, float* conf, int* tobs, int* inv, hipStream_t st);
+
+}  // namespace swgn

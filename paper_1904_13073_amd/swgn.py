@@ -26,7 +26,13 @@ class SwConfig(C.Structure):
                 ("lambda_reg", C.c_float), ("node_sigma", C.c_float), ("corr_dist", C.c_float),
                 ("corr_normal", C.c_float), ("edge_gate", C.c_float), ("damping", C.c_float),
                 ("jac_dtype", C.c_int32), ("dot_fp64", C.c_int32), ("debug_iter", C.c_int32),
-                ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32)]
+                ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32), ("visibility", C.c_int32),
+                ("stable_conf", C.c_float), ("recent_frames", C.c_int32), ("fusion_dist", C.c_float),
+                ("fusion_normal", C.c_float)]
+
+
+class SwFusionStats(C.Structure):
+    _fields_ = [("n_fused", C.c_int32), ("n_candidates", C.c_int32)]
 
 
 class SwFrameStats(C.Structure):
@@ -82,7 +88,8 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
            "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
-           "sw_batch_autotune", "sw_get_layout"]
+           "sw_batch_autotune", "sw_get_layout", "sw_set_surfel_attributes", "sw_get_surfel_attributes",
+           "sw_get_reference_surfels", "sw_set_frame_time", "sw_fuse_frame", "sw_get_last_fusion"]
 
 SW_EPENDING = 1
 
@@ -119,6 +126,12 @@ def lib() -> C.CDLL:
         "sw_get_last_maps": (i32, [vp, ip, ip, fp, fp]),
         "sw_get_last_system": (i32, [vp, fp, fp, fp]),
         "sw_get_last_jacobian": (i32, [vp, fp, fp]),
+        "sw_set_surfel_attributes": (i32, [vp, i64, fp, fp, ip, i32]),
+        "sw_get_surfel_attributes": (i32, [vp, fp, fp, ip]),
+        "sw_get_reference_surfels": (i32, [vp, fp, fp]),
+        "sw_set_frame_time": (i32, [vp, i32]),
+        "sw_fuse_frame": (i32, [vp, fp, i32, i32, C.POINTER(SwFusionStats)]),
+        "sw_get_last_fusion": (i32, [vp, ip, fp, fp]),
         "sw_create_batch": (i32, [vp, i32, C.POINTER(vp)]),
         "sw_destroy_batch": (i32, [vp]),
         "sw_batch_last_error": (C.c_char_p, [vp]),
@@ -437,6 +450,56 @@ def sw_get_last_jacobian(h):
     return r, J
 
 
+def sw_set_surfel_attributes(h, radius=None, confidence=None, t_observed=None):
+    ns, _, _ = sw_get_sizes(h)
+    pr, dr, kr = _ptr(radius, np.float32)
+    pc, dc, kc = _ptr(confidence, np.float32)
+    pt, dt, kt = _ptr(t_observed, np.int32)
+    devs = {d for d, p in ((dr, pr), (dc, pc), (dt, pt)) if p is not None}
+    if len(devs) > 1:
+        raise ValueError("attributes must all be host arrays or all device tensors")
+    _check(h, lib().sw_set_surfel_attributes(h, ns, pr, pc, pt, devs.pop() if devs else 0))
+
+
+def sw_get_surfel_attributes(h):
+    ns, _, _ = sw_get_sizes(h)
+    r = np.empty(ns, np.float32)
+    c = np.empty(ns, np.float32)
+    t = np.empty(ns, np.int32)
+    _check(h, lib().sw_get_surfel_attributes(h, r.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p),
+                                             t.ctypes.data_as(C.c_void_p)))
+    return r, c, t
+
+
+def sw_get_reference_surfels(h):
+    ns, _, _ = sw_get_sizes(h)
+    pos = np.empty((ns, 3), np.float32)
+    nrm = np.empty((ns, 3), np.float32)
+    _check(h, lib().sw_get_reference_surfels(h, pos.ctypes.data_as(C.c_void_p), nrm.ctypes.data_as(C.c_void_p)))
+    return pos, nrm
+
+
+def sw_set_frame_time(h, t_now: int):
+    _check(h, lib().sw_set_frame_time(h, int(t_now)))
+
+
+def sw_fuse_frame(h, depth, t_now: int):
+    p, dev, ka = _ptr(depth, np.float32)
+    st = SwFusionStats()
+    _check(h, lib().sw_fuse_frame(h, p, dev, int(t_now), C.byref(st)))
+    return dict(n_fused=st.n_fused, n_candidates=st.n_candidates)
+
+
+def sw_get_last_fusion(h, width: int, height: int):
+    ns, _, _ = sw_get_sizes(h)
+    m = np.empty((height, width), np.int32)
+    lv = np.empty((ns, 3), np.float32)
+    ln = np.empty((ns, 3), np.float32)
+    _check(h, lib().sw_get_last_fusion(h, m.ctypes.data_as(C.c_void_p), lv.ctypes.data_as(C.c_void_p),
+                                       ln.ctypes.data_as(C.c_void_p)))
+    return m, lv, ln
+
+
 class Stream:
     """One depth stream: owns a library handle (convenience over the functions above)."""
 
@@ -501,6 +564,24 @@ class Stream:
 
     def last_jacobian(self):
         return sw_get_last_jacobian(self.h)
+
+    def set_surfel_attributes(self, radius=None, confidence=None, t_observed=None):
+        sw_set_surfel_attributes(self.h, radius, confidence, t_observed)
+
+    def surfel_attributes(self):
+        return sw_get_surfel_attributes(self.h)
+
+    def reference_surfels(self):
+        return sw_get_reference_surfels(self.h)
+
+    def set_frame_time(self, t_now: int):
+        sw_set_frame_time(self.h, t_now)
+
+    def fuse_frame(self, depth, t_now: int):
+        return sw_fuse_frame(self.h, depth, t_now)
+
+    def last_fusion(self):
+        return sw_get_last_fusion(self.h, self.cfg.width, self.cfg.height)
 
 
 def config_for(scene, **overrides) -> SwConfig:

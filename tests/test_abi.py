@@ -56,7 +56,8 @@ def test_defaults_and_status_strings():
     ("gn_iters", 17), ("gn_iters", -1), ("pcg_iters", 5000), ("lambda_reg", -1.0),
     ("node_sigma", 0.0), ("corr_dist", 0.0), ("corr_normal", 1.5), ("edge_gate", -0.1),
     ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
-    ("rigid_iters", 17), ("rigid_iters", -1),
+    ("rigid_iters", 17), ("rigid_iters", -1), ("visibility", 2), ("stable_conf", float("inf")),
+    ("recent_frames", -1), ("fusion_dist", 0.0), ("fusion_normal", 1.5),
 ])
 def test_create_rejects_bad_config(field, value):
     from paper_1904_13073_amd import swgn
@@ -99,3 +100,19 @@ def test_server_entry_points_validate_on_the_host():
     assert L.sw_server_submit(None, None, None, 0, C.byref(t)) == swgn.SW_EINVAL
     assert L.sw_server_poll(None, 1, 0, None, None) == swgn.SW_EINVAL
     assert L.sw_server_attach(None, None) == swgn.SW_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_fusion_entry_points_validate_on_the_host():
+    from paper_1904_13073_amd import swgn
+    L = swgn.lib()
+    st = swgn.SwFusionStats()
+    assert L.sw_fuse_frame(None, None, 0, 0, C.byref(st)) == swgn.SW_EINVAL
+    assert L.sw_set_surfel_attributes(None, 1, None, None, None, 0) == swgn.SW_EINVAL
+    assert L.sw_get_surfel_attributes(None, None, None, None) == swgn.SW_EINVAL
+    assert L.sw_get_reference_surfels(None, None, None) == swgn.SW_EINVAL
+    assert L.sw_set_frame_time(None, 3) == swgn.SW_EINVAL
+    assert L.sw_get_last_fusion(None, None, None, None) == swgn.SW_EINVAL
+    c = swgn.sw_config_default()
+    assert c.visibility == 0 and c.recent_frames == 2 and abs(c.stable_conf - 10.0) < 1e-6
+    assert abs(c.fusion_dist - 0.001) < 1e-9 and abs(c.fusion_normal - 0.85) < 1e-6

@@ -213,3 +213,32 @@ def test_given_correspondences_reproduce_and_move_the_association(scene_cache):
     assert d.tolist() == [k]
     v = lin["ws"]["v"][i]
     assert np.isclose(alt["r_data"][k], pb.N64[y, x + 1] @ (v - pb.V64[y, x + 1]), rtol=1e-12, atol=1e-15)
+
+
+def test_visibility_mask_removes_surfels_from_the_index_map(scene_cache):
+    """Sec. 7 visibility: with every surfel visible the solve is unchanged;
+    with a mask, hidden surfels are in no index-map pixel and match nothing,
+    and the map is the one rendered from the visible surfels alone."""
+    s = scene_cache("tiny")
+    rng = np.random.default_rng(4)
+    ns = s.surfel_pos.shape[0]
+    conf = rng.uniform(0.0, 20.0, ns).astype(np.float32)
+    tob = rng.integers(0, 10, ns)
+    vis = S.visible_surfels(conf, tob, t_now=9, stable_conf=10.0, recent_frames=2)
+    assert np.array_equal(vis, (conf > 10.0) | (tob >= 7))
+    R, t = Q.se3_to_rt(s.gt_se3.astype(np.float64))
+    base = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
+    allv = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
+                          idx=base.idx, w=base.w, nbr=base.nbr, visible=np.ones(ns, bool))
+    l0, l1 = S.linearize(base, R, t), S.linearize(allv, R, t)
+    assert np.array_equal(l0["corr_map"], l1["corr_map"]) and np.array_equal(l0["r_data"], l1["r_data"])
+    masked = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
+                            idx=base.idx, w=base.w, nbr=base.nbr, visible=vis)
+    lm = S.linearize(masked, R, t)
+    hidden = np.flatnonzero(~vis)
+    assert not np.isin(lm["I"], hidden).any()
+    assert not np.isin(lm["corr_idx"], hidden).any()
+    ws = lm["ws"]
+    want_I = R32.index_map(ws["v"].astype(np.float32), s.cam, ws["valid"])
+    assert np.array_equal(lm["I"], want_I)
+    assert 0 < lm["corr_idx"].size < l0["corr_idx"].size
