@@ -71,6 +71,11 @@ typedef struct sw_config {
     int32_t recent_frames;     /* delta_recent, 2 (Table 1) */
     float fusion_dist;         /* depth fusion distance gate delta_distance, 0.001 m (Table 1) */
     float fusion_normal;       /* depth fusion normal gate delta_normal, 0.85 (Table 1) */
+    float warp_eps;            /* intrinsic deformation bound epsilon of live skinning and of
+                                  the compressive-warp test (Eq. 7, Eq. 8), 0.2 (Table 1) */
+    float append_nn;           /* delta_nn: append candidates whose kept nearest-node weight
+                                  sum is below it are dropped (Sec. 6.4); the paper gives no
+                                  value, 0.3 */
 } sw_config;
 
 /* Statistics of one depth-map fusion (sw_fuse_frame). */
@@ -78,6 +83,15 @@ typedef struct sw_fusion_stats {
     int32_t n_fused;           /* depth surfels fused into a live surfel */
     int32_t n_candidates;      /* pixels with a normal that found no surfel (append candidates) */
 } sw_fusion_stats;
+
+/* Statistics of one append-candidate selection (sw_append_candidates). */
+typedef struct sw_append_stats {
+    int32_t n_candidates;      /* pixels with a normal that fusion matched to no surfel */
+    int32_t n_far;             /* dropped: kept nearest-node weight sum below append_nn */
+    int32_t n_compressive;     /* dropped: the warp back stretches by more than 1 + warp_eps */
+    int32_t n_appended;        /* survivors */
+    int32_t n_written;         /* survivors written (at most max_out) */
+} sw_append_stats;
 
 /* Per-frame statistics, one entry per Gauss-Newton iteration (<= 16). */
 typedef struct sw_frame_stats {
@@ -195,6 +209,32 @@ sw_status sw_fuse_frame(sw_stream s, const float* depth, int32_t on_device, int3
  * used (n x 3 each, caller order; NaN positions for surfels without a valid
  * blend). Any pointer may be NULL. SW_ESTATE before the first fusion. */
 sw_status sw_get_last_fusion(sw_stream s, int32_t* match_map, float* live_pos, float* live_nrm);
+
+/* Append candidates of the last fusion (Sec. 6.2 - 6.4), at the current warp
+ * field. A candidate is a pixel with a normal that the fusion matched to no
+ * surfel. It is skinned to its 4 nearest live node positions c_j = T_j p_j
+ * (ties to the lower index); node i of the set stays only if
+ * (1 - warp_eps)^2 |p_i - p_0|^2 < |c_i - c_0|^2 < (1 + warp_eps)^2 |p_i - p_0|^2
+ * (Eq. 7; the nearest node always stays). It is dropped if the Gaussian
+ * weights exp(-|V - c_j|^2 / (2 node_sigma^2)) of the kept nodes sum to less
+ * than append_nn, or if the warp back to the reference frame (the inverse of
+ * the normalised blend of the kept nodes, weights at the point) has a
+ * derivative, taken by central differences with a 1 mm step, whose largest
+ * singular value exceeds 1 + warp_eps (Eq. 8). Survivors come in row-major
+ * pixel order: pixel index y * W + x, reference position and normal
+ * (3 floats each), the depth surfel's radius and confidence (as in
+ * sw_fuse_frame). At most max_out are written (host arrays with on_device = 0,
+ * device arrays on the stream's HIP stream with 1); stats->n_appended counts
+ * all. They are not added to the stream: the caller appends them to its
+ * surfels (sw_set_reference_surfels, sw_set_surfel_attributes with
+ * t_observed = t_now, then sw_set_node_graph with the current transforms).
+ * Synchronous. SW_ESTATE unless the stream's last depth frame was fused (a
+ * solve in between replaces the frame) or while attached to a server. */
+sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, int32_t* pixel, float* pos,
+                               float* nrm, float* radius, float* confidence, sw_append_stats* stats);
+
+/* Live node positions T_k p_k at the current transforms (n_nodes x 3, host). */
+sw_status sw_get_live_nodes(sw_stream s, float* pos);
 
 /* ---- batches: frames of several streams solved together ----
  *

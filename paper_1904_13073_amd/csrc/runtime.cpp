@@ -202,6 +202,8 @@ sw_status check_config(const sw_config* c, std::string& why) {
     if (!(finite(c->fusion_normal) && c->fusion_normal >= -1 && c->fusion_normal <= 1)) {
         why = "fusion_normal must be in [-1, 1]"; return SW_EINVAL;
     }
+    if (!(finite(c->warp_eps) && c->warp_eps > 0 && c->warp_eps < 1)) { why = "warp_eps must be in (0, 1)"; return SW_EINVAL; }
+    if (!(finite(c->append_nn) && c->append_nn >= 0)) { why = "append_nn must be >= 0"; return SW_EINVAL; }
     return SW_OK;
 }
 
@@ -541,6 +543,7 @@ void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* 
     const int n = (int)ss.size();
     for (int i = 0; i < n; ++i) {
         const FrameDesc& h = ss[i]->h;
+        ++ss[i]->depth_gen;
         if (!on_device) {
             copy_in(h.depth, depths[i], sizeof(float) * h.npx, 0, ex.st);
             din.p[i] = h.depth;
@@ -803,6 +806,8 @@ void sw_config_default(sw_config* c) {
     c->recent_frames = 2;
     c->fusion_dist = 0.001f;
     c->fusion_normal = 0.85f;
+    c->warp_eps = 0.2f;
+    c->append_nn = 0.3f;
 }
 
 const char* sw_status_string(sw_status st) {
@@ -1029,7 +1034,7 @@ sw_status sw_fuse_frame(sw_stream s, const float* depth, int32_t on_device, int3
             s->flive = s->fuse_mem.alloc<float>(6 * (size_t)h.pitch);
             s->fmatch = s->fuse_mem.alloc<int>(h.npx);
             s->fcount = s->fuse_mem.alloc<int>(2);
-            if (!s->fcount_host) SWGN_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->fcount_host), 2 * sizeof(int)));
+            if (!s->fcount_host) SWGN_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->fcount_host), 8 * sizeof(int)));
         }
         s->t_now = t_now;
         h.t_now = t_now;
@@ -1038,6 +1043,7 @@ sw_status sw_fuse_frame(sw_stream s, const float* depth, int32_t on_device, int3
         std::vector<sw_stream> one{s};
         std::vector<int> ev;
         enqueue_depth(s->exec, one, &depth, on_device, false, ev);
+        s->fuse_gen = s->depth_gen;
         launch_fill_i32(s->fcount, 2, 0, st);
         FuseArgs a{};
         a.ns = (int)s->ns;
@@ -1095,6 +1101,106 @@ sw_status sw_get_last_fusion(sw_stream s, int32_t* match_map, float* live_pos, f
                 }
         }
         SWGN_HIP(hipStreamSynchronize(st));
+        return SW_OK;
+    });
+}
+
+sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, int32_t* pixel, float* pos,
+                               float* nrm, float* radius, float* confidence, sw_append_stats* stats) {
+    if (!s) return SW_EINVAL;
+    if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
+    if (!s->graph_set || !s->fused || s->fuse_gen != s->depth_gen)
+        return fail(s->err, SW_ESTATE, "append candidates need a fusion as the stream's last depth frame");
+    if (max_out < 0) return fail(s->err, SW_EINVAL, "max_out must be >= 0");
+    if (max_out > 0 && !(pixel && pos && nrm && radius && confidence))
+        return fail(s->err, SW_EINVAL, "output pointers must not be NULL when max_out > 0");
+    if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const FrameDesc& h = s->h;
+        const int npx = h.npx;
+        if (!s->aflag) {
+            s->aflag = s->append_mem.alloc<int>(npx + 1);
+            s->apos = s->append_mem.alloc<int>(npx + 1);
+            s->ascan = s->append_mem.alloc<int>(scan_tmp_size(npx + 1));
+            s->acount = s->append_mem.alloc<int>(4);
+            s->asv = s->append_mem.alloc<float4>(npx);
+            s->asn = s->append_mem.alloc<float4>(npx);
+            s->apix = s->append_mem.alloc<int>(npx);
+            s->apos3 = s->append_mem.alloc<float>(3 * (size_t)npx);
+            s->anrm3 = s->append_mem.alloc<float>(3 * (size_t)npx);
+            s->arad = s->append_mem.alloc<float>(npx);
+            s->aconf = s->append_mem.alloc<float>(npx);
+        }
+        AppendArgs a{};
+        a.cam = h.cam;
+        a.nn = h.nn;
+        a.eps = s->cfg.warp_eps;
+        a.delta_nn = s->cfg.append_nn;
+        a.inv2s2 = 1.0f / (2.0f * s->cfg.node_sigma * s->cfg.node_sigma);
+        a.cos_max = 0.258819045f;              // cos 75 deg
+        a.nmap = h.nmap;
+        a.match = s->fmatch;
+        a.cl = h.cl;
+        a.pref = h.pref;
+        a.dq = h.dq;
+        a.flag = s->aflag;
+        a.sv = s->asv;
+        a.sn = s->asn;
+        a.counts = s->acount;
+        if (on_device) {
+            a.max_out = max_out;
+            a.out_pixel = pixel; a.out_pos = pos; a.out_nrm = nrm; a.out_rad = radius; a.out_conf = confidence;
+        } else {
+            a.max_out = std::min(max_out, npx);
+            a.out_pixel = s->apix; a.out_pos = s->apos3; a.out_nrm = s->anrm3; a.out_rad = s->arad;
+            a.out_conf = s->aconf;
+        }
+        launch_fill_i32(s->acount, 4, 0, st);
+        launch_fill_i32(s->aflag + npx, 1, 0, st);
+        launch_append(a, s->apos, s->ascan, st);
+        SWGN_HIP(hipGetLastError());
+        int* hc = s->fcount_host;
+        SWGN_HIP(hipMemcpyAsync(hc + 2, s->acount, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(hc + 5, s->apos + npx, sizeof(int), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        const int n = hc[5];
+        const int nw = std::min(n, a.max_out);
+        if (!on_device && nw > 0) {
+            SWGN_HIP(hipMemcpyAsync(pixel, s->apix, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipMemcpyAsync(pos, s->apos3, sizeof(float) * 3 * nw, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipMemcpyAsync(nrm, s->anrm3, sizeof(float) * 3 * nw, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipMemcpyAsync(radius, s->arad, sizeof(float) * nw, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipMemcpyAsync(confidence, s->aconf, sizeof(float) * nw, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipStreamSynchronize(st));
+        }
+        if (stats) {
+            stats->n_candidates = hc[2];
+            stats->n_far = hc[3];
+            stats->n_compressive = hc[4];
+            stats->n_appended = n;
+            stats->n_written = nw;
+        }
+        return SW_OK;
+    });
+}
+
+sw_status sw_get_live_nodes(sw_stream s, float* pos) {
+    if (!s) return SW_EINVAL;
+    if (s->server) server_quiesce(s->server, s);
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "no node graph set");
+    if (!pos) return fail(s->err, SW_EINVAL, "pos must not be NULL");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const int nn = s->h.nn;
+        std::vector<float4> c(nn);
+        SWGN_HIP(hipMemcpyAsync(c.data(), s->h.cl, sizeof(float4) * nn, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < nn; ++k) {
+            pos[3 * k + 0] = c[k].x;
+            pos[3 * k + 1] = c[k].y;
+            pos[3 * k + 2] = c[k].z;
+        }
         return SW_OK;
     });
 }

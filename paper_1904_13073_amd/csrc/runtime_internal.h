@@ -122,8 +122,16 @@ struct sw_stream_s {
     float* flive = nullptr;               // [6][pitch] live positions and normals of the last fusion
     int* fmatch = nullptr;                // [npx]
     int* fcount = nullptr;                // [2]
-    int* fcount_host = nullptr;           // pinned
+    int* fcount_host = nullptr;           // pinned, [8]: fusion counts, append counts
     bool fused = false;
+    uint64_t depth_gen = 0;               // bumped by every depth preprocessing
+    uint64_t fuse_gen = ~0ull;            // depth_gen of the last fusion
+    // append-candidate workspace, allocated on first use
+    swgn::rt::Arena append_mem;
+    int *aflag = nullptr, *apos = nullptr, *ascan = nullptr, *acount = nullptr;
+    float4 *asv = nullptr, *asn = nullptr;
+    int* apix = nullptr;                  // staging of host outputs, capacity npx
+    float *apos3 = nullptr, *anrm3 = nullptr, *arad = nullptr, *aconf = nullptr;
     bool surfels_set = false;
     bool graph_set = false;
     sw_server server = nullptr;           // set while attached to a serving loop

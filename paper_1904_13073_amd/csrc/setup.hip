@@ -18,22 +18,6 @@ namespace swgn {
 // own. Nodes are visited in ascending index, so equal keys keep the lower
 // index first.
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ void knn_insert(float (&kd)[K], int (&ki)[K], float key, int j) {
-    if (!(key < kd[K - 1])) return;
-    int p = K - 1;
-#pragma unroll
-    for (int q = K - 1; q > 0; --q) {
-        if (key < kd[q - 1]) {
-            kd[q] = kd[q - 1];
-            ki[q] = ki[q - 1];
-            p = q - 1;
-        }
-    }
-    kd[p] = key;
-    ki[p] = j;
-}
-
 constexpr int kKnnTile = 1024;
 
 __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restrict__ pos, int nn,

@@ -39,6 +39,31 @@ struct FuseArgs {
 
 void launch_fuse(const FuseArgs& a, hipStream_t st);
 
+// Arguments of the append-candidate kernels (see append.hip).
+struct AppendArgs {
+    Cam cam;
+    int nn;
+    int max_out;                  // capacity of the out_ arrays
+    float eps;                    // intrinsic deformation bound of Eq. 7 / Eq. 8
+    float delta_nn;               // weight-sum threshold
+    float inv2s2;                 // 1 / (2 sigma^2)
+    float cos_max;                // cos 75 deg: the radius clamp
+    const float4* nmap;           // (normal, depth) per pixel of the fused frame
+    const int* match;             // [H][W] fused surfel per pixel, -1
+    const float4* cl;             // live node positions
+    const float4* pref;           // reference node positions
+    const float4* dq;             // node dual quaternions
+    int* flag;                    // [npx + 1] survivor flags (the last stays 0)
+    float4 *sv, *sn;              // [npx] reference position / normal of survivors
+    int* counts;                  // [0] candidates, [1] far, [2] compressive
+    int* out_pixel;
+    float *out_pos, *out_nrm, *out_rad, *out_conf;
+};
+
+// Evaluation, exclusive scan of the flags into pos[npx + 1] (pos[npx] = the
+// number of survivors) and compaction.
+void launch_append(const AppendArgs& a, int* pos, int* scan_tmp, hipStream_t st);
+
 // Sorted copies of the caller-order attributes (sorted i takes caller
 // orig[i]) and the inverse permutation inv[orig[i]] = i.
 void launch_fuse_gather(int ns, const int* orig, const float* crad, const float* cconf, const int* ctobs,

@@ -77,6 +77,25 @@ __device__ __forceinline__ float3 qrot(float c0, float3 u, float3 v) {
     return add3(add3(v, scale3(uv, 2.0f * c0)), scale3(uuv, 2.0f));
 }
 
+// Insert (key, j) into the ascending K-nearest list (kd, ki); equal keys keep
+// the earlier (lower) index first, so scanning j upwards breaks ties to the
+// lower index.
+template <int K>
+__device__ __forceinline__ void knn_insert(float (&kd)[K], int (&ki)[K], float key, int j) {
+    if (!(key < kd[K - 1])) return;
+    int p = K - 1;
+#pragma unroll
+    for (int q = K - 1; q > 0; --q) {
+        if (key < kd[q - 1]) {
+            kd[q] = kd[q - 1];
+            ki[q] = ki[q - 1];
+            p = q - 1;
+        }
+    }
+    kd[p] = key;
+    ki[p] = j;
+}
+
 // Result of warping one surfel by the blend of its 4 nodes.
 struct Warp {
     Q4 cr, cd;        // normalised blend c = b / |b_r|

@@ -28,11 +28,16 @@ class SwConfig(C.Structure):
                 ("jac_dtype", C.c_int32), ("dot_fp64", C.c_int32), ("debug_iter", C.c_int32),
                 ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32), ("visibility", C.c_int32),
                 ("stable_conf", C.c_float), ("recent_frames", C.c_int32), ("fusion_dist", C.c_float),
-                ("fusion_normal", C.c_float)]
+                ("fusion_normal", C.c_float), ("warp_eps", C.c_float), ("append_nn", C.c_float)]
 
 
 class SwFusionStats(C.Structure):
     _fields_ = [("n_fused", C.c_int32), ("n_candidates", C.c_int32)]
+
+
+class SwAppendStats(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("n_far", C.c_int32), ("n_compressive", C.c_int32),
+                ("n_appended", C.c_int32), ("n_written", C.c_int32)]
 
 
 class SwFrameStats(C.Structure):
@@ -89,7 +94,8 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
            "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
            "sw_batch_autotune", "sw_get_layout", "sw_set_surfel_attributes", "sw_get_surfel_attributes",
-           "sw_get_reference_surfels", "sw_set_frame_time", "sw_fuse_frame", "sw_get_last_fusion"]
+           "sw_get_reference_surfels", "sw_set_frame_time", "sw_fuse_frame", "sw_get_last_fusion",
+           "sw_append_candidates", "sw_get_live_nodes"]
 
 SW_EPENDING = 1
 
@@ -132,6 +138,8 @@ def lib() -> C.CDLL:
         "sw_set_frame_time": (i32, [vp, i32]),
         "sw_fuse_frame": (i32, [vp, fp, i32, i32, C.POINTER(SwFusionStats)]),
         "sw_get_last_fusion": (i32, [vp, ip, fp, fp]),
+        "sw_append_candidates": (i32, [vp, i32, i32, ip, fp, fp, fp, fp, C.POINTER(SwAppendStats)]),
+        "sw_get_live_nodes": (i32, [vp, fp]),
         "sw_create_batch": (i32, [vp, i32, C.POINTER(vp)]),
         "sw_destroy_batch": (i32, [vp]),
         "sw_batch_last_error": (C.c_char_p, [vp]),
@@ -500,6 +508,34 @@ def sw_get_last_fusion(h, width: int, height: int):
     return m, lv, ln
 
 
+def sw_append_candidates(h, max_out: int):
+    """Append candidates of the last fusion (host arrays of max_out entries):
+    dict of pixel, pos, nrm, radius, confidence (the written ones) and the
+    counts."""
+    n = int(max_out)
+    pix = np.empty(max(n, 1), np.int32)
+    pos = np.empty((max(n, 1), 3), np.float32)
+    nrm = np.empty((max(n, 1), 3), np.float32)
+    rad = np.empty(max(n, 1), np.float32)
+    conf = np.empty(max(n, 1), np.float32)
+    st = SwAppendStats()
+    _check(h, lib().sw_append_candidates(h, n, 0, pix.ctypes.data_as(C.c_void_p), pos.ctypes.data_as(C.c_void_p),
+                                         nrm.ctypes.data_as(C.c_void_p), rad.ctypes.data_as(C.c_void_p),
+                                         conf.ctypes.data_as(C.c_void_p), C.byref(st)))
+    k = st.n_written
+    out = {f: getattr(st, f) for f, _ in st._fields_}
+    out.update(pixel=pix[:k].copy(), pos=pos[:k].copy(), nrm=nrm[:k].copy(), radius=rad[:k].copy(),
+               confidence=conf[:k].copy())
+    return out
+
+
+def sw_get_live_nodes(h) -> np.ndarray:
+    _, nn, _ = sw_get_sizes(h)
+    out = np.empty((nn, 3), np.float32)
+    _check(h, lib().sw_get_live_nodes(h, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
 class Stream:
     """One depth stream: owns a library handle (convenience over the functions above)."""
 
@@ -582,6 +618,12 @@ class Stream:
 
     def last_fusion(self):
         return sw_get_last_fusion(self.h, self.cfg.width, self.cfg.height)
+
+    def append_candidates(self, max_out: Optional[int] = None):
+        return sw_append_candidates(self.h, self.cfg.width * self.cfg.height if max_out is None else max_out)
+
+    def live_nodes(self) -> np.ndarray:
+        return sw_get_live_nodes(self.h)
 
 
 def config_for(scene, **overrides) -> SwConfig:

@@ -58,6 +58,7 @@ def test_defaults_and_status_strings():
     ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
     ("rigid_iters", 17), ("rigid_iters", -1), ("visibility", 2), ("stable_conf", float("inf")),
     ("recent_frames", -1), ("fusion_dist", 0.0), ("fusion_normal", 1.5),
+    ("warp_eps", 0.0), ("warp_eps", 1.0), ("append_nn", -0.1), ("append_nn", float("nan")),
 ])
 def test_create_rejects_bad_config(field, value):
     from paper_1904_13073_amd import swgn
@@ -116,3 +117,7 @@ def test_fusion_entry_points_validate_on_the_host():
     c = swgn.sw_config_default()
     assert c.visibility == 0 and c.recent_frames == 2 and abs(c.stable_conf - 10.0) < 1e-6
     assert abs(c.fusion_dist - 0.001) < 1e-9 and abs(c.fusion_normal - 0.85) < 1e-6
+    assert abs(c.warp_eps - 0.2) < 1e-7 and abs(c.append_nn - 0.3) < 1e-7
+    ast = swgn.SwAppendStats()
+    assert L.sw_append_candidates(None, 0, 0, None, None, None, None, None, C.byref(ast)) == swgn.SW_EINVAL
+    assert L.sw_get_live_nodes(None, None) == swgn.SW_EINVAL
