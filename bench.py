@@ -125,6 +125,25 @@ def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):
     return roof, {k: round(v, 1) for k, v in rates.items()}
 
 
+def device_copy_gbs(torch, dev, mib=1024, reps=10):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of `mib` MiB (read + write bytes) timed with events over `reps` copies."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def arrival_trace(n_streams, hz, seconds, seed=0):
     """Poisson arrivals: (time, stream) pairs, exponential gaps of mean 1/hz per stream."""
     import numpy as np
@@ -380,6 +399,9 @@ def main():
     px.close()
     tst.close()
     roofline, rates = stage_roofline(per_frame_us, launches, kb, replay)
+    copy_gbs = device_copy_gbs(torch, dev)
+    roofline["achievable_copy_gbs"] = copy_gbs
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     # depth-map fusion after the frame's solve (one call: depth preprocessing,
     # the 4x super-sampled index map, match and fuse; it ends in a sync)
@@ -438,6 +460,8 @@ def main():
         b_fused = bool(orders[5] & 4)
         b_roof, b_rates = stage_roofline(btot / breps, launches_per_frame(G, Pi, b_fused), kb, b_replay,
                                          scale=B, streams=B)
+        b_roof["achievable_copy_gbs"] = copy_gbs
+        b_roof["frac_of_copy"] = round(b_roof["achieved"] / copy_gbs, 4)
         batched = {"streams": B, "value": round(B * nbs / bel, 2), "unit": "frames/s",
                    "ms_per_batch": round(1000.0 * bel / nbs, 3),
                    "latency_ms": {"p50": round(1000 * percentile(blat, 0.5), 4),
