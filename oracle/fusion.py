@@ -34,7 +34,7 @@ Readings taken here (the paper leaves them open):
   own blended transform at the current warp field: v_ref = R^T (v' - t),
   n_ref = R^T n' (R, t of the normalised blend); its skinning is kept;
 * depth pixels with a normal that find no surfel are reported as append
-  candidates (Sec. 6.3); appending them is not part of this step.
+  candidates (Sec. 6.4); appending them is a step of its own.
 
 Integer decisions (sub-pixel, winner, gates, selection) are taken in FP32 on
 FP32 inputs (the live positions and normals handed in, as the GPU holds

@@ -66,25 +66,34 @@ __global__ void __launch_bounds__(256) k_fuse_live(FuseArgs a) {
 __global__ void __launch_bounds__(256) k_fuse_match(FuseArgs a) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const int npx = a.cam.W * a.cam.H;
-    if (u >= npx) return;
-    const int x = u % a.cam.W, y = u / a.cam.W;
-    const float4 nm = a.nmap[u];
+    const bool in = u < npx;
+    const int x = in ? u % a.cam.W : 0, y = in ? u / a.cam.W : 0;
+    const float4 nm = in ? a.nmap[u] : make_float4(0.f, 0.f, 0.f, 0.f);
     int best = -1, best_orig = 0x7fffffff;
     float best_c = 0.f, best_d2 = 0.f;
     const float d = nm.w;
     const float3 V = make_float3((((float)x - a.cam.cx) / a.cam.fx) * d, (((float)y - a.cam.cy) / a.cam.fy) * d, d);
     if (nm.w > 0.f) {
+        // the 16 keys, then the occupied ones' sorted indices, then their live
+        // surfels: three rounds of independent loads instead of a chain per
+        // candidate (the winner does not depend on the visiting order)
         const int W4 = 4 * a.cam.W;
+        unsigned long long key[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) key[q] = a.zmap4[(int64_t)(4 * y + (q >> 2)) * W4 + 4 * x + (q & 3)];
+        int sid[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sid[q] = key[q] != ~0ull ? a.inv[(int)(unsigned)(key[q] & 0xffffffffu)] : -1;
+#pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const unsigned long long key = a.zmap4[(int64_t)(4 * y + (q >> 2)) * W4 + 4 * x + (q & 3)];
-            if (key == ~0ull) continue;
-            const int org = (int)(unsigned)(key & 0xffffffffu);
-            const int s = a.inv[org];
+            const int s = sid[q];
+            if (s < 0) continue;
+            const int org = (int)(unsigned)(key[q] & 0xffffffffu);
             const float dx = a.lx[s] - V.x, dy = a.ly[s] - V.y, dz = a.lz[s] - V.z;
             const float d2 = (dx * dx + dy * dy) + dz * dz;
             const float dot = (a.lnx[s] * nm.x + a.lny[s] * nm.y) + a.lnz[s] * nm.z;
-            if (!(d2 <= a.dist2) || !(dot >= a.cosn)) continue;
             const float c = a.conf[s];
+            if (!(d2 <= a.dist2) || !(dot >= a.cosn)) continue;
             const bool better = best < 0 || c > best_c || (c == best_c && (d2 < best_d2 ||
                                                                      (d2 == best_d2 && org < best_orig)));
             if (better) {
@@ -94,11 +103,17 @@ __global__ void __launch_bounds__(256) k_fuse_match(FuseArgs a) {
                 best_d2 = d2;
             }
         }
-        if (best < 0) atomicAdd(&a.counts[1], 1);     // an append candidate (Sec. 6.3)
     }
+    // counts summed per wave, one atomic each: fused pixels and append
+    // candidates (pixels with a normal and no surfel, Sec. 6.4)
+    const unsigned long long bf = __ballot(best >= 0), bc = __ballot(nm.w > 0.f && best < 0);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (bf) atomicAdd(&a.counts[0], __popcll(bf));
+        if (bc) atomicAdd(&a.counts[1], __popcll(bc));
+    }
+    if (!in) return;
     a.match[u] = best < 0 ? -1 : best_orig;
     if (best < 0) return;
-    atomicAdd(&a.counts[0], 1);
     // the depth surfel (Sec. 5)
     const float gx = (float)x - a.cam.cx, gy = (float)y - a.cam.cy;
     const float gamma2 = (gx * gx + gy * gy) / (a.cam.cx * a.cam.cx + a.cam.cy * a.cam.cy);
