@@ -76,6 +76,9 @@ typedef struct sw_config {
     float append_nn;           /* delta_nn: append candidates whose kept nearest-node weight
                                   sum is below it are dropped (Sec. 6.4); the paper gives no
                                   value, 0.3 */
+    int32_t t_low_confid;      /* frames a surfel may stay below stable_conf after its
+                                  initialisation before the geometry update drops it, 30
+                                  (Table 1) */
 } sw_config;
 
 /* Statistics of one depth-map fusion (sw_fuse_frame). */
@@ -92,6 +95,13 @@ typedef struct sw_append_stats {
     int32_t n_appended;        /* survivors */
     int32_t n_written;         /* survivors written (at most max_out) */
 } sw_append_stats;
+
+/* Statistics of one geometry update (sw_update_geometry). */
+typedef struct sw_geometry_stats {
+    int32_t n_removed;         /* existing surfels dropped as unstable */
+    int32_t n_surfels;         /* surfels after the update */
+    sw_append_stats append;    /* the append selection (all survivors appended) */
+} sw_geometry_stats;
 
 /* Per-frame statistics, one entry per Gauss-Newton iteration (<= 16). */
 typedef struct sw_frame_stats {
@@ -168,16 +178,18 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
 
 /* ---- surfel attributes and depth-map fusion (Sec. 5, Sec. 6.1, Sec. 6.4) ---- */
 
-/* Radius (m), confidence and last observed frame of every surfel, in the
- * caller's surfel order (n = the count given to sw_set_reference_surfels);
- * any pointer may be NULL to keep that attribute. Defaults after
- * sw_set_reference_surfels: radius 0, confidence 1, t_observed 0. Setting
- * surfels again resets them. The data is copied. */
+/* Radius (m), confidence, last observed frame and initialisation frame of
+ * every surfel, in the caller's surfel order (n = the count given to
+ * sw_set_reference_surfels); any pointer may be NULL to keep that attribute.
+ * Defaults after sw_set_reference_surfels: radius 0, confidence 1,
+ * t_observed 0, t_init 0. Setting surfels again resets them. The data is
+ * copied. */
 sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, const float* confidence,
-                                   const int32_t* t_observed, int32_t on_device);
+                                   const int32_t* t_observed, const int32_t* t_init, int32_t on_device);
 
 /* Read the attributes (caller order, host arrays of n entries; NULL skips). */
-sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed);
+sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed,
+                                   int32_t* t_init);
 
 /* Read the reference surfels (n x 3 positions and normals, caller order, host):
  * the ones given, as updated by sw_fuse_frame. */
@@ -235,6 +247,20 @@ sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, 
 
 /* Live node positions T_k p_k at the current transforms (n_nodes x 3, host). */
 sw_status sw_get_live_nodes(sw_stream s, float* pos);
+
+/* Geometry update after a fusion (Sec. 6.4 and the GPU selection of Sec. 6.7),
+ * on the device: existing surfels whose confidence is below stable_conf more
+ * than t_low_confid frames after their t_init are dropped; the survivors of
+ * the append selection of the last fusion (as sw_append_candidates) are
+ * appended with t_init = t_observed = t_now; the surfel array becomes the
+ * kept surfels in their caller order followed by the appended ones in pixel
+ * order, and every surfel is skinned again to the same nodes, whose
+ * transforms are kept bit for bit (the node graph itself is not extended).
+ * Caller indices change accordingly; read the new surfels with
+ * sw_get_reference_surfels / sw_get_surfel_attributes. Synchronous. SW_ESTATE
+ * as sw_append_candidates; SW_EINVAL if no surfel would remain or the count
+ * would exceed the library's limit (nothing is changed then). */
+sw_status sw_update_geometry(sw_stream s, sw_geometry_stats* stats);
 
 /* ---- batches: frames of several streams solved together ----
  *

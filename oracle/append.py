@@ -30,7 +30,13 @@ Readings taken here (the paper leaves them open):
   point; "|d x_ref / d x_live|" in 3D is read as its largest singular value
   (the largest stretch of any direction);
 * appended surfels carry the depth surfel's radius and confidence (Sec. 5),
-  t_observed = t_now, and come in row-major pixel order.
+  t_init = t_observed = t_now, and come in row-major pixel order;
+* an existing surfel is dropped when its confidence is below delta_stable and
+  more than t_low_confid frames have passed since its t_init (Table 1: 10 and
+  30); the updated surfel array holds the kept surfels in their order, then
+  the appended ones (the compaction the complexity paragraph of Sec. 6.7
+  describes); the second removal rule (similarity to index-map neighbours) is
+  a criterion of Keller et al. the paper does not restate and is not taken.
 
 Integer decisions that have an exact FP32 form (nearest nodes, the ratio test)
 are taken in FP32 on the FP32 live node positions handed in, as the GPU holds
@@ -141,3 +147,20 @@ def append_candidates(match: np.ndarray, depth: np.ndarray, N32: np.ndarray, nva
     cd = depth_confidence(cam)[ys, xs]
     return dict(pixel=ys * W + xs, idx=idx, keep=keep, S=S, near=near, stretch=smax, compressive=compressive,
                 ok=ok, v_ref=vref, n_ref=nref, radius=rd, conf=cd)
+
+
+def unstable(conf: np.ndarray, t_init: np.ndarray, t_now: int, stable_conf: float, t_low_confid: int) -> np.ndarray:
+    """Surfels removed by the geometry update: confidence below delta_stable
+    (FP32 comparison) more than t_low_confid frames after initialisation."""
+    c = np.asarray(conf, np.float32)
+    return (c < np.float32(stable_conf)) & (int(t_now) - np.asarray(t_init, np.int64) > int(t_low_confid))
+
+
+def update_surfels(pos, nrm, rad, conf, t_obs, t_init, keep, app: dict, t_now: int):
+    """The updated surfel array: kept surfels in order, then the appended ones."""
+    ok = app["ok"]
+    n_app = int(ok.sum())
+    cat = lambda a, b: np.concatenate([np.asarray(a)[keep], b])
+    return dict(pos=cat(pos, app["v_ref"][ok]), nrm=cat(nrm, app["n_ref"][ok]), radius=cat(rad, app["radius"][ok]),
+                conf=cat(conf, app["conf"][ok]), t_obs=cat(t_obs, np.full(n_app, t_now)),
+                t_init=cat(t_init, np.full(n_app, t_now)))

@@ -23,6 +23,9 @@
 //                 row-major pixel order) writes its pixel, reference position
 //                 and normal, and the depth surfel's radius and confidence
 //                 (Sec. 5), up to the caller's capacity.
+//   keep_mark, compact_surfels   the geometry update: flags of the existing
+//                 surfels that stay, then (after a scan) the kept surfels and
+//                 the appended ones copied into fresh caller-order arrays.
 #include "swgn_fusion.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
@@ -189,7 +192,69 @@ __global__ void __launch_bounds__(256) k_append_write(AppendArgs a, const int* _
     a.out_rad[k] = 1.41421356237f * nm.w / (a.cam.fx * fmaxf(fabsf(nm.z), a.cos_max));
 }
 
+// Geometry update (Sec. 6.4): an existing surfel stays unless its confidence
+// is below delta_stable more than t_low_confid frames after its t_init.
+__global__ void __launch_bounds__(256) k_keep_mark(int ns, const float* __restrict__ conf,
+                                                   const int* __restrict__ tinit, int t_now, float stable,
+                                                   int t_low, int* __restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns) flag[i] = (conf[i] < stable && t_now - tinit[i] > t_low) ? 0 : 1;
+}
+
+// The updated arrays: kept surfel i at pos[i], appended surfel k at nkeep + k.
+__global__ void __launch_bounds__(256) k_compact_surfels(CompactArgs c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < c.ns) {
+        if (!c.flag[i]) return;
+        const int j = c.pos[i];
+        for (int q = 0; q < 3; ++q) {
+            c.dpos[3 * (int64_t)j + q] = c.spos[3 * (int64_t)i + q];
+            c.dnrm[3 * (int64_t)j + q] = c.snrm[3 * (int64_t)i + q];
+        }
+        c.drad[j] = c.srad[i];
+        c.dconf[j] = c.sconf[i];
+        c.dtobs[j] = c.stobs[i];
+        c.dtinit[j] = c.stinit[i];
+    } else if (i < c.ns + c.napp) {
+        const int k = i - c.ns, j = c.nkeep + k;
+        for (int q = 0; q < 3; ++q) {
+            c.dpos[3 * (int64_t)j + q] = c.apos[3 * (int64_t)k + q];
+            c.dnrm[3 * (int64_t)j + q] = c.anrm[3 * (int64_t)k + q];
+        }
+        c.drad[j] = c.arad[k];
+        c.dconf[j] = c.aconf[k];
+        c.dtobs[j] = c.t_now;
+        c.dtinit[j] = c.t_now;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_f4_to_positions(int n, const float4* __restrict__ in,
+                                                         float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = in[i];
+    out[3 * i + 0] = p.x;
+    out[3 * i + 1] = p.y;
+    out[3 * i + 2] = p.z;
+}
+
 }  // namespace
+
+void launch_f4_to_positions(int n, const float4* in, float* out, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_f4_to_positions, dim3((n + 255) / 256), dim3(256), 0, st, n, in, out);
+}
+
+void launch_keep_mark(int ns, const float* conf, const int* tinit, int t_now, float stable, int t_low, int* flag,
+                      hipStream_t st) {
+    if (ns > 0)
+        hipLaunchKernelGGL(k_keep_mark, dim3((ns + 255) / 256), dim3(256), 0, st, ns, conf, tinit, t_now, stable,
+                           t_low, flag);
+}
+
+void launch_compact_surfels(const CompactArgs& c, hipStream_t st) {
+    const int64_t n = (int64_t)c.ns + c.napp;
+    if (n > 0) hipLaunchKernelGGL(k_compact_surfels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c);
+}
 
 void launch_append(const AppendArgs& a, int* pos, int* scan_tmp, hipStream_t st) {
     const int npx = a.cam.W * a.cam.H;

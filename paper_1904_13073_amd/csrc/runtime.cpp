@@ -204,6 +204,7 @@ sw_status check_config(const sw_config* c, std::string& why) {
     }
     if (!(finite(c->warp_eps) && c->warp_eps > 0 && c->warp_eps < 1)) { why = "warp_eps must be in (0, 1)"; return SW_EINVAL; }
     if (!(finite(c->append_nn) && c->append_nn >= 0)) { why = "append_nn must be >= 0"; return SW_EINVAL; }
+    if (c->t_low_confid < 0) { why = "t_low_confid must be >= 0"; return SW_EINVAL; }
     return SW_OK;
 }
 
@@ -286,7 +287,8 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int4* 
     s->nent = (int64_t)L.ent_sub.size();
 }
 
-void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_se3, int32_t on_device) {
+void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_se3, int32_t on_device,
+                 const float4* keep_rq, const float4* keep_tt) {
     hipStream_t st = s->exec.st;
     s->graph_mem.release();
     s->ws_mem.release();
@@ -333,7 +335,14 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
         se3_in = tmp.alloc<float>(12 * (size_t)nn);
         copy_in(se3_in, node_se3, sizeof(float) * 12 * nn, on_device, st);
     }
-    launch_nodes_from_se3(nn, se3_in, pref, h.rq, h.tt, h.dq, h.cl, st);
+    if (keep_rq) {
+        // the node state as it is (a rebuild after a geometry update)
+        SWGN_HIP(hipMemcpyAsync(h.rq, keep_rq, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
+        SWGN_HIP(hipMemcpyAsync(h.tt, keep_tt, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
+        launch_tables_from_state(nn, pref, h.rq, h.tt, h.dq, h.cl, st);
+    } else {
+        launch_nodes_from_se3(nn, se3_in, pref, h.rq, h.tt, h.dq, h.cl, st);
+    }
 
     // skinning and node graph
     int4* idx_in = tmp.alloc<int4>(ns);
@@ -808,6 +817,7 @@ void sw_config_default(sw_config* c) {
     c->fusion_normal = 0.85f;
     c->warp_eps = 0.2f;
     c->append_nn = 0.3f;
+    c->t_low_confid = 30;
 }
 
 const char* sw_status_string(sw_status st) {
@@ -880,13 +890,15 @@ sw_status sw_set_reference_surfels(sw_stream s, int64_t n, const float* pos, con
         s->in_nrm = s->surf_mem.alloc<float>(3 * (size_t)n);
         copy_in(s->in_pos, pos, sizeof(float) * 3 * n, on_device, s->exec.st);
         copy_in(s->in_nrm, nrm, sizeof(float) * 3 * n, on_device, s->exec.st);
-        // attributes: radius 0, confidence 1, last observed frame 0
+        // attributes: radius 0, confidence 1, last observed and initialisation frame 0
         s->in_rad = s->surf_mem.alloc<float>(n);
         s->in_conf = s->surf_mem.alloc<float>(n);
         s->in_tobs = s->surf_mem.alloc<int>(n);
+        s->in_tinit = s->surf_mem.alloc<int>(n);
         launch_fill_i32(reinterpret_cast<int*>(s->in_rad), (int)n, 0, s->exec.st);
         launch_fill_i32(reinterpret_cast<int*>(s->in_conf), (int)n, 0x3f800000, s->exec.st);
         launch_fill_i32(s->in_tobs, (int)n, 0, s->exec.st);
+        launch_fill_i32(s->in_tinit, (int)n, 0, s->exec.st);
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
         s->surfels_set = true;
         return SW_OK;
@@ -902,7 +914,7 @@ sw_status sw_set_node_graph(sw_stream s, int32_t n_nodes, const float* node_pos,
     if (!node_pos) return fail(s->err, SW_EINVAL, "node positions must not be NULL");
     if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
     return guarded(s->err, [&]() -> sw_status {
-        build_graph(s, n_nodes, node_pos, node_se3, on_device);
+        build_graph(s, n_nodes, node_pos, node_se3, on_device, nullptr, nullptr);
         return SW_OK;
     });
 }
@@ -957,7 +969,7 @@ sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity) {
 // ---- surfel attributes and depth-map fusion ----
 
 sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, const float* confidence,
-                                   const int32_t* t_observed, int32_t on_device) {
+                                   const int32_t* t_observed, const int32_t* t_init, int32_t on_device) {
     if (!s) return SW_EINVAL;
     if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
     if (!s->surfels_set) return fail(s->err, SW_ESTATE, "surfels must be set first");
@@ -968,6 +980,7 @@ sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, 
         if (radius) copy_in(s->in_rad, radius, sizeof(float) * n, on_device, st);
         if (confidence) copy_in(s->in_conf, confidence, sizeof(float) * n, on_device, st);
         if (t_observed) copy_in(s->in_tobs, t_observed, sizeof(int32_t) * n, on_device, st);
+        if (t_init) copy_in(s->in_tinit, t_init, sizeof(int32_t) * n, on_device, st);
         if (s->graph_set)
             launch_fuse_gather((int)s->ns, s->h.orig, s->in_rad, s->in_conf, s->in_tobs, s->h.radius, s->h.conf,
                                s->h.t_obs, const_cast<int*>(s->h.inv), st);
@@ -977,7 +990,8 @@ sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, 
     });
 }
 
-sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed) {
+sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence, int32_t* t_observed,
+                                   int32_t* t_init) {
     if (!s) return SW_EINVAL;
     if (s->server) server_quiesce(s->server, s);
     if (!s->surfels_set) return fail(s->err, SW_ESTATE, "surfels not set");
@@ -987,6 +1001,7 @@ sw_status sw_get_surfel_attributes(sw_stream s, float* radius, float* confidence
         if (radius) SWGN_HIP(hipMemcpyAsync(radius, s->in_rad, sizeof(float) * n, hipMemcpyDeviceToHost, st));
         if (confidence) SWGN_HIP(hipMemcpyAsync(confidence, s->in_conf, sizeof(float) * n, hipMemcpyDeviceToHost, st));
         if (t_observed) SWGN_HIP(hipMemcpyAsync(t_observed, s->in_tobs, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        if (t_init) SWGN_HIP(hipMemcpyAsync(t_init, s->in_tinit, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
         SWGN_HIP(hipStreamSynchronize(st));
         return SW_OK;
     });
@@ -1105,67 +1120,93 @@ sw_status sw_get_last_fusion(sw_stream s, int32_t* match_map, float* live_pos, f
     });
 }
 
-sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, int32_t* pixel, float* pos,
-                               float* nrm, float* radius, float* confidence, sw_append_stats* stats) {
-    if (!s) return SW_EINVAL;
+namespace {
+
+// The append selection of the last fusion into out_* (device arrays of
+// capacity max_out), or into the stream's staging arrays (capacity npx) when
+// pixel is NULL; counts into stats. The caller has checked the state.
+void run_append(sw_stream s, int32_t max_out, int32_t* pixel, float* pos, float* nrm, float* radius,
+                float* confidence, sw_append_stats* stats) {
+    hipStream_t st = s->exec.st;
+    const FrameDesc& h = s->h;
+    const int npx = h.npx;
+    if (!s->aflag) {
+        s->aflag = s->append_mem.alloc<int>(npx + 1);
+        s->apos = s->append_mem.alloc<int>(npx + 1);
+        s->ascan = s->append_mem.alloc<int>(scan_tmp_size(npx + 1));
+        s->acount = s->append_mem.alloc<int>(4);
+        s->asv = s->append_mem.alloc<float4>(npx);
+        s->asn = s->append_mem.alloc<float4>(npx);
+        s->apix = s->append_mem.alloc<int>(npx);
+        s->apos3 = s->append_mem.alloc<float>(3 * (size_t)npx);
+        s->anrm3 = s->append_mem.alloc<float>(3 * (size_t)npx);
+        s->arad = s->append_mem.alloc<float>(npx);
+        s->aconf = s->append_mem.alloc<float>(npx);
+    }
+    AppendArgs a{};
+    a.cam = h.cam;
+    a.nn = h.nn;
+    a.eps = s->cfg.warp_eps;
+    a.delta_nn = s->cfg.append_nn;
+    a.inv2s2 = 1.0f / (2.0f * s->cfg.node_sigma * s->cfg.node_sigma);
+    a.cos_max = 0.258819045f;              // cos 75 deg
+    a.nmap = h.nmap;
+    a.match = s->fmatch;
+    a.cl = h.cl;
+    a.pref = h.pref;
+    a.dq = h.dq;
+    a.flag = s->aflag;
+    a.sv = s->asv;
+    a.sn = s->asn;
+    a.counts = s->acount;
+    if (pixel) {
+        a.max_out = max_out;
+        a.out_pixel = pixel; a.out_pos = pos; a.out_nrm = nrm; a.out_rad = radius; a.out_conf = confidence;
+    } else {
+        a.max_out = std::min(max_out, npx);
+        a.out_pixel = s->apix; a.out_pos = s->apos3; a.out_nrm = s->anrm3; a.out_rad = s->arad;
+        a.out_conf = s->aconf;
+    }
+    launch_fill_i32(s->acount, 4, 0, st);
+    launch_fill_i32(s->aflag + npx, 1, 0, st);
+    launch_append(a, s->apos, s->ascan, st);
+    SWGN_HIP(hipGetLastError());
+    int* hc = s->fcount_host;
+    SWGN_HIP(hipMemcpyAsync(hc + 2, s->acount, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(hc + 5, s->apos + npx, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipStreamSynchronize(st));
+    stats->n_candidates = hc[2];
+    stats->n_far = hc[3];
+    stats->n_compressive = hc[4];
+    stats->n_appended = hc[5];
+    stats->n_written = std::min(hc[5], a.max_out);
+}
+
+sw_status append_state(sw_stream s) {
     if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
     if (!s->graph_set || !s->fused || s->fuse_gen != s->depth_gen)
         return fail(s->err, SW_ESTATE, "append candidates need a fusion as the stream's last depth frame");
+    return SW_OK;
+}
+
+}  // namespace
+
+sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, int32_t* pixel, float* pos,
+                               float* nrm, float* radius, float* confidence, sw_append_stats* stats) {
+    if (!s) return SW_EINVAL;
+    if (append_state(s) != SW_OK) return SW_ESTATE;
     if (max_out < 0) return fail(s->err, SW_EINVAL, "max_out must be >= 0");
     if (max_out > 0 && !(pixel && pos && nrm && radius && confidence))
         return fail(s->err, SW_EINVAL, "output pointers must not be NULL when max_out > 0");
     if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
     return guarded(s->err, [&]() -> sw_status {
         hipStream_t st = s->exec.st;
-        const FrameDesc& h = s->h;
-        const int npx = h.npx;
-        if (!s->aflag) {
-            s->aflag = s->append_mem.alloc<int>(npx + 1);
-            s->apos = s->append_mem.alloc<int>(npx + 1);
-            s->ascan = s->append_mem.alloc<int>(scan_tmp_size(npx + 1));
-            s->acount = s->append_mem.alloc<int>(4);
-            s->asv = s->append_mem.alloc<float4>(npx);
-            s->asn = s->append_mem.alloc<float4>(npx);
-            s->apix = s->append_mem.alloc<int>(npx);
-            s->apos3 = s->append_mem.alloc<float>(3 * (size_t)npx);
-            s->anrm3 = s->append_mem.alloc<float>(3 * (size_t)npx);
-            s->arad = s->append_mem.alloc<float>(npx);
-            s->aconf = s->append_mem.alloc<float>(npx);
-        }
-        AppendArgs a{};
-        a.cam = h.cam;
-        a.nn = h.nn;
-        a.eps = s->cfg.warp_eps;
-        a.delta_nn = s->cfg.append_nn;
-        a.inv2s2 = 1.0f / (2.0f * s->cfg.node_sigma * s->cfg.node_sigma);
-        a.cos_max = 0.258819045f;              // cos 75 deg
-        a.nmap = h.nmap;
-        a.match = s->fmatch;
-        a.cl = h.cl;
-        a.pref = h.pref;
-        a.dq = h.dq;
-        a.flag = s->aflag;
-        a.sv = s->asv;
-        a.sn = s->asn;
-        a.counts = s->acount;
-        if (on_device) {
-            a.max_out = max_out;
-            a.out_pixel = pixel; a.out_pos = pos; a.out_nrm = nrm; a.out_rad = radius; a.out_conf = confidence;
-        } else {
-            a.max_out = std::min(max_out, npx);
-            a.out_pixel = s->apix; a.out_pos = s->apos3; a.out_nrm = s->anrm3; a.out_rad = s->arad;
-            a.out_conf = s->aconf;
-        }
-        launch_fill_i32(s->acount, 4, 0, st);
-        launch_fill_i32(s->aflag + npx, 1, 0, st);
-        launch_append(a, s->apos, s->ascan, st);
-        SWGN_HIP(hipGetLastError());
-        int* hc = s->fcount_host;
-        SWGN_HIP(hipMemcpyAsync(hc + 2, s->acount, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-        SWGN_HIP(hipMemcpyAsync(hc + 5, s->apos + npx, sizeof(int), hipMemcpyDeviceToHost, st));
-        SWGN_HIP(hipStreamSynchronize(st));
-        const int n = hc[5];
-        const int nw = std::min(n, a.max_out);
+        sw_append_stats as{};
+        if (on_device && max_out > 0)
+            run_append(s, max_out, pixel, pos, nrm, radius, confidence, &as);
+        else
+            run_append(s, on_device ? 0 : max_out, nullptr, nullptr, nullptr, nullptr, nullptr, &as);
+        const int nw = as.n_written;
         if (!on_device && nw > 0) {
             SWGN_HIP(hipMemcpyAsync(pixel, s->apix, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
             SWGN_HIP(hipMemcpyAsync(pos, s->apos3, sizeof(float) * 3 * nw, hipMemcpyDeviceToHost, st));
@@ -1174,12 +1215,68 @@ sw_status sw_append_candidates(sw_stream s, int32_t max_out, int32_t on_device, 
             SWGN_HIP(hipMemcpyAsync(confidence, s->aconf, sizeof(float) * nw, hipMemcpyDeviceToHost, st));
             SWGN_HIP(hipStreamSynchronize(st));
         }
+        if (stats) *stats = as;
+        return SW_OK;
+    });
+}
+
+sw_status sw_update_geometry(sw_stream s, sw_geometry_stats* stats) {
+    if (!s) return SW_EINVAL;
+    if (append_state(s) != SW_OK) return SW_ESTATE;
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        const int ns = (int)s->ns;
+        const int nn = s->h.nn;
+        sw_append_stats as{};
+        run_append(s, s->h.npx, nullptr, nullptr, nullptr, nullptr, nullptr, &as);
+        const int napp = as.n_written;
+        // which existing surfels stay (caller order), and where
+        Arena tmp;
+        int* flag = tmp.alloc<int>(ns + 1);
+        int* pos = tmp.alloc<int>(ns + 1);
+        int* scan = tmp.alloc<int>(scan_tmp_size(ns + 1));
+        launch_keep_mark(ns, s->in_conf, s->in_tinit, s->t_now, s->cfg.stable_conf, s->cfg.t_low_confid, flag, st);
+        launch_fill_i32(flag + ns, 1, 0, st);
+        exclusive_scan(flag, pos, ns + 1, scan, st);
+        const int nkeep = read_scalar(pos + ns, st);
+        const int64_t nnew = (int64_t)nkeep + napp;
+        if (nnew < 1 || nnew >= kMaxSurfels)
+            return fail(s->err, SW_EINVAL, "the update would leave no surfel or exceed the surfel limit");
+        // the node state and positions, kept across the rebuild
+        float4* rq = tmp.alloc<float4>(nn);
+        float4* tt = tmp.alloc<float4>(nn);
+        float* np3 = tmp.alloc<float>(3 * (size_t)nn);
+        SWGN_HIP(hipMemcpyAsync(rq, s->h.rq, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
+        SWGN_HIP(hipMemcpyAsync(tt, s->h.tt, sizeof(float4) * nn, hipMemcpyDeviceToDevice, st));
+        launch_f4_to_positions(nn, s->h.pref, np3, st);
+        // the compacted caller-order arrays
+        Arena fresh;
+        CompactArgs c{};
+        c.ns = ns; c.nkeep = nkeep; c.napp = napp; c.t_now = s->t_now;
+        c.flag = flag; c.pos = pos;
+        c.spos = s->in_pos; c.snrm = s->in_nrm; c.srad = s->in_rad; c.sconf = s->in_conf;
+        c.stobs = s->in_tobs; c.stinit = s->in_tinit;
+        c.apos = s->apos3; c.anrm = s->anrm3; c.arad = s->arad; c.aconf = s->aconf;
+        c.dpos = fresh.alloc<float>(3 * (size_t)nnew);
+        c.dnrm = fresh.alloc<float>(3 * (size_t)nnew);
+        c.drad = fresh.alloc<float>(nnew);
+        c.dconf = fresh.alloc<float>(nnew);
+        c.dtobs = fresh.alloc<int>(nnew);
+        c.dtinit = fresh.alloc<int>(nnew);
+        launch_compact_surfels(c, st);
+        SWGN_HIP(hipGetLastError());
+        SWGN_HIP(hipStreamSynchronize(st));
+        // swap in the new surfels (the old arrays go with `fresh`) and rebuild
+        s->surf_mem.swap(fresh);
+        s->ns = nnew;
+        s->in_pos = c.dpos; s->in_nrm = c.dnrm; s->in_rad = c.drad; s->in_conf = c.dconf;
+        s->in_tobs = c.dtobs; s->in_tinit = c.dtinit;
+        build_graph(s, nn, np3, nullptr, 1, rq, tt);
+        SWGN_HIP(hipStreamSynchronize(st));
         if (stats) {
-            stats->n_candidates = hc[2];
-            stats->n_far = hc[3];
-            stats->n_compressive = hc[4];
-            stats->n_appended = n;
-            stats->n_written = nw;
+            stats->n_removed = ns - nkeep;
+            stats->n_surfels = (int32_t)nnew;
+            stats->append = as;
         }
         return SW_OK;
     });

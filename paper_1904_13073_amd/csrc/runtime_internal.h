@@ -44,6 +44,10 @@ public:
     }
     void release();
     size_t bytes() const { return bytes_; }
+    void swap(Arena& o) {
+        ptrs_.swap(o.ptrs_);
+        std::swap(bytes_, o.bytes_);
+    }
 
 private:
     std::vector<void*> ptrs_;
@@ -114,6 +118,7 @@ struct sw_stream_s {
     float* in_rad = nullptr;              // attributes, caller order (kept current by fusion)
     float* in_conf = nullptr;
     int* in_tobs = nullptr;
+    int* in_tinit = nullptr;
     int t_now = 0;                        // frame time (visibility of recent surfels)
 
     // depth-map fusion workspace, allocated on first use

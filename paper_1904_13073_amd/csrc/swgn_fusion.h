@@ -64,6 +64,27 @@ struct AppendArgs {
 // number of survivors) and compaction.
 void launch_append(const AppendArgs& a, int* pos, int* scan_tmp, hipStream_t st);
 
+// flag[i] = 1 for the existing surfels a geometry update keeps (caller order).
+void launch_keep_mark(int ns, const float* conf, const int* tinit, int t_now, float stable, int t_low, int* flag,
+                      hipStream_t st);
+
+// Arguments of the compaction of a geometry update: the kept surfels (flag,
+// exclusive-scan positions pos) and napp appended ones into fresh arrays.
+struct CompactArgs {
+    int ns, nkeep, napp, t_now;
+    const int *flag, *pos;
+    const float *spos, *snrm, *srad, *sconf;
+    const int *stobs, *stinit;
+    const float *apos, *anrm, *arad, *aconf;
+    float *dpos, *dnrm, *drad, *dconf;
+    int *dtobs, *dtinit;
+};
+
+void launch_compact_surfels(const CompactArgs& c, hipStream_t st);
+
+// Node positions as float4 -> packed x, y, z.
+void launch_f4_to_positions(int n, const float4* in, float* out, hipStream_t st);
+
 // Sorted copies of the caller-order attributes (sorted i takes caller
 // orig[i]) and the inverse permutation inv[orig[i]] = i.
 void launch_fuse_gather(int ns, const int* orig, const float* crad, const float* cconf, const int* ctobs,

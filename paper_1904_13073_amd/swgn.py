@@ -28,7 +28,8 @@ class SwConfig(C.Structure):
                 ("jac_dtype", C.c_int32), ("dot_fp64", C.c_int32), ("debug_iter", C.c_int32),
                 ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32), ("visibility", C.c_int32),
                 ("stable_conf", C.c_float), ("recent_frames", C.c_int32), ("fusion_dist", C.c_float),
-                ("fusion_normal", C.c_float), ("warp_eps", C.c_float), ("append_nn", C.c_float)]
+                ("fusion_normal", C.c_float), ("warp_eps", C.c_float), ("append_nn", C.c_float),
+                ("t_low_confid", C.c_int32)]
 
 
 class SwFusionStats(C.Structure):
@@ -38,6 +39,10 @@ class SwFusionStats(C.Structure):
 class SwAppendStats(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("n_far", C.c_int32), ("n_compressive", C.c_int32),
                 ("n_appended", C.c_int32), ("n_written", C.c_int32)]
+
+
+class SwGeometryStats(C.Structure):
+    _fields_ = [("n_removed", C.c_int32), ("n_surfels", C.c_int32), ("append", SwAppendStats)]
 
 
 class SwFrameStats(C.Structure):
@@ -95,7 +100,7 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
            "sw_batch_autotune", "sw_get_layout", "sw_set_surfel_attributes", "sw_get_surfel_attributes",
            "sw_get_reference_surfels", "sw_set_frame_time", "sw_fuse_frame", "sw_get_last_fusion",
-           "sw_append_candidates", "sw_get_live_nodes"]
+           "sw_append_candidates", "sw_get_live_nodes", "sw_update_geometry"]
 
 SW_EPENDING = 1
 
@@ -132,14 +137,15 @@ def lib() -> C.CDLL:
         "sw_get_last_maps": (i32, [vp, ip, ip, fp, fp]),
         "sw_get_last_system": (i32, [vp, fp, fp, fp]),
         "sw_get_last_jacobian": (i32, [vp, fp, fp]),
-        "sw_set_surfel_attributes": (i32, [vp, i64, fp, fp, ip, i32]),
-        "sw_get_surfel_attributes": (i32, [vp, fp, fp, ip]),
+        "sw_set_surfel_attributes": (i32, [vp, i64, fp, fp, ip, ip, i32]),
+        "sw_get_surfel_attributes": (i32, [vp, fp, fp, ip, ip]),
         "sw_get_reference_surfels": (i32, [vp, fp, fp]),
         "sw_set_frame_time": (i32, [vp, i32]),
         "sw_fuse_frame": (i32, [vp, fp, i32, i32, C.POINTER(SwFusionStats)]),
         "sw_get_last_fusion": (i32, [vp, ip, fp, fp]),
         "sw_append_candidates": (i32, [vp, i32, i32, ip, fp, fp, fp, fp, C.POINTER(SwAppendStats)]),
         "sw_get_live_nodes": (i32, [vp, fp]),
+        "sw_update_geometry": (i32, [vp, C.POINTER(SwGeometryStats)]),
         "sw_create_batch": (i32, [vp, i32, C.POINTER(vp)]),
         "sw_destroy_batch": (i32, [vp]),
         "sw_batch_last_error": (C.c_char_p, [vp]),
@@ -458,25 +464,36 @@ def sw_get_last_jacobian(h):
     return r, J
 
 
-def sw_set_surfel_attributes(h, radius=None, confidence=None, t_observed=None):
+def sw_set_surfel_attributes(h, radius=None, confidence=None, t_observed=None, t_init=None):
     ns, _, _ = sw_get_sizes(h)
     pr, dr, kr = _ptr(radius, np.float32)
     pc, dc, kc = _ptr(confidence, np.float32)
     pt, dt, kt = _ptr(t_observed, np.int32)
-    devs = {d for d, p in ((dr, pr), (dc, pc), (dt, pt)) if p is not None}
+    pi, di, ki = _ptr(t_init, np.int32)
+    devs = {d for d, p in ((dr, pr), (dc, pc), (dt, pt), (di, pi)) if p is not None}
     if len(devs) > 1:
         raise ValueError("attributes must all be host arrays or all device tensors")
-    _check(h, lib().sw_set_surfel_attributes(h, ns, pr, pc, pt, devs.pop() if devs else 0))
+    _check(h, lib().sw_set_surfel_attributes(h, ns, pr, pc, pt, pi, devs.pop() if devs else 0))
 
 
-def sw_get_surfel_attributes(h):
+def sw_get_surfel_attributes(h, with_t_init: bool = False):
+    """(radius, confidence, t_observed[, t_init]) in caller order."""
     ns, _, _ = sw_get_sizes(h)
     r = np.empty(ns, np.float32)
     c = np.empty(ns, np.float32)
     t = np.empty(ns, np.int32)
+    ti = np.empty(ns, np.int32)
     _check(h, lib().sw_get_surfel_attributes(h, r.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p),
-                                             t.ctypes.data_as(C.c_void_p)))
-    return r, c, t
+                                             t.ctypes.data_as(C.c_void_p), ti.ctypes.data_as(C.c_void_p)))
+    return (r, c, t, ti) if with_t_init else (r, c, t)
+
+
+def sw_update_geometry(h) -> dict:
+    st = SwGeometryStats()
+    _check(h, lib().sw_update_geometry(h, C.byref(st)))
+    out = {"n_removed": st.n_removed, "n_surfels": st.n_surfels}
+    out["append"] = {f: getattr(st.append, f) for f, _ in st.append._fields_}
+    return out
 
 
 def sw_get_reference_surfels(h):
@@ -601,11 +618,14 @@ class Stream:
     def last_jacobian(self):
         return sw_get_last_jacobian(self.h)
 
-    def set_surfel_attributes(self, radius=None, confidence=None, t_observed=None):
-        sw_set_surfel_attributes(self.h, radius, confidence, t_observed)
+    def set_surfel_attributes(self, radius=None, confidence=None, t_observed=None, t_init=None):
+        sw_set_surfel_attributes(self.h, radius, confidence, t_observed, t_init)
 
-    def surfel_attributes(self):
-        return sw_get_surfel_attributes(self.h)
+    def surfel_attributes(self, with_t_init: bool = False):
+        return sw_get_surfel_attributes(self.h, with_t_init)
+
+    def update_geometry(self) -> dict:
+        return sw_update_geometry(self.h)
 
     def reference_surfels(self):
         return sw_get_reference_surfels(self.h)

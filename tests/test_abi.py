@@ -58,7 +58,7 @@ def test_defaults_and_status_strings():
     ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
     ("rigid_iters", 17), ("rigid_iters", -1), ("visibility", 2), ("stable_conf", float("inf")),
     ("recent_frames", -1), ("fusion_dist", 0.0), ("fusion_normal", 1.5),
-    ("warp_eps", 0.0), ("warp_eps", 1.0), ("append_nn", -0.1), ("append_nn", float("nan")),
+    ("warp_eps", 0.0), ("warp_eps", 1.0), ("append_nn", -0.1), ("append_nn", float("nan")), ("t_low_confid", -1),
 ])
 def test_create_rejects_bad_config(field, value):
     from paper_1904_13073_amd import swgn
@@ -109,8 +109,8 @@ def test_fusion_entry_points_validate_on_the_host():
     L = swgn.lib()
     st = swgn.SwFusionStats()
     assert L.sw_fuse_frame(None, None, 0, 0, C.byref(st)) == swgn.SW_EINVAL
-    assert L.sw_set_surfel_attributes(None, 1, None, None, None, 0) == swgn.SW_EINVAL
-    assert L.sw_get_surfel_attributes(None, None, None, None) == swgn.SW_EINVAL
+    assert L.sw_set_surfel_attributes(None, 1, None, None, None, None, 0) == swgn.SW_EINVAL
+    assert L.sw_get_surfel_attributes(None, None, None, None, None) == swgn.SW_EINVAL
     assert L.sw_get_reference_surfels(None, None, None) == swgn.SW_EINVAL
     assert L.sw_set_frame_time(None, 3) == swgn.SW_EINVAL
     assert L.sw_get_last_fusion(None, None, None, None) == swgn.SW_EINVAL
@@ -121,3 +121,6 @@ def test_fusion_entry_points_validate_on_the_host():
     ast = swgn.SwAppendStats()
     assert L.sw_append_candidates(None, 0, 0, None, None, None, None, None, C.byref(ast)) == swgn.SW_EINVAL
     assert L.sw_get_live_nodes(None, None) == swgn.SW_EINVAL
+    gst = swgn.SwGeometryStats()
+    assert L.sw_update_geometry(None, C.byref(gst)) == swgn.SW_EINVAL
+    assert c.t_low_confid == 30

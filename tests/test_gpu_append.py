@@ -135,3 +135,46 @@ def test_appended_surfels_join_the_model(swgn, scene_cache):
     st.close()
     assert r1["n_corr"][0] >= r0["n_corr"][-1]
     assert np.isfinite(r1["e_data"]).all()
+
+
+def test_geometry_update_removes_appends_and_reskins(swgn, scene_cache):
+    """sw_update_geometry: the long-unstable surfels go, the append survivors
+    of the same fusion follow the kept ones, the node state is untouched and
+    the new surfels are skinned as a fresh set would be (bit-exact nearest
+    nodes); the next solve runs on the updated model."""
+    from oracle import skin
+    s = scene_cache("tiny")
+    ns = s.surfel_pos.shape[0]
+    rng = np.random.default_rng(8)
+    conf = rng.uniform(1.0, 20.0, ns).astype(np.float32)
+    t_init = rng.integers(0, 40, ns).astype(np.int32)
+    st = stream_for(swgn, s, fusion_dist=0.004)
+    st.set_surfel_attributes(None, conf, None, t_init)
+    st.solve_frame(s.depth)
+    se3 = st.node_se3()
+    st.fuse_frame(s.depth, t_now=45)
+    pos0, nrm0 = st.reference_surfels()
+    rad0, conf0, tob0, ti0 = st.surfel_attributes(with_t_init=True)
+    app = st.append_candidates()
+    g = st.update_geometry()
+    keep = ~A.unstable(conf0, ti0, 45, 10.0, 30)
+    assert g["n_removed"] == int((~keep).sum()) > 0
+    assert g["append"]["n_appended"] == app["n_appended"] > 0
+    assert g["n_surfels"] == int(keep.sum()) + app["n_appended"] == st.sizes()[0]
+    pos1, nrm1 = st.reference_surfels()
+    rad1, conf1, tob1, ti1 = st.surfel_attributes(with_t_init=True)
+    na = app["n_appended"]
+    assert np.array_equal(pos1, np.concatenate([pos0[keep], app["pos"]]))
+    assert np.array_equal(nrm1, np.concatenate([nrm0[keep], app["nrm"]]))
+    assert np.array_equal(rad1, np.concatenate([rad0[keep], app["radius"]]))
+    assert np.array_equal(conf1, np.concatenate([conf0[keep], app["confidence"]]))
+    assert np.array_equal(tob1, np.concatenate([tob0[keep], np.full(na, 45, np.int32)]))
+    assert np.array_equal(ti1, np.concatenate([ti0[keep], np.full(na, 45, np.int32)]))
+    assert np.array_equal(st.node_se3(), se3)
+    idx, _ = st.skinning()
+    assert np.array_equal(idx, skin.knn_fp32(pos1, s.node_pos, 4))
+    with pytest.raises(swgn.SwError):
+        st.update_geometry()                                        # the fused frame is spent
+    r = st.solve_frame(s.depth)
+    st.close()
+    assert r["n_corr"][0] > 0 and np.isfinite(r["e_data"]).all()

@@ -145,3 +145,21 @@ def test_pipeline_candidates_weights_and_attributes():
     ys_c, xs_c = np.divmod(out["pixel"], 24)
     assert np.allclose(out["radius"], F.depth_radius(depth.astype(np.float64), N32.astype(np.float64), cam)[ys_c, xs_c])
     assert np.allclose(out["conf"], F.depth_confidence(cam)[ys_c, xs_c])
+
+
+def test_unstable_surfels_and_the_updated_array():
+    conf = np.array([1.0, 12.0, 9.99, 10.0, 3.0, 50.0], np.float32)
+    t_init = np.array([0, 0, 0, 0, 20, 0])
+    gone = A.unstable(conf, t_init, 31, 10.0, 30)
+    # below 10 and older than 30 frames: 0 and 2; 3 sits at the threshold, 4 is young
+    assert gone.tolist() == [True, False, True, False, False, False]
+    assert not A.unstable(conf, t_init, 30, 10.0, 30).any()        # exactly 30 frames: kept
+    app = dict(ok=np.array([True, False, True]), v_ref=np.arange(9.0).reshape(3, 3),
+               n_ref=-np.arange(9.0).reshape(3, 3), radius=np.array([0.1, 0.2, 0.3]), conf=np.array([0.5, 0.6, 0.7]))
+    pos = np.arange(18.0).reshape(6, 3)
+    out = A.update_surfels(pos, -pos, np.full(6, 0.01), conf, np.zeros(6, int), t_init, ~gone, app, 31)
+    assert np.array_equal(out["pos"], np.concatenate([pos[[1, 3, 4, 5]], [[0, 1, 2], [6, 7, 8]]]))
+    assert np.array_equal(out["nrm"][-2:], [[0, -1, -2], [-6, -7, -8]])
+    assert out["radius"].tolist() == [0.01] * 4 + [0.1, 0.3]
+    assert out["t_obs"].tolist() == [0, 0, 0, 0, 31, 31] and out["t_init"].tolist() == [0, 0, 20, 0, 31, 31]
+    assert np.allclose(out["conf"], [12.0, 10.0, 3.0, 50.0, 0.5, 0.7])
