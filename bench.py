@@ -414,10 +414,27 @@ def main():
         a = time.perf_counter()
         fstats = fst.fuse_frame(depth, t_now=2 + k)
         flat.append(time.perf_counter() - a)
+    # the geometry update after a fusion (removal, appending, compaction and
+    # re-skinning of every surfel): each timed call follows an untimed fusion
     fst.close()
+    glat = []
+    gstats = None
+    for k in range(3):
+        gst = make_stream()
+        gst.solve_frame(depth, with_stats=False)
+        gst.fuse_frame(depth, t_now=1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        gstats = gst.update_geometry()
+        glat.append(time.perf_counter() - a)
+        gst.close()
     fusion = {"us_per_frame": {"p50": round(1e6 * percentile(flat, 0.5), 1),
                                "mean": round(1e6 * float(np.mean(flat)), 1)},
-              "n_fused": fstats["n_fused"], "n_candidates": fstats["n_candidates"]}
+              "n_fused": fstats["n_fused"], "n_candidates": fstats["n_candidates"],
+              "geometry_update_ms": {"p50": round(1e3 * percentile(glat, 0.5), 3),
+                                     "surfels_after": gstats["n_surfels"],
+                                     "appended": gstats["append"]["n_appended"],
+                                     "removed": gstats["n_removed"]}}
     print(f"[bench] fusion: {fusion}", file=sys.stderr, flush=True)
 
     batched = None

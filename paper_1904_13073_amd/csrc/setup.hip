@@ -54,33 +54,48 @@ __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restric
     out_w[i] = make_float4(e0 * inv, e1 * inv, e2 * inv, e3 * inv);
 }
 
-__global__ void __launch_bounds__(256) k_node_graph(int nn, const float4* __restrict__ nodes,
-                                                    int* __restrict__ nbr) {
-    __shared__ float4 tile[kKnnTile];
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    float4 me = j < nn ? nodes[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+// One wave per node j: lane l keeps the 8 nearest of the nodes l, l + 64, ...
+// (ascending index, so equal keys keep the lower index first), then the wave
+// merges its 64 sorted lists by taking, 8 times, the smallest (key, index)
+// head: the same set and order as one sequential scan.
+constexpr int kGraphNodesPerBlock = 4;
+
+__global__ void __launch_bounds__(64 * kGraphNodesPerBlock) k_node_graph(int nn, const float4* __restrict__ nodes,
+                                                                         int* __restrict__ nbr) {
+    const int lane = threadIdx.x % kWave;
+    const int j = blockIdx.x * kGraphNodesPerBlock + threadIdx.x / kWave;
+    if (j >= nn) return;                     // whole waves: no barrier follows
+    const float4 me = nodes[j];
     float kd[8];
     int ki[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) { kd[q] = INFINITY; ki[q] = 0; }
-    for (int base = 0; base < nn; base += kKnnTile) {
-        int cnt = min(kKnnTile, nn - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = nodes[base + t];
-        __syncthreads();
-        if (j < nn) {
-            for (int t = 0; t < cnt; ++t) {
-                if (base + t == j) continue;
-                float4 p = tile[t];
-                float dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
-                float key = (dx * dx + dy * dy) + dz * dz;
-                knn_insert<8>(kd, ki, key, base + t);
-            }
+    for (int q = 0; q < 8; ++q) { kd[q] = INFINITY; ki[q] = 0x7fffffff; }
+    for (int t = lane; t < nn; t += kWave) {
+        if (t == j) continue;
+        const float4 p = nodes[t];
+        const float dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+        knn_insert<8>(kd, ki, (dx * dx + dy * dy) + dz * dz, t);
+    }
+    int out = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        float bk = kd[0];
+        int bi = ki[0];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ok = __shfl_xor(bk, o, kWave);
+            const int oi = __shfl_xor(bi, o, kWave);
+            if (ok < bk || (ok == bk && oi < bi)) { bk = ok; bi = oi; }
+        }
+        if (lane == r) out = bi;
+        if (ki[0] == bi) {                   // this lane's head was taken: shift its list
+#pragma unroll
+            for (int q = 0; q < 7; ++q) { kd[q] = kd[q + 1]; ki[q] = ki[q + 1]; }
+            kd[7] = INFINITY;
+            ki[7] = 0x7fffffff;
         }
     }
-    if (j >= nn) return;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) nbr[8 * j + q] = ki[q];
+    if (lane < 8) nbr[8 * j + lane] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -472,7 +487,8 @@ void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, 
 }
 
 void launch_node_graph(int nn, const float4* nodes, int* nbr, hipStream_t st) {
-    hipLaunchKernelGGL(k_node_graph, dim3((nn + 255) / 256), dim3(256), 0, st, nn, nodes, nbr);
+    hipLaunchKernelGGL(k_node_graph, dim3((nn + kGraphNodesPerBlock - 1) / kGraphNodesPerBlock),
+                       dim3(64 * kGraphNodesPerBlock), 0, st, nn, nodes, nbr);
 }
 
 void launch_tuple_keys(int ns, int npad, const int4* idx, uint64_t* key, uint32_t* val, hipStream_t st) {
