@@ -24,6 +24,7 @@
 
 #include "runtime_internal.h"
 #include "segments.h"
+#include "swgn_setup.h"
 #include "swgn_fusion.h"
 #include "swgn.h"
 #include "swgn_frame.h"
@@ -37,17 +38,29 @@ namespace swgn {
 namespace rt {
 
 void* Arena::raw(size_t bytes) {
-    void* p = nullptr;
+    constexpr size_t kFirstChunk = (size_t)4 << 20, kMaxChunk = (size_t)256 << 20;
     bytes = ((bytes == 0 ? 1 : bytes) + 255) & ~size_t(255);
-    SWGN_HIP(hipMalloc(&p, bytes));
-    ptrs_.push_back(p);
+    if (!chunks_.empty()) {
+        Chunk& c = chunks_.back();
+        if (c.size - c.used >= bytes) {
+            char* p = c.base + c.used;
+            c.used += bytes;
+            bytes_ += bytes;
+            return p;
+        }
+    }
+    const size_t grow = chunks_.empty() ? kFirstChunk : std::min(kMaxChunk, 2 * chunks_.back().size);
+    const size_t size = std::max(bytes, grow);
+    void* p = nullptr;
+    SWGN_HIP(hipMalloc(&p, size));
+    chunks_.push_back(Chunk{static_cast<char*>(p), size, bytes});
     bytes_ += bytes;
     return p;
 }
 
 void Arena::release() {
-    for (void* p : ptrs_) (void)hipFree(p);
-    ptrs_.clear();
+    for (const Chunk& c : chunks_) (void)hipFree(c.base);
+    chunks_.clear();
     bytes_ = 0;
 }
 
@@ -240,21 +253,26 @@ void publish_desc(sw_stream s) {
 // of whole segments with at most kCorrBlock surfels. Each block's entries
 // list the float offsets of its sub-blocks (and, for a diagonal block, of the
 // matching J^T r piece) in segment order.
-void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int4* sidx, const int* row_ptr,
-                    const int* col_idx, Arena& G) {
+// The segment layout: on the host from the runs of equal node sets (keys and
+// run starts only, a few bytes per run), then each surfel's node positions
+// on the device.
+void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* set_start, int nsets,
+                    const int4* sidx, const int* row_ptr, const int* col_idx, Arena& G, Arena& tmp) {
     hipStream_t st = s->exec.st;
     const int ns = h.ns, nn = h.nn;
-    std::vector<uint64_t> hkey(ns);
-    std::vector<int32_t> hidx(4 * (size_t)ns);
-    std::vector<int> hrow(nn + 1), hcol(h.nb);
-    SWGN_HIP(hipMemcpyAsync(hkey.data(), key, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, st));
-    SWGN_HIP(hipMemcpyAsync(hidx.data(), sidx, sizeof(int4) * ns, hipMemcpyDeviceToHost, st));
+    uint64_t* d_keys = tmp.alloc<uint64_t>(std::max(1, nsets));
+    launch_set_keys(nsets, key, set_start, d_keys, st);
+    std::vector<uint64_t> hkey(nsets);
+    std::vector<int> hstart(nsets + 1), hrow(nn + 1), hcol(h.nb);
+    SWGN_HIP(hipMemcpyAsync(hkey.data(), d_keys, sizeof(uint64_t) * nsets, hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(hstart.data(), set_start, sizeof(int) * (nsets + 1), hipMemcpyDeviceToHost, st));
     SWGN_HIP(hipMemcpyAsync(hrow.data(), row_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
     SWGN_HIP(hipMemcpyAsync(hcol.data(), col_idx, sizeof(int) * h.nb, hipMemcpyDeviceToHost, st));
     SWGN_HIP(hipStreamSynchronize(st));
     SegmentLayout L;
     std::string why;
-    if (!segment_layout(ns, nn, h.nb, hkey.data(), hidx.data(), hrow.data(), hcol.data(), kCorrPack, L, why))
+    if (!segment_layout_sets(nsets, hkey.data(), hstart.data(), nn, h.nb, hrow.data(), hcol.data(), kCorrPack, L,
+                             why))
         throw HipFail{hipErrorInvalidValue, why};
     const int nseg = (int)L.mask.size();
     auto up = [&](auto* dst, const auto& v) {
@@ -269,9 +287,16 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int4* 
     int* d_ep = G.alloc<int>(L.ent_ptr.size());
     uint32_t* d_es = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_sub.size()));
     uint32_t* d_eg = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_grad.size()));
-    up(d_seg, L.seg_start); up(d_pos4, L.pos4); up(d_mask, L.mask); up(d_off, L.off);
+    int* d_nodes = tmp.alloc<int>(std::max<size_t>(1, L.seg_nodes.size()));
+    int* d_bad = tmp.alloc<int>(1);
+    up(d_seg, L.seg_start); up(d_mask, L.mask); up(d_off, L.off);
     up(d_ps, L.pack_start); up(d_pg, L.pack_seg); up(d_ep, L.ent_ptr); up(d_es, L.ent_sub); up(d_eg, L.ent_grad);
-    SWGN_HIP(hipStreamSynchronize(st));
+    up(d_nodes, L.seg_nodes);
+    launch_fill_i32(d_bad, 1, 0, st);
+    launch_seg_pos4(ns, nseg, d_seg, d_nodes, sidx, d_pos4, d_bad, st);
+    SWGN_HIP(hipGetLastError());
+    if (read_scalar(d_bad, st) != 0)
+        throw HipFail{hipErrorInvalidValue, "segment layout: a surfel's slot nodes differ from its node set"};
     h.nseg = nseg;
     h.npack = (int)L.pack_start.size() - 1;
     h.part_floats = (int64_t)L.total;
@@ -402,7 +427,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     launch_offlist(h.nb, blk_row, col_idx, offlist, st);
     h.offlist = offlist;
 
-    build_segments(s, h, key, sidx, row_ptr, col_idx, G);
+    build_segments(s, h, key, set_start, s->nsets, sidx, row_ptr, col_idx, G, tmp);
 
     // in-edges of every node (j with the node in N_j), ascending j
     const int npad_i = pow2_at_least(8 * (int64_t)nn, 1024);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -37,20 +38,27 @@ struct HipFail {
 class Arena {
 public:
     ~Arena() { release(); }
+    // 256-byte aligned; carved from the current chunk of device memory or a new
+    // one (chunks grow geometrically from 4 MiB, so an arena of many arrays
+    // costs a few hipMalloc calls, not one per array)
     void* raw(size_t bytes);
     template <class T>
     T* alloc(size_t n) {
         return static_cast<T*>(raw(n * sizeof(T)));
     }
     void release();
-    size_t bytes() const { return bytes_; }
+    size_t bytes() const { return bytes_; }   // bytes handed out (aligned)
     void swap(Arena& o) {
-        ptrs_.swap(o.ptrs_);
+        chunks_.swap(o.chunks_);
         std::swap(bytes_, o.bytes_);
     }
 
 private:
-    std::vector<void*> ptrs_;
+    struct Chunk {
+        char* base;
+        size_t size, used;
+    };
+    std::vector<Chunk> chunks_;
     size_t bytes_ = 0;
 };
 

@@ -18,75 +18,88 @@ void decode_key(uint64_t k, int* t) {
 
 }  // namespace
 
-bool segment_layout(int ns, int nn, int nb, const uint64_t* key, const int32_t* idx4, const int* row_ptr,
-                    const int* col_idx, int max_surfels, SegmentLayout& L, std::string& why) {
+bool segment_layout_sets(int nsets, const uint64_t* set_key, const int* set_start, int nn, int nb,
+                         const int* row_ptr, const int* col_idx, int max_surfels, SegmentLayout& L,
+                         std::string& why) {
     L = SegmentLayout{};
-    if (ns < 0 || nn <= 0 || nb < nn || max_surfels <= 0) {
+    if (nsets < 0 || nn <= 0 || nb < nn || max_surfels <= 0 || (nsets > 0 && set_start[0] != 0)) {
         why = "segment layout: bad sizes";
         return false;
     }
-    // greedy runs whose node union stays within 5 nodes
-    std::vector<int> nodes;                              // 5 per segment, -1 padded
+    // greedy segments whose node union stays within 5 nodes and max_surfels
+    // surfels; within a run of one node set only the length can cut, so the
+    // walk is per run: a run that does not fit starts a segment, a long one is
+    // cut every max_surfels surfels
+    std::vector<uint64_t> seg_sets;      // node sets of the open segment
+    std::vector<int> seg_set_ptr{0};     // per closed segment: its range in all_sets
+    std::vector<uint64_t> all_sets;
     int cur[5] = {-1, -1, -1, -1, -1}, cn = 0, start = 0;
     auto close = [&]() {
         L.seg_start.push_back(start);
-        for (int q = 0; q < 5; ++q) nodes.push_back(q < cn ? cur[q] : -1);
+        for (int q = 0; q < 5; ++q) L.seg_nodes.push_back(q < cn ? cur[q] : -1);
+        all_sets.insert(all_sets.end(), seg_sets.begin(), seg_sets.end());
+        seg_set_ptr.push_back((int)all_sets.size());
+        seg_sets.clear();
     };
-    for (int i = 0; i < ns; ++i) {
+    for (int r = 0; r < nsets; ++r) {
         int t[4];
-        decode_key(key[i], t);
+        decode_key(set_key[r], t);
         for (int k = 0; k < 4; ++k)
             if (t[k] >= nn || (k > 0 && t[k] <= t[k - 1])) {
                 why = "segment layout: a node set is not 4 distinct ascending nodes";
                 return false;
             }
-        if (i > 0 && key[i] < key[i - 1]) {
-            why = "segment layout: surfels are not sorted by node set";
+        const int a = set_start[r], b = set_start[r + 1];
+        if (b <= a || (r > 0 && set_key[r] <= set_key[r - 1])) {
+            why = "segment layout: node-set runs are empty or not ascending";
             return false;
         }
-        // union of the run's nodes and t, ascending; at most 5 + 4 entries
-        int u[9], un = 0, a = 0, b = 0;
-        while (a < cn || b < 4) {
+        // union of the segment's nodes and t, ascending; at most 5 + 4 entries
+        int u[9], un = 0, x = 0, y = 0;
+        while (x < cn || y < 4) {
             int v;
-            if (b >= 4 || (a < cn && cur[a] < t[b])) v = cur[a++];
-            else if (a >= cn || t[b] < cur[a]) v = t[b++];
-            else { v = cur[a++]; ++b; }
+            if (y >= 4 || (x < cn && cur[x] < t[y])) v = cur[x++];
+            else if (x >= cn || t[y] < cur[x]) v = t[y++];
+            else { v = cur[x++]; ++y; }
             u[un++] = v;
         }
-        if (i == 0 || un > 5 || i - start >= max_surfels) {
-            if (i > 0) close();
-            start = i;
+        if (r == 0 || un > 5 || a - start >= max_surfels) {
+            if (r > 0) close();
+            start = a;
             cn = 4;
             for (int q = 0; q < 4; ++q) cur[q] = t[q];
         } else {
             cn = un;
             for (int q = 0; q < un; ++q) cur[q] = u[q];
         }
+        seg_sets.push_back(set_key[r]);
+        while (b - start > max_surfels) {
+            close();
+            start += max_surfels;
+            cn = 4;
+            for (int q = 0; q < 4; ++q) cur[q] = t[q];
+            seg_sets.push_back(set_key[r]);
+        }
     }
-    if (ns > 0) close();
+    if (nsets > 0) close();
     const int nseg = (int)L.seg_start.size();
+    const int ns = nsets > 0 ? set_start[nsets] : 0;
     L.seg_start.push_back(ns);
 
-    // positions of each surfel's nodes, pair mask and offset of each segment
-    L.pos4.assign(ns, 0);
+    // pair mask (from the node sets a segment holds) and offset of each segment
     L.mask.assign(nseg, 0);
     L.off.assign(nseg + 1, 0);
     uint64_t total = 0;
     for (int g = 0; g < nseg; ++g) {
-        const int* nd = &nodes[5 * g];
+        const int* nd = &L.seg_nodes[5 * g];
         uint32_t m = 0;
-        for (int i = L.seg_start[g]; i < L.seg_start[g + 1]; ++i) {
-            int p[4];
+        for (int q = seg_set_ptr[g]; q < seg_set_ptr[g + 1]; ++q) {
+            int t[4], p[4];
+            decode_key(all_sets[q], t);
             for (int k = 0; k < 4; ++k) {
-                const int id = idx4[4 * (int64_t)i + k];
                 p[k] = 0;
-                while (p[k] < 5 && nd[p[k]] != id) ++p[k];
-                if (p[k] == 5) {
-                    why = "segment layout: a surfel's slot nodes differ from its node set";
-                    return false;
-                }
+                while (p[k] < 5 && nd[p[k]] != t[k]) ++p[k];
             }
-            L.pos4[i] = (uint16_t)(p[0] | (p[1] << 3) | (p[2] << 6) | (p[3] << 9));
             for (int x = 0; x < 4; ++x)
                 for (int y = 0; y < 4; ++y)
                     if (p[x] <= p[y]) m |= 1u << (first_pair(p[x]) + p[y] - p[x]);
@@ -105,8 +118,9 @@ bool segment_layout(int ns, int nn, int nb, const uint64_t* key, const int32_t* 
     // entries of every block in segment order (a counting sort by block)
     struct Ent { int blk; uint32_t sub, grad; };
     std::vector<Ent> ents;
+    ents.reserve((size_t)nseg * 10);
     for (int g = 0; g < nseg; ++g) {
-        const int* nd = &nodes[5 * g];
+        const int* nd = &L.seg_nodes[5 * g];
         const uint32_t m = L.mask[g];
         const uint32_t np = (uint32_t)__builtin_popcount(m);
         uint32_t rank = 0;
@@ -148,6 +162,51 @@ bool segment_layout(int ns, int nn, int nb, const uint64_t* key, const int32_t* 
         }
     L.pack_start.push_back(ns);
     L.pack_seg.push_back(nseg);
+    return true;
+}
+
+bool segment_layout(int ns, int nn, int nb, const uint64_t* key, const int32_t* idx4, const int* row_ptr,
+                    const int* col_idx, int max_surfels, SegmentLayout& L, std::string& why) {
+    if (ns < 0) {
+        why = "segment layout: bad sizes";
+        return false;
+    }
+    // runs of equal keys
+    std::vector<uint64_t> set_key;
+    std::vector<int> set_start;
+    for (int i = 0; i < ns; ++i) {
+        if (i > 0 && key[i] < key[i - 1]) {
+            why = "segment layout: surfels are not sorted by node set";
+            return false;
+        }
+        if (i == 0 || key[i] != key[i - 1]) {
+            set_key.push_back(key[i]);
+            set_start.push_back(i);
+        }
+    }
+    set_start.push_back(ns);
+    if (!segment_layout_sets((int)set_key.size(), set_key.data(), set_start.data(), nn, nb, row_ptr, col_idx,
+                             max_surfels, L, why))
+        return false;
+    // positions of each surfel's nodes among its segment's nodes
+    L.pos4.assign(ns, 0);
+    const int nseg = (int)L.seg_start.size() - 1;
+    for (int g = 0; g < nseg; ++g) {
+        const int* nd = &L.seg_nodes[5 * g];
+        for (int i = L.seg_start[g]; i < L.seg_start[g + 1]; ++i) {
+            int p[4];
+            for (int k = 0; k < 4; ++k) {
+                const int id = idx4[4 * (int64_t)i + k];
+                p[k] = 0;
+                while (p[k] < 5 && nd[p[k]] != id) ++p[k];
+                if (p[k] == 5) {
+                    why = "segment layout: a surfel's slot nodes differ from its node set";
+                    return false;
+                }
+            }
+            L.pos4[i] = (uint16_t)(p[0] | (p[1] << 3) | (p[2] << 6) | (p[3] << 9));
+        }
+    }
     return true;
 }
 

@@ -21,7 +21,8 @@ namespace swgn {
 
 struct SegmentLayout {
     std::vector<int> seg_start;         // [nseg + 1]
-    std::vector<uint16_t> pos4;         // [ns]
+    std::vector<int> seg_nodes;         // [5 nseg] the segment's nodes, ascending, -1 padded
+    std::vector<uint16_t> pos4;         // [ns] (segment_layout only)
     std::vector<uint16_t> mask;         // [nseg]
     std::vector<uint32_t> off;          // [nseg + 1] float offsets
     std::vector<int> ent_ptr;           // [nb + 1]
@@ -40,5 +41,14 @@ struct SegmentLayout {
 // storage would exceed 2^32 floats.
 bool segment_layout(int ns, int nn, int nb, const uint64_t* key, const int32_t* idx4, const int* row_ptr,
                     const int* col_idx, int max_surfels, SegmentLayout& out, std::string& why);
+
+// The same layout from the runs of equal node sets alone (everything but
+// pos4, which depends on each surfel's slot order): run r holds surfels
+// set_start[r] .. set_start[r + 1] - 1 (non-empty, set_start[0] = 0), all with
+// node set set_key[r]; keys strictly ascend. The work is per run and per
+// segment, not per surfel.
+bool segment_layout_sets(int nsets, const uint64_t* set_key, const int* set_start, int nn, int nb,
+                         const int* row_ptr, const int* col_idx, int max_surfels, SegmentLayout& out,
+                         std::string& why);
 
 }  // namespace swgn

@@ -8,6 +8,7 @@
 // integer OR / ADD whose results do not depend on order.
 #include "swgn_impl.h"
 #include "swgn_launch.h"
+#include "swgn_setup.h"
 
 namespace swgn {
 
@@ -280,6 +281,46 @@ __global__ void k_run_starts(int ns, const int* __restrict__ flag, const int* __
     if (i == 0) run_start[pos[ns]] = ns;
 }
 
+// The node set of every run (its first surfel's key).
+__global__ void k_set_keys(int nsets, const uint64_t* __restrict__ key, const int* __restrict__ run_start,
+                           uint64_t* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nsets) out[r] = key[run_start[r]];
+}
+
+// Positions (3 bits each) of surfel i's 4 nodes, in its slot order, among
+// its segment's nodes; the segment is found by binary search over the
+// segment starts. A node missing from the segment sets *bad.
+__global__ void k_seg_pos4(int ns, int nseg, const int* __restrict__ seg_start, const int* __restrict__ seg_nodes,
+                           const int4* __restrict__ idx, uint16_t* __restrict__ pos4, int* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    int lo = 0, hi = nseg - 1;                 // largest g with seg_start[g] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    int nd[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) nd[q] = seg_nodes[5 * lo + q];
+    const int4 t = idx[i];
+    const int id[4] = {t.x, t.y, t.z, t.w};
+    int code = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int p = 5;
+#pragma unroll
+        for (int q = 4; q >= 0; --q)
+            if (nd[q] == id[k]) p = q;
+        ok = ok && p < 5;
+        code |= (p < 5 ? p : 0) << (3 * k);
+    }
+    pos4[i] = (uint16_t)code;
+    if (!ok) atomicOr(bad, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Block pattern: bitmap of the upper triangle, one row of nn bits per node.
 // ---------------------------------------------------------------------------
@@ -501,6 +542,18 @@ void launch_permute_surfels(int ns, int seg_len, const uint64_t* key, const uint
                             int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_permute_surfels, dim3((ns + 255) / 256), dim3(256), 0, st, ns, seg_len, key, val, ipos, inrm,
                        iidx, iw, px, py, pz, nx, ny, nz, oidx, ow, orig, flag);
+}
+
+void launch_set_keys(int nsets, const uint64_t* key, const int* run_start, uint64_t* out, hipStream_t st) {
+    if (nsets > 0)
+        hipLaunchKernelGGL(k_set_keys, dim3((nsets + 255) / 256), dim3(256), 0, st, nsets, key, run_start, out);
+}
+
+void launch_seg_pos4(int ns, int nseg, const int* seg_start, const int* seg_nodes, const int4* idx, uint16_t* pos4,
+                     int* bad, hipStream_t st) {
+    if (ns > 0 && nseg > 0)
+        hipLaunchKernelGGL(k_seg_pos4, dim3((ns + 255) / 256), dim3(256), 0, st, ns, nseg, seg_start, seg_nodes, idx,
+                           pos4, bad);
 }
 
 void launch_run_starts(int ns, const int* flag, const int* pos, int* run_start, hipStream_t st) {
