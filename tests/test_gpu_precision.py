@@ -27,7 +27,7 @@ def swgn():
     return gpu_lib()
 
 
-@pytest.mark.parametrize("name", ["tiny", "c1"])
+@pytest.mark.parametrize("name", ["tiny", "c1", "c2"])
 def test_jacobian_precision_against_the_oracle(swgn, scene_cache, name):
     """Each storage type against the FP64 oracle run on that solve's own
     correspondences (captured per iteration; they may differ from the
