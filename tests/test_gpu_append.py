@@ -178,3 +178,28 @@ def test_geometry_update_removes_appends_and_reskins(swgn, scene_cache):
     r = st.solve_frame(s.depth)
     st.close()
     assert r["n_corr"][0] > 0 and np.isfinite(r["e_data"]).all()
+
+
+def test_empty_frame_fuses_nothing_and_an_update_that_would_empty_the_model_is_refused(swgn, scene_cache):
+    """A depth frame without measurements: no pixel has a normal, so nothing
+    fuses and nothing is a candidate. With every surfel unstable and old, an
+    update would leave no surfel: it is refused and the model stays usable."""
+    s = scene_cache("tiny")
+    ns = s.surfel_pos.shape[0]
+    st = stream_for(swgn, s)
+    st.set_surfel_attributes(None, np.full(ns, 1.0, np.float32), None, np.zeros(ns, np.int32))
+    pos0, _ = st.reference_surfels()
+    empty = np.zeros_like(s.depth)
+    f = st.fuse_frame(empty, t_now=100)
+    assert f == {"n_fused": 0, "n_candidates": 0}
+    match = st.last_fusion()[0]
+    assert np.all(match == -1)
+    a = st.append_candidates()
+    assert a["n_candidates"] == a["n_appended"] == 0 and a["pixel"].size == 0
+    assert np.array_equal(st.reference_surfels()[0], pos0)
+    with pytest.raises(swgn.SwError):
+        st.update_geometry()                                        # would remove all surfels, append none
+    assert st.sizes()[0] == ns
+    r = st.solve_frame(s.depth)
+    st.close()
+    assert r["n_corr"][0] > 0
