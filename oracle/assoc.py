@@ -11,7 +11,11 @@ Readings taken here:
 * surfel i corresponds to pixel u_i it projects to iff it won u_i in the index
   map, u_i has a depth normal, |v_i - V(u_i)| < corr_dist and
   n_i . N(u_i) > corr_normal;
-* the map is re-rendered and P re-associated at every Gauss-Newton iteration.
+* the map is re-rendered and P re-associated at every Gauss-Newton iteration;
+* with splats (the surfels as opaque discs of their radius, Sec. 7), P is
+  taken per pixel: every pixel with a normal pairs with the surfel that won
+  it, under the same gates on the surfel's centre and normal, so a surfel can
+  hold several pairs (replica32.splat_index_map states the rendering).
 
 All of these are integer decisions, taken by `replica32` on the FP32-rounded
 live surfels.
@@ -47,3 +51,14 @@ def associate(v_live: np.ndarray, n_live: np.ndarray, valid: np.ndarray,
     m, ux, uy = replica32.correspondence(v32, n32, I, frame.depth, frame.N32, frame.nvalid,
                                          cam, corr_dist, corr_normal, valid)
     return I, m, ux, uy
+
+
+def associate_splats(v_live: np.ndarray, n_live: np.ndarray, radius: np.ndarray, valid: np.ndarray,
+                     frame: DepthFrame, cam, corr_dist: float, corr_normal: float):
+    """Splat index map and its pairs (surfel, pixel x, pixel y), row-major."""
+    v32 = v_live.astype(np.float32)
+    n32 = n_live.astype(np.float32)
+    I = replica32.splat_index_map(v32, n32, radius, cam, valid)
+    k, ux, uy = replica32.splat_pairs(v32, n32, I, frame.depth, frame.N32, frame.nvalid, cam, corr_dist,
+                                      corr_normal)
+    return I, k, ux, uy

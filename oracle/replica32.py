@@ -14,7 +14,9 @@ operation order written below. The decisions are:
   towards the camera) (Sec. 5);
 * the pixel of a projection, floor(fx*(x/z) + cx + 0.5) (Sec. 6.1, 7);
 * the index-map winner: smallest (FP32 z bits, surfel index) (Sec. 7);
-* the correspondence gates |v - V(u)|^2 < dist^2 and n . N(u) > cos (Sec. 7).
+* the correspondence gates |v - V(u)|^2 < dist^2 and n . N(u) > cos (Sec. 7);
+* with splats (Sec. 7, surfels as opaque discs): the footprint box, the
+  ray-disc coverage test and the hit depth (see splat_index_map).
 
 Nothing in this module is an FP64 quantity of the oracle; it only decides.
 """
@@ -156,3 +158,94 @@ def correspondence(v: np.ndarray, n: np.ndarray, I: np.ndarray, depth: np.ndarra
         dot = (n[:, 0] * Nd[:, 0] + n[:, 1] * Nd[:, 1]) + n[:, 2] * Nd[:, 2]
         m &= dot > f32(corr_normal)
     return m, ux, uy
+
+
+SPLAT_MAX_PX = 4          # half-size cap of a splat's pixel box
+
+
+def splat_index_map(v: np.ndarray, n: np.ndarray, radius: np.ndarray, cam, valid: np.ndarray | None = None):
+    """Index map of opaque disc splats: per pixel the surfel with the smallest
+    (FP32 hit depth bits, index), -1 where none.
+
+    A surfel whose centre projects into the image to pixel (ux, uy) (the point
+    rule of `project`) is tried on the pixels of the box ux +- h, uy +- h
+    (clipped to the image), h = min(4, ceil(fx r / z)) in FP32. The ray of
+    pixel u is d = ((u_x - cx)/fx, (u_y - cy)/fy, 1); with nd = n . d and
+    nv = n . v, the hit is t = nv / nd, P = t d, and the pixel is covered if
+    nd != 0, t > 0 and |P - v|^2 <= r^2; its depth is t. A surfel of radius 0
+    is an unsized point: its centre pixel at depth z."""
+    v = v.astype(f32)
+    n = n.astype(f32)
+    r = np.asarray(radius, f32)
+    ux0, uy0, inside = project(v, cam)
+    if valid is not None:
+        inside = inside & valid
+    W, H = cam.width, cam.height
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        rho = (f32(cam.fx) * r) / v[:, 2]
+        h = np.where(inside, np.minimum(SPLAT_MAX_PX, np.ceil(np.where(inside, rho, f32(0)))), 0).astype(np.int64)
+    pix_l, key_l, id_l = [], [], []
+    ids_all = np.arange(v.shape[0])
+    for oy in range(-SPLAT_MAX_PX, SPLAT_MAX_PX + 1):
+        for ox in range(-SPLAT_MAX_PX, SPLAT_MAX_PX + 1):
+            sel = inside & (np.abs(ox) <= h) & (np.abs(oy) <= h)
+            ux = ux0 + ox
+            uy = uy0 + oy
+            sel &= (ux >= 0) & (ux < W) & (uy >= 0) & (uy < H)
+            ids = ids_all[sel]
+            if ids.size == 0:
+                continue
+            vx, vy, vz = v[ids, 0], v[ids, 1], v[ids, 2]
+            nx, ny, nz = n[ids, 0], n[ids, 1], n[ids, 2]
+            point = r[ids] == f32(0)
+            with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+                dx = (ux[ids].astype(f32) - f32(cam.cx)) / f32(cam.fx)
+                dy = (uy[ids].astype(f32) - f32(cam.cy)) / f32(cam.fy)
+                nd = (nx * dx + ny * dy) + nz
+                nv = (nx * vx + ny * vy) + nz * vz
+                t = nv / nd
+                ex = t * dx - vx
+                ey = t * dy - vy
+                ez = t - vz
+                e2 = (ex * ex + ey * ey) + ez * ez
+                cov = (nd != f32(0)) & (t > f32(0)) & (e2 <= r[ids] * r[ids])
+            centre = (ox == 0) & (oy == 0)
+            take = np.where(point, centre, cov)
+            depth = np.where(point, vz, t)
+            pix_l.append((uy[ids] * W + ux[ids])[take])
+            key_l.append(depth[take].astype(f32).view(np.uint32))
+            id_l.append(ids[take])
+    I = np.full(W * H, -1, dtype=np.int64)
+    if pix_l:
+        pix = np.concatenate(pix_l)
+        key = np.concatenate(key_l)
+        idv = np.concatenate(id_l)
+        order = np.lexsort((idv, key, pix))
+        ps = pix[order]
+        first = np.ones(order.size, dtype=bool)
+        first[1:] = ps[1:] != ps[:-1]
+        I[ps[first]] = idv[order][first]
+    return I.reshape(H, W)
+
+
+def splat_pairs(v: np.ndarray, n: np.ndarray, I: np.ndarray, depth: np.ndarray, N32: np.ndarray,
+                nvalid: np.ndarray, cam, corr_dist: float, corr_normal: float):
+    """Pixel-driven pairs of a splat index map: pixel u with a normal pairs
+    with its winner k if |v_k - V(u)|^2 < dist^2 and n_k . N(u) > cos (FP32,
+    the surfel's centre and normal). Returns the surfel and pixel (x, y) of
+    every pair, in row-major pixel order."""
+    v = v.astype(f32)
+    n = n.astype(f32)
+    uy, ux = np.nonzero((I >= 0) & nvalid)
+    k = I[uy, ux]
+    D = depth.astype(f32)[uy, ux]
+    Vd = backproject(ux, uy, D, cam)
+    Nd = N32[uy, ux]
+    with np.errstate(invalid="ignore", over="ignore"):
+        dx = v[k, 0] - Vd[:, 0]
+        dy = v[k, 1] - Vd[:, 1]
+        dz = v[k, 2] - Vd[:, 2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        dot = (n[k, 0] * Nd[:, 0] + n[k, 1] * Nd[:, 1]) + n[k, 2] * Nd[:, 2]
+        ok = (d2 < f32(corr_dist) * f32(corr_dist)) & (dot > f32(corr_normal))
+    return k[ok], ux[ok], uy[ok]

@@ -50,6 +50,7 @@ class Problem:
     corr_dist: float
     corr_normal: float
     visible: Optional[np.ndarray] = None     # surfels rendered into the index map (None: all)
+    splat_radius: Optional[np.ndarray] = None  # render opaque disc splats of these radii (None: points)
 
 
 def visible_surfels(conf: np.ndarray, t_observed: np.ndarray, t_now: int, stable_conf: float,
@@ -62,7 +63,7 @@ def visible_surfels(conf: np.ndarray, t_observed: np.ndarray, t_now: int, stable
 
 
 def make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
-                 idx=None, w=None, nbr=None, visible=None) -> Problem:
+                 idx=None, w=None, nbr=None, visible=None, splat_radius=None) -> Problem:
     if idx is None or w is None:
         idx, w = skin.skinning(surfel_pos, node_pos, params.node_sigma)
     if nbr is None:
@@ -73,7 +74,8 @@ def make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
                    depthmod.vertex_map(depth, cam), depthmod.normal_map(depth, cam),
                    float(params.lambda_reg), float(params.damping),
                    float(params.corr_dist), float(params.corr_normal),
-                   None if visible is None else np.asarray(visible, bool))
+                   None if visible is None else np.asarray(visible, bool),
+                   None if splat_radius is None else np.asarray(splat_radius, np.float32))
 
 
 def node_tables(node_pos: np.ndarray, R: np.ndarray, t: np.ndarray):
@@ -103,6 +105,8 @@ def linearize(pb: Problem, R: np.ndarray, t: np.ndarray, corr_map: Optional[np.n
     boundary, a gate at its threshold); the association itself is the one
     decided here."""
     ws = warp_surfels(pb, R, t)
+    if pb.splat_radius is not None:
+        return _linearize_pairs(pb, R, t, ws, corr_map)
     I, m, ux, uy = assoc.associate(ws["v"], ws["n"], ws["valid"], pb.frame, pb.cam,
                                    pb.corr_dist, pb.corr_normal)
     if corr_map is not None:
@@ -125,6 +129,31 @@ def linearize(pb: Problem, R: np.ndarray, t: np.ndarray, corr_map: Optional[np.n
     corr_map = np.full(I.shape, -1, dtype=np.int64)
     corr_map[uy[ci], ux[ci]] = ci
     return dict(ws=ws, I=I, corr=m, corr_idx=ci, ux=ux, uy=uy, corr_map=corr_map,
+                r_data=r_data, J_data=J_data, r_arap=r_arap, Jj=Jj, Jm=Jm,
+                e_data=float(np.sum(r_data ** 2)), e_reg=float(np.sum(r_arap ** 2)))
+
+
+def _linearize_pairs(pb: Problem, R: np.ndarray, t: np.ndarray, ws: Dict, corr_map: Optional[np.ndarray]):
+    """Splat rendering: one data row per pair (surfel, pixel); a surfel can
+    hold several. corr_map, when given, supplies the pairs (pixel -> surfel)."""
+    I, k, ux, uy = assoc.associate_splats(ws["v"], ws["n"], pb.splat_radius, ws["valid"], pb.frame, pb.cam,
+                                          pb.corr_dist, pb.corr_normal)
+    if corr_map is not None:
+        cm = np.asarray(corr_map)
+        uy, ux = np.nonzero(cm >= 0)
+        k = cm[uy, ux]
+    Vd = pb.V64[uy, ux]
+    Nd = pb.N64[uy, ux]
+    r_data = data_residuals(ws["v"][k], Vd, Nd)
+    J_data = data_jacobian(ws["b"][k], pb.surfel_pos[k].astype(np.float64), Nd,
+                           pb.w[k], ws["s"][k], ws["r"], ws["d"], ws["c"], pb.idx[k])
+    r_arap = arap_residuals(pb.node_pos, R, t, pb.nbr)
+    Jj, Jm = arap_jacobians(pb.node_pos, R, pb.nbr)
+    cmap = np.full(I.shape, -1, dtype=np.int64)
+    cmap[uy, ux] = k
+    corr = np.zeros(pb.surfel_pos.shape[0], dtype=bool)
+    corr[k] = True
+    return dict(ws=ws, I=I, corr=corr, corr_idx=k, pair_ux=ux, pair_uy=uy, corr_map=cmap,
                 r_data=r_data, J_data=J_data, r_arap=r_arap, Jj=Jj, Jm=Jm,
                 e_data=float(np.sum(r_data ** 2)), e_reg=float(np.sum(r_arap ** 2)))
 
@@ -266,9 +295,10 @@ def gn_solve(pb: Problem, se3_init: np.ndarray, gn_iters: int, pcg_iters: Option
 
 
 def oracle_solve(cam, surfel_pos, surfel_nrm, node_pos, depth, params,
-                 se3_init=None, linear: str = "pcg", visible=None, **kw):
+                 se3_init=None, linear: str = "pcg", visible=None, splat_radius=None, **kw):
     """One frame solve from a scene's inputs (skinning and graph included)."""
-    pb = make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params, visible=visible)
+    pb = make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params, visible=visible,
+                      splat_radius=splat_radius)
     if se3_init is None:
         se3_init = identity_se3(node_pos.shape[0])
     kw.setdefault("rigid_iters", getattr(params, "rigid_iters", 0))
