@@ -437,6 +437,24 @@ def main():
                                      "removed": gstats["n_removed"]}}
     print(f"[bench] fusion: {fusion}", file=sys.stderr, flush=True)
 
+    # the same frame with the surfels rendered as opaque disc splats of their
+    # depth-surfel radii (pairs per pixel; a surfel may hold several)
+    nzc = np.maximum(np.abs(scene.surfel_nrm[:, 2]), np.cos(np.deg2rad(75.0)))
+    rad = (np.sqrt(2.0) * scene.surfel_pos[:, 2] / (scene.cam.fx * nzc)).astype(np.float32)
+    sst = make_stream(splat=1)
+    sst.set_surfel_attributes(rad)
+    sres = sst.solve_frame(depth)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    nsp = max(5, args.steps // 10)
+    for _ in range(nsp):
+        sst.solve_frame(depth, with_stats=False)
+    torch.cuda.synchronize()
+    splat = {"value": round(nsp / (time.perf_counter() - a), 2), "unit": "frames/s",
+             "pairs_last_iteration": sres["n_corr"][-1], "point_rule_correspondences": stats["n_corr"][-1]}
+    sst.close()
+    print(f"[bench] splats: {splat}", file=sys.stderr, flush=True)
+
     batched = None
     if args.batch > 0:
         B = min(args.batch, 64)
@@ -535,6 +553,7 @@ def main():
         "kernel_gbs": rates,
         "n_corr": stats["n_corr"][-1],
         "fusion": fusion,
+        "splat": splat,
     }
     if batched is not None:
         out["batched"] = batched

@@ -79,6 +79,18 @@ typedef struct sw_config {
     int32_t t_low_confid;      /* frames a surfel may stay below stable_conf after its
                                   initialisation before the geometry update drops it, 30
                                   (Table 1) */
+    int32_t splat;             /* solver index map (Sec. 7): 0 = unsized points (default);
+                                  1 = opaque disc splats of the surfels' radii: a surfel whose
+                                  centre projects into the image is tried on the pixels within
+                                  min(4, ceil(fx r / z)) of its centre pixel, pixel u is covered
+                                  when its centre ray meets the disc (n.d != 0, t = n.v / n.d
+                                  > 0, |t d - v|^2 <= r^2) at depth t, nearest depth wins,
+                                  ties to the lower index; radius 0 renders a point. Every
+                                  pixel with a normal then pairs with its winner under the
+                                  correspondence gates, so a surfel may hold several pairs
+                                  (each a data row; n_corr counts pairs). The rigid
+                                  pre-alignment keeps points. A batch with splat streams is
+                                  not captured as a graph (the pass count is read back) */
 } sw_config;
 
 /* Statistics of one depth-map fusion (sw_fuse_frame). */

@@ -85,15 +85,67 @@ __device__ __forceinline__ unsigned long long zkey(float z, int orig) {
     return ((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)(unsigned)orig;
 }
 
+// Splats (Sec. 7: the live surfels rendered as opaque discs). A surfel whose
+// centre projects to pixel (ux, uy) is tried on the box ux +- h, uy +- h,
+// h = min(4, ceil(fx r / z)); the ray of pixel u is d = ((u_x - cx)/fx,
+// (u_y - cy)/fy, 1) and covers it when n . d != 0, t = (n . v)/(n . d) > 0 and
+// |t d - v|^2 <= r^2, at depth t. A surfel of radius 0 (or less) is an
+// unsized point at its centre pixel.
+constexpr int kSplatMaxPx = 4;
+
+__device__ __forceinline__ int splat_half(const Cam& c, float r, float z) {
+    return (int)fminf((float)kSplatMaxPx, ceilf((c.fx * r) / z));
+}
+
+__device__ __forceinline__ void splat_render(const FrameDesc& d, float3 v, float3 n, float r, int ux, int uy,
+                                             int org) {
+    if (!(r > 0.f)) {
+        atomicMin(&d.zbuf[uy * d.cam.W + ux], zkey(v.z, org));
+        return;
+    }
+    const int h = splat_half(d.cam, r, v.z);
+    const float nv = (n.x * v.x + n.y * v.y) + n.z * v.z;
+    const float r2 = r * r;
+    for (int oy = -h; oy <= h; ++oy) {
+        const int y = uy + oy;
+        if (y < 0 || y >= d.cam.H) continue;
+        const float dy = ((float)y - d.cam.cy) / d.cam.fy;
+        for (int ox = -h; ox <= h; ++ox) {
+            const int x = ux + ox;
+            if (x < 0 || x >= d.cam.W) continue;
+            const float dx = ((float)x - d.cam.cx) / d.cam.fx;
+            const float nd = (n.x * dx + n.y * dy) + n.z;
+            if (nd == 0.f) continue;
+            const float t = nv / nd;
+            if (!(t > 0.f)) continue;
+            const float ex = t * dx - v.x, ey = t * dy - v.y, ez = t - v.z;
+            const float e2 = (ex * ex + ey * ey) + ez * ez;
+            if (e2 <= r2) atomicMin(&d.zbuf[y * d.cam.W + x], zkey(t, org));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Warp + index map
 // ---------------------------------------------------------------------------
+// SPLAT: a launch with a splat stream (the point rule's launches carry none of
+// the splat code)
+template <bool SPLAT>
 __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const int i = at.tile * kWarpBlock + threadIdx.x;
+    if (SPLAT && d.splat && i == 0) *d.max_pairs = 0;   // the correspondence pass of this iteration counts anew
     if (i >= d.ns || !visible(d, i)) return;     // (the correspondence test needs the surfel in the map)
     float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
+    if (SPLAT && d.splat) {
+        const float3 n = make_float3(d.nx[i], d.ny[i], d.nz[i]);
+        const Warp ws = warp_surfel(d.idx[i], d.w[i], v, n, d.dq);
+        int sx, sy;
+        if (!ws.ok || !project(d.cam, ws.v, sx, sy)) return;
+        splat_render(d, ws.v, ws.n, d.radius[i], sx, sy, d.orig[i]);
+        return;
+    }
     Warp wp = warp_surfel(d.idx[i], d.w[i], v, make_float3(0.f, 0.f, 0.f), d.dq);
     if (!wp.ok) return;
     int ux, uy;
@@ -223,6 +275,7 @@ __device__ __forceinline__ float keep_jac(float v, int dtype) {
     return v;
 }
 
+template <bool SPLAT>
 __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
@@ -230,11 +283,19 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
     const FrameDesc& d = *b.d[at.s];
+    // splat pass: pass p pairs every surfel with its p-th pixel (row-major in
+    // its box); passes after the first add into the first's outputs and skip
+    // packs whose surfels have no p-th pair
+    const int pass = SPLAT ? b.pcg_it : 0;
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
     const int p0 = d.pack_start[at.tile], p1 = d.pack_start[at.tile + 1];
     const int i = p0 + (int)threadIdx.x;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const bool live = i < p1;
+    if (pass > 0) {
+        if (!SPLAT || !d.splat) return;                        // uniform: a workgroup is one stream's
+        if (!__syncthreads_or(live && d.npairs[i] > pass)) return;
+    }
     float r = 0.f;
     float Jw[4][3], Jt[4][3];
 #pragma unroll
@@ -254,9 +315,44 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     int ux, uy;
     const bool in = project(d.cam, wp.v, ux, uy);
     bool ok = live & wp.ok & in;
+    if (SPLAT && d.splat) {                                    // uniform
+        // the pixels this surfel won (index part of the key) that have a
+        // normal and pass the gates, row-major in its box; take the pass-th
+        int cnt = 0, fx = ux, fy = uy;
+        if (ok) {
+            const float rr = d.radius[ic];
+            const int h = rr > 0.f ? splat_half(d.cam, rr, wp.v.z) : 0;
+            for (int oy = -h; oy <= h; ++oy) {
+                const int y = uy + oy;
+                if (y < 0 || y >= d.cam.H) continue;
+                for (int ox = -h; ox <= h; ++ox) {
+                    const int x = ux + ox;
+                    if (x < 0 || x >= d.cam.W) continue;
+                    const int u = y * d.cam.W + x;
+                    if ((unsigned)(d.zbuf[u] & 0xffffffffull) != (unsigned)org) continue;
+                    const float4 q = d.nmap[u];
+                    if (!(q.w > 0.f)) continue;
+                    const float3 dq3 = sub3(wp.v, backproject(d.cam, x, y, q.w));
+                    const float q2 = (dq3.x * dq3.x + dq3.y * dq3.y) + dq3.z * dq3.z;
+                    if (!(q2 < d.dist2) || !(dot3(wp.n, make_float3(q.x, q.y, q.z)) > d.cosn)) continue;
+                    if (cnt == pass) { fx = x; fy = y; }
+                    ++cnt;
+                }
+            }
+        }
+        if (pass == 0) {
+            if (live) d.npairs[i] = cnt;
+            int m = cnt;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+            if (lane == 0 && m > 0) atomicMax(d.max_pairs, m);
+        }
+        ok = ok & (cnt > pass);
+        ux = fx;
+        uy = fy;
+    }
     const int pix = ok ? uy * d.cam.W + ux : 0;
-    const unsigned long long zb = d.zbuf[pix];
-    ok = ok & (zb == zkey(wp.v.z, org));
+    if (!(SPLAT && d.splat)) ok = ok & (d.zbuf[pix] == zkey(wp.v.z, org));   // (loaded beside the normal map)
     const float4 nm = d.nmap[pix];
     ok = ok & (nm.w > 0.f);
     const float3 V = backproject(d.cam, ux, uy, nm.w);
@@ -320,10 +416,15 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     if (threadIdx.x == 0) {
         int c = 0;
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
-        d.part_e[at.tile] = e;
-        d.part_n[at.tile] = c;
+        if (pass > 0) {
+            d.part_e[at.tile] += e;
+            d.part_n[at.tile] += c;
+        } else {
+            d.part_e[at.tile] = e;
+            d.part_n[at.tile] = c;
+        }
     }
-    if (capture) {
+    if (capture && pass == 0) {
         // the wave's rows as whole 128-byte lines, two rows per store
         const int base = wave * kWave;
         float* dst = d.J + (size_t)(p0 + base) * 32;
@@ -377,7 +478,14 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
-        for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
+        if (pass > 0) {
+            for (int q = lane; q < size / 4; q += kWave) {
+                const float4 a = out[q], c4 = stage4[wave][q];
+                out[q] = make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w);
+            }
+        } else {
+            for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -711,8 +819,14 @@ void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStre
     if (grid <= 0) return;
     switch (stage) {
         case kStDepth: hipLaunchKernelGGL(k_depth_prep, dim3(grid), dim3(256), 0, st, b, *depth); break;
-        case kStWarp: hipLaunchKernelGGL(k_warp_zbuf, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
-        case kStCorr: hipLaunchKernelGGL(k_corr_gram, dim3(grid), dim3(kCorrBlock), 0, st, b); break;
+        case kStWarp:
+            if (b.splat) hipLaunchKernelGGL(k_warp_zbuf<true>, dim3(grid), dim3(kWarpBlock), 0, st, b);
+            else hipLaunchKernelGGL(k_warp_zbuf<false>, dim3(grid), dim3(kWarpBlock), 0, st, b);
+            break;
+        case kStCorr:
+            if (b.splat) hipLaunchKernelGGL(k_corr_gram<true>, dim3(grid), dim3(kCorrBlock), 0, st, b);
+            else hipLaunchKernelGGL(k_corr_gram<false>, dim3(grid), dim3(kCorrBlock), 0, st, b);
+            break;
         case kStRigidWarp: hipLaunchKernelGGL(k_rigid_warp, dim3(grid), dim3(kWarpBlock), 0, st, b); break;
         case kStRigidSys: hipLaunchKernelGGL(k_rigid_sys, dim3(grid), dim3(256), 0, st, b); break;
         case kStRigidSolve: hipLaunchKernelGGL(k_rigid_solve, dim3(grid), dim3(kNodeBlock), 0, st, b); break;

@@ -169,6 +169,8 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.rig64, 12 * 8);
     take(h.rig_part, 8 * (size_t)kRigidSums * (size_t)cdiv(h.ns, kRigidSurfels));
     take(h.rig_stats, sizeof(RigidStats) * kMaxIters);
+    take(h.npairs, 4 * (size_t)std::max(1, h.splat ? h.pitch : 1));
+    take(h.max_pairs, 16);
     return off;
 }
 
@@ -218,6 +220,7 @@ sw_status check_config(const sw_config* c, std::string& why) {
     if (!(finite(c->warp_eps) && c->warp_eps > 0 && c->warp_eps < 1)) { why = "warp_eps must be in (0, 1)"; return SW_EINVAL; }
     if (!(finite(c->append_nn) && c->append_nn >= 0)) { why = "append_nn must be >= 0"; return SW_EINVAL; }
     if (c->t_low_confid < 0) { why = "t_low_confid must be >= 0"; return SW_EINVAL; }
+    if (c->splat != 0 && c->splat != 1) { why = "splat must be 0 or 1"; return SW_EINVAL; }
     return SW_OK;
 }
 
@@ -338,6 +341,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.lambda = s->cfg.lambda_reg;
     h.mu = s->cfg.damping;
     h.vis_mode = s->cfg.visibility;
+    h.splat = s->cfg.splat;
     h.stable_conf = s->cfg.stable_conf;
     h.recent = s->cfg.recent_frames;
     h.t_now = s->t_now;
@@ -551,6 +555,7 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
     }
     b.off[b.n] = off;
     if (off == 0) return;
+    for (int i = 0; i < b.n; ++i) b.splat |= (its[i] >= 0 && ss[i]->h.splat) ? 1 : 0;
     if (timing) {
         SWGN_HIP(hipEventRecord(ex.event(ev_stage.size()), ex.st));
         ev_stage.push_back(stage);
@@ -628,6 +633,12 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
         launch_fill_i32(s->h.dbg_corr, s->h.npx, -1, st);
     }
     run_stage(ex, kStCorr, ss, its, 0, nullptr, timing, ev);
+    // splats: one more correspondence pass for every pair beyond a surfel's
+    // first (the most pairs of any surfel is read back after the first pass)
+    int passes = 1;
+    for (int i = 0; i < n; ++i)
+        if (its[i] >= 0 && ss[i]->h.splat) passes = std::max(passes, read_scalar(ss[i]->h.max_pairs, st));
+    for (int p = 1; p < passes; ++p) run_stage(ex, kStCorr, ss, its, p, nullptr, timing, ev);
     run_stage(ex, kStAsmSeg, ss, its, 0, nullptr, timing, ev);
     run_stage(ex, kStAsmFold, ss, its, 0, nullptr, timing, ev);
     for (int i = 0; i < n; ++i) {
@@ -749,9 +760,11 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
     std::vector<int> ev;
     int gmax = 0;
     bool any_capture = false;
+    bool any_splat = false;
     for (int i = 0; i < n; ++i) {
         gmax = std::max(gmax, ss[i]->cfg.gn_iters);
         any_capture |= ss[i]->cfg.debug_iter >= 0 && ss[i]->cfg.debug_iter < ss[i]->cfg.gn_iters;
+        any_splat |= ss[i]->cfg.splat != 0;     // its pass count is read back each iteration
     }
     enqueue_depth(ex, ss, depths, on_device, timing, ev);
     enqueue_rigid(ex, ss, timing, ev);
@@ -764,7 +777,7 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
         }
         enqueue_collect(ex, ss);
     };
-    if (ex.graphs && !timing && !any_capture) {
+    if (ex.graphs && !timing && !any_capture && !any_splat) {
         // the iterations and the statistics copy of this exact batch as one
         // graph, captured on first use and replayed while the batch and its
         // streams' buffers are unchanged
@@ -843,6 +856,7 @@ void sw_config_default(sw_config* c) {
     c->warp_eps = 0.2f;
     c->append_nn = 0.3f;
     c->t_low_confid = 30;
+    c->splat = 0;
 }
 
 const char* sw_status_string(sw_status st) {

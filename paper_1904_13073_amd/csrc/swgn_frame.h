@@ -83,6 +83,7 @@ struct FrameDesc {
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
     int rigid_iters;              // rigid alignment steps before the non-rigid ones
     int vis_mode;                 // 1: only stable or recently observed surfels are rendered
+    int splat;                    // 1: surfels rendered as opaque discs of their radius, pairs per pixel
     float stable_conf;            // delta_stable
     int recent, t_now;            // delta_recent, current frame time
     Cam cam;
@@ -93,6 +94,8 @@ struct FrameDesc {
     const float4* w;
     const int* orig;
     float *radius, *conf;         // surfel attributes (radius, confidence, last observed frame)
+    int* npairs;                  // splat: pixels paired with each surfel (sorted order)
+    int* max_pairs;               // splat: the most pairs of any surfel this iteration
     int* t_obs;
     const int* inv;               // caller index -> sorted position
     // resident: nodes
@@ -209,6 +212,7 @@ struct Batch {
                                   // it - 1 in a fused step)
     int order;                    // kOrderXcd: tiles in XCD-contiguous order
     int wide;                     // the stage's wider geometry (kVarWide)
+    int splat;                    // some stream renders splats (the kernels with splat code run)
     int off[kMaxBatch + 1];       // stream s owns tiles [off[s], off[s+1])
     const FrameDesc* d[kMaxBatch];
     int8_t it[kMaxBatch];         // Gauss-Newton iteration of each stream

@@ -29,7 +29,7 @@ class SwConfig(C.Structure):
                 ("stage_timing", C.c_int32), ("rigid_iters", C.c_int32), ("visibility", C.c_int32),
                 ("stable_conf", C.c_float), ("recent_frames", C.c_int32), ("fusion_dist", C.c_float),
                 ("fusion_normal", C.c_float), ("warp_eps", C.c_float), ("append_nn", C.c_float),
-                ("t_low_confid", C.c_int32)]
+                ("t_low_confid", C.c_int32), ("splat", C.c_int32)]
 
 
 class SwFusionStats(C.Structure):

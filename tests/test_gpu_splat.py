@@ -1,0 +1,106 @@
+"""Splat visibility (Sec. 7, the live surfels as opaque discs) on the GPU,
+through the C ABI, against the oracle.
+
+The splat index map and the pixel pairs are integer outputs with exact FP32
+forms: bit-exact at the identity state. A whole frame is compared with the
+oracle run on the GPU's own per-iteration pairs, within the frame tolerances
+of the point rule; batches and radius 0 are checked bit for bit."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_lib, se3_errors
+from oracle import replica32 as R32
+from oracle import solve as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swgn():
+    return gpu_lib()
+
+
+def _radii(s):
+    """Depth-surfel radii at the reference: sqrt(2) z / (fx max(|n_z|, cos 75 deg))."""
+    nz = np.maximum(np.abs(s.surfel_nrm[:, 2]), np.cos(np.deg2rad(75.0)))
+    return (np.sqrt(2.0) * s.surfel_pos[:, 2] / (s.cam.fx * nz)).astype(np.float32)
+
+
+def _stream(swgn, s, rad, se3=None, **cfg):
+    st = swgn.Stream(swgn.config_for(s, splat=1, **cfg))
+    st.set_reference_surfels(s.surfel_pos, s.surfel_nrm)
+    st.set_node_graph(s.node_pos, None if se3 is None else np.asarray(se3, np.float32))
+    st.set_surfel_attributes(rad)
+    return st
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_splat_index_map_and_pairs_bit_exact(swgn, scene_cache, name):
+    s = scene_cache(name)
+    rad = _radii(s)
+    st = _stream(swgn, s, rad, debug_iter=0, gn_iters=1)
+    res = st.solve_frame(s.depth)
+    I, Cm, live, _ = st.last_maps()
+    st.close()
+    assert np.array_equal(live, s.surfel_pos)
+    v, n = s.surfel_pos.astype(np.float32), s.surfel_nrm.astype(np.float32)
+    I_ref = R32.splat_index_map(v, n, rad, s.cam)
+    assert np.array_equal(I, I_ref)
+    N32, ok = R32.normal_map(s.depth, s.cam, s.params.edge_gate)
+    k, ux, uy = R32.splat_pairs(v, n, I_ref, s.depth, N32, ok, s.cam, s.params.corr_dist, s.params.corr_normal)
+    C_ref = np.full(I.shape, -1, np.int64)
+    C_ref[uy, ux] = k
+    assert np.array_equal(Cm, C_ref)
+    assert res["n_corr"][0] == k.size
+    counts = np.bincount(k, minlength=v.shape[0])
+    assert counts.max() >= 2                         # the extra passes are exercised
+    print(f"{name}: {k.size} pairs, surfels with 2+ pairs {(counts >= 2).sum()}, most {counts.max()}")
+
+
+def test_splat_frame_matches_oracle_on_its_pairs(swgn, scene_cache):
+    s = scene_cache("c1")
+    rad = _radii(s)
+    st = _stream(swgn, s, rad)
+    stats = st.solve_frame(s.depth)
+    got = st.node_se3()
+    st.close()
+    maps = []
+    for k in range(s.params.gn_iters):
+        st = _stream(swgn, s, rad, debug_iter=k)
+        st.solve_frame(s.depth)
+        maps.append(st.last_maps()[1])
+        assert np.array_equal(st.node_se3(), got)
+        st.close()
+    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
+                              splat_radius=rad, corr_maps=maps)
+    ang, dpos = se3_errors(got, want, s.node_pos)
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
+    assert stats["n_corr"] == tr["n_corr"]
+    e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
+    e_ref = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
+    assert np.max(np.abs(e_gpu - e_ref) / e_ref) < 1e-4
+
+
+def test_splat_batch_equals_solo_and_radius_zero_is_the_point_rule(swgn, scene_cache):
+    a, b = scene_cache("tiny"), scene_cache("c1")
+    ra, rb = _radii(a), _radii(b)
+    solo = []
+    for s, r in ((a, ra), (b, rb)):
+        st = _stream(swgn, s, r)
+        st.solve_frame(s.depth)
+        solo.append(st.node_se3())
+        st.close()
+    sts = [_stream(swgn, a, ra), _stream(swgn, b, rb), swgn.Stream(swgn.config_for(a))]
+    sts[2].set_reference_surfels(a.surfel_pos, a.surfel_nrm)
+    sts[2].set_node_graph(a.node_pos)
+    bx = swgn.Batch(graph=True)
+    bx.solve(sts, [a.depth, b.depth, a.depth], with_stats=False)
+    assert np.array_equal(sts[0].node_se3(), solo[0]) and np.array_equal(sts[1].node_se3(), solo[1])
+    point = sts[2].node_se3()
+    bx.close()
+    for t in sts:
+        t.close()
+    zero = _stream(swgn, a, np.zeros_like(ra))
+    zero.solve_frame(a.depth)
+    assert np.array_equal(zero.node_se3(), point)
+    zero.close()
