@@ -89,8 +89,10 @@ typedef struct sw_config {
                                   pixel with a normal then pairs with its winner under the
                                   correspondence gates, so a surfel may hold several pairs
                                   (each a data row; n_corr counts pairs). The rigid
-                                  pre-alignment keeps points. A batch with splat streams is
-                                  not captured as a graph (the pass count is read back) */
+                                  pre-alignment keeps points. A captured iteration's Jacobian
+                                  row of a surfel with several pairs is the first row of their
+                                  4 x 4 factor (the sum of the pairs' Gram matrices is that of
+                                  the factor's rows) */
 } sw_config;
 
 /* Statistics of one depth-map fusion (sw_fuse_frame). */

@@ -120,7 +120,12 @@ __device__ __forceinline__ void splat_render(const FrameDesc& d, float3 v, float
             if (!(t > 0.f)) continue;
             const float ex = t * dx - v.x, ey = t * dy - v.y, ez = t - v.z;
             const float e2 = (ex * ex + ey * ey) + ez * ez;
-            if (e2 <= r2) atomicMin(&d.zbuf[y * d.cam.W + x], zkey(t, org));
+            if (!(e2 <= r2)) continue;
+            // keys only decrease, so a key not below the one read leaves the
+            // map unchanged and needs no atomic
+            const unsigned long long key = zkey(t, org);
+            unsigned long long* z = &d.zbuf[y * d.cam.W + x];
+            if (key < __hip_atomic_load(z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(z, key);
         }
     }
 }
@@ -135,7 +140,6 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
     const int i = at.tile * kWarpBlock + threadIdx.x;
-    if (SPLAT && d.splat && i == 0) *d.max_pairs = 0;   // the correspondence pass of this iteration counts anew
     if (i >= d.ns || !visible(d, i)) return;     // (the correspondence test needs the surfel in the map)
     float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);
     if (SPLAT && d.splat) {
@@ -275,27 +279,192 @@ __device__ __forceinline__ float keep_jac(float v, int dtype) {
     return v;
 }
 
+// Splat pairs of one surfel: every pair row is [N_p^T D | r_p] = a_p^T E with
+// a_p = (N_p, r_p) and E = diag(D, 1), D the 3 x 30 Jacobian of the warped
+// position, so the pairs' Gram sum is E^T (sum_p a_p a_p^T) E = E^T R^T R E for
+// the 4 x 4 triangular factor R of the stacked a_p: at most four rows
+// [J(R_j) | R_j3] (J is linear in the normal) carry all of a surfel's pairs.
+// R is built by inserting the a_p one at a time: the first unused row takes
+// what is left of a_p as it is (so a single pair's row is its own exactly);
+// a used row is rotated with a_p in the plane of their j-th entries (Givens),
+// which keeps R^T R + a a^T.
+__device__ __forceinline__ void factor_insert(float (&R)[4][4], int used, float w0, float w1, float w2,
+                                              float w3) {
+    float w[4] = {w0, w1, w2, w3};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (used <= j) {
+#pragma unroll
+            for (int k = j; k < 4; ++k) R[j][k] = w[k];
+            return;
+        }
+        if (w[j] == 0.f) continue;
+        const float rad = sqrtf(R[j][j] * R[j][j] + w[j] * w[j]);
+        if (!(rad > 0.f)) continue;
+        const float c = R[j][j] / rad, s = w[j] / rad;
+#pragma unroll
+        for (int k = j; k < 4; ++k) {
+            const float a = R[j][k], e = w[k];
+            R[j][k] = c * a + s * e;
+            w[k] = c * e - s * a;
+        }
+        w[j] = 0.f;
+    }
+}
+
+// The thread's row in LDS: node block k at its node's position in the segment
+// (threads past the pack capacity are never live and keep no row).
+__device__ __forceinline__ void put_row(const FrameDesc& d, float* rows, bool live, int i, float (&Jw)[4][3],
+                                        float (&Jt)[4][3], float r) {
+    if (threadIdx.x >= kCorrPack) return;
+    float* row = &rows[threadIdx.x * kRowPad];
+    const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
+    const int jd = d.jac_dtype;          // uniform: one branch for the whole row
+    if (jd != 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Jw[k][c] = keep_jac(Jw[k][c], jd);
+                Jt[k][c] = keep_jac(Jt[k][c], jd);
+            }
+    }
+    int used = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pos = (p4 >> (3 * k)) & 7;
+        used |= 1 << pos;
+        float* o = row + pos * 6;
+        o[0] = Jw[k][0]; o[1] = Jw[k][1]; o[2] = Jw[k][2];
+        o[3] = Jt[k][0]; o[4] = Jt[k][1]; o[5] = Jt[k][2];
+    }
+    // the segment's fifth node position, if the surfel does not touch it
+#pragma unroll
+    for (int pos = 0; pos < 5; ++pos)
+        if (!(used & (1 << pos))) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) row[pos * 6 + c] = 0.f;
+        }
+    row[30] = r;
+}
+
+// The tile statistics: sum of squared residuals (FP64) and pair count. Also
+// zeroes the slack after the last row, read as column 31 (whose products are
+// dropped). A block-wide barrier.
+__device__ __forceinline__ void tile_sums(const FrameDesc& d, float* rows, double* sh, int* shi, int tile,
+                                          double e_own, int npair) {
+    if (threadIdx.x == kCorrBlock - 1) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) rows[kCorrPack * kRowPad + c] = 0.f;
+    }
+    const double e = block_sum(e_own, sh);
+    const int cnt = wave_sumi(npair);
+    if ((threadIdx.x % kWave) == 0) shi[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
+        d.part_e[tile] = e;
+        d.part_n[tile] = c;
+    }
+}
+
+// A captured iteration's rows, as whole 128-byte lines, two rows per store.
+__device__ __forceinline__ void capture_rows(const FrameDesc& d, const float* rows, int p0, int p1) {
+    {
+        const int lane = threadIdx.x % kWave, base = (threadIdx.x / kWave) * kWave;
+        float* dst = d.J + (size_t)(p0 + base) * 32;
+        const int nrow = min(kWave, p1 - p0 - base);
+#pragma nounroll
+        for (int q = 0; q < kWave / 2; ++q) {
+            const int rr = 2 * q + (lane >> 5), c = lane & 31;
+            if (rr < nrow) dst[rr * 32 + c] = c < 31 ? rows[(base + rr) * kRowPad + c] : 0.f;
+        }
+    }
+}
+
+// Segment Gram matrices of the pack's rows, one wave per segment. Accumulator
+// element t of lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 +
+// t % 4. The output slot of each element: the rank of its node pair among the
+// segment's pairs x 36 + position in the 6x6 sub-block; J^T r and r^T r after
+// the sub-blocks. The whole output is staged in LDS and stored as whole lines;
+// with `more` (later splat rounds) segments without a marked row are skipped
+// and the sums are added to the stored ones (the same lanes stored those words).
+__device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* rows, float4* stage, int tile, int p0,
+                                              const unsigned long long* more) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int comp = lane & 31, half = lane >> 5;
+    const int g0 = d.pack_seg[tile], g1 = d.pack_seg[tile + 1];
+    float* sg = reinterpret_cast<float*>(stage);
+    const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
+    for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
+        const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
+        if (more != nullptr) {
+            bool any = false;
+            for (int m = s0 + lane; m < s1; m += kWave) any |= ((more[m / kWave] >> (m % kWave)) & 1ull) != 0;
+            if (__ballot(any) == 0) continue;                  // uniform over the wave
+        }
+        f32x16 acc;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = 0.f;
+        for (int m0 = s0; m0 < s1; m0 += 16) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int sr = m0 + 2 * q + half;   // surfel of this half-wave
+                v[q] = sr < s1 ? rows[sr * kRowPad + comp] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
+        }
+        const uint32_t mask = d.seg_mask[seg];
+        const int npr = __builtin_popcount(mask);
+        const int size = 36 * npr + 32;
+        const uint4 q0 = codes[0], q1 = codes[1];
+        const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+            const uint32_t bit = code & 15u, off = code >> 4;
+            const bool tail = bit == 15u;
+            const bool keep = code != 0xffffu && (tail || ((mask >> bit) & 1u));
+            const int sl = tail ? 36 * npr + (int)off : 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (int)off;
+            if (keep) sg[sl] = acc[t];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
+        if (more != nullptr) {
+            for (int q = lane; q < size / 4; q += kWave) {
+                const float4 a = out[q], c4 = stage[q];
+                out[q] = make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w);
+            }
+        } else {
+            for (int q = lane; q < size / 4; q += kWave) out[q] = stage[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// SPLAT: a launch with a splat stream (the point rule's launches carry none of
+// the splat code)
 template <bool SPLAT>
 __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
+    __shared__ unsigned long long more[kCorrBlock / kWave];   // splat rounds: the surfels with a row
     __shared__ float rows[kCorrPack * kRowPad + 8];
     __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
     const FrameDesc& d = *b.d[at.s];
-    // splat pass: pass p pairs every surfel with its p-th pixel (row-major in
-    // its box); passes after the first add into the first's outputs and skip
-    // packs whose surfels have no p-th pair
-    const int pass = SPLAT ? b.pcg_it : 0;
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
     const int p0 = d.pack_start[at.tile], p1 = d.pack_start[at.tile + 1];
     const int i = p0 + (int)threadIdx.x;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const bool live = i < p1;
-    if (pass > 0) {
-        if (!SPLAT || !d.splat) return;                        // uniform: a workgroup is one stream's
-        if (!__syncthreads_or(live && d.npairs[i] > pass)) return;
-    }
     float r = 0.f;
     float Jw[4][3], Jt[4][3];
 #pragma unroll
@@ -315,10 +484,23 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     int ux, uy;
     const bool in = project(d.cam, wp.v, ux, uy);
     bool ok = live & wp.ok & in;
-    if (SPLAT && d.splat) {                                    // uniform
+    if (SPLAT && d.splat) {                                    // uniform: a workgroup is one stream's
         // the pixels this surfel won (index part of the key) that have a
-        // normal and pass the gates, row-major in its box; take the pass-th
-        int cnt = 0, fx = ux, fy = uy;
+        // normal and pass the gates, in row-major order of its box, reduced
+        // to the factor R of their rows (a_p = (N_p, r_p))
+        if (live && capture) {
+            const float nanv = __int_as_float(0x7fc00000);
+            d.dbg_live[3 * org + 0] = wp.ok ? wp.v.x : nanv;
+            d.dbg_live[3 * org + 1] = wp.ok ? wp.v.y : nanv;
+            d.dbg_live[3 * org + 2] = wp.ok ? wp.v.z : nanv;
+        }
+        int npair = 0;
+        double e_own = 0.0;
+        float R[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) R[j][k] = 0.f;
         if (ok) {
             const float rr = d.radius[ic];
             const int h = rr > 0.f ? splat_half(d.cam, rr, wp.v.z) : 0;
@@ -334,25 +516,55 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
                     if (!(q.w > 0.f)) continue;
                     const float3 dq3 = sub3(wp.v, backproject(d.cam, x, y, q.w));
                     const float q2 = (dq3.x * dq3.x + dq3.y * dq3.y) + dq3.z * dq3.z;
-                    if (!(q2 < d.dist2) || !(dot3(wp.n, make_float3(q.x, q.y, q.z)) > d.cosn)) continue;
-                    if (cnt == pass) { fx = x; fy = y; }
-                    ++cnt;
+                    const float3 Nq = make_float3(q.x, q.y, q.z);
+                    if (!(q2 < d.dist2) || !(dot3(wp.n, Nq) > d.cosn)) continue;
+                    const float rp = dot3(Nq, dq3);
+                    factor_insert(R, npair, Nq.x, Nq.y, Nq.z, rp);
+                    e_own += (double)rp * (double)rp;
+                    ++npair;
+                    if (capture) d.dbg_corr[u] = org;
                 }
             }
         }
-        if (pass == 0) {
-            if (live) d.npairs[i] = cnt;
-            int m = cnt;
+        tile_sums(d, rows, sh, shi, at.tile, e_own, npair);
+        // round j: row j of the factor of every surfel with more than j pairs;
+        // later rounds add their Gram sums to the first's outputs and stop at
+        // the first round no surfel of the pack has. The warp is formed again
+        // per round, so that only the factor stays live across rounds.
+#pragma nounroll
+        for (int j = 0; j < 4; ++j) {
+            const bool has = npair > j;
+            if (j > 0 && !__syncthreads_or(has)) break;        // uniform; the rows are free again
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-            if (lane == 0 && m > 0) atomicMax(d.max_pairs, m);
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { Jw[k][c] = 0.f; Jt[k][c] = 0.f; }
+            r = 0.f;
+            if (has) {
+                const float nx = j == 0 ? R[0][0] : 0.f;
+                const float ny = j == 0 ? R[0][1] : (j == 1 ? R[1][1] : 0.f);
+                const float nz = j == 0 ? R[0][2] : (j == 1 ? R[1][2] : (j == 2 ? R[2][2] : 0.f));
+                r = j == 0 ? R[0][3] : (j == 1 ? R[1][3] : (j == 2 ? R[2][3] : R[3][3]));
+                int i2 = i;
+                asm volatile("" : "+v"(i2));                     // (kept per round, not hoisted)
+                const int4 id2 = d.idx[i2];
+                const float4 w42 = d.w[i2];
+                const float3 v2 = make_float3(d.px[i2], d.py[i2], d.pz[i2]);
+                const float3 n2 = make_float3(d.nx[i2], d.ny[i2], d.nz[i2]);
+                const Warp w2 = warp_surfel(id2, w42, v2, n2, d.dq);
+                jacobian_rows(d, id2, w42, v2, make_float3(nx, ny, nz), w2, Jw, Jt);
+            }
+            const unsigned long long bal = __ballot(has);
+            if (lane == 0) more[wave] = bal;
+            put_row(d, rows, live, i, Jw, Jt, r);
+            __syncthreads();
+            if (j == 0 && capture) capture_rows(d, rows, p0, p1);
+            segment_grams(d, rows, stage4[wave], at.tile, p0, j > 0 ? more : nullptr);
         }
-        ok = ok & (cnt > pass);
-        ux = fx;
-        uy = fy;
+        return;
     }
     const int pix = ok ? uy * d.cam.W + ux : 0;
-    if (!(SPLAT && d.splat)) ok = ok & (d.zbuf[pix] == zkey(wp.v.z, org));   // (loaded beside the normal map)
+    ok = ok & (d.zbuf[pix] == zkey(wp.v.z, org));   // (loaded beside the normal map)
     const float4 nm = d.nmap[pix];
     ok = ok & (nm.w > 0.f);
     const float3 V = backproject(d.cam, ux, uy, nm.w);
@@ -416,15 +628,10 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     if (threadIdx.x == 0) {
         int c = 0;
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
-        if (pass > 0) {
-            d.part_e[at.tile] += e;
-            d.part_n[at.tile] += c;
-        } else {
-            d.part_e[at.tile] = e;
-            d.part_n[at.tile] = c;
-        }
+        d.part_e[at.tile] = e;
+        d.part_n[at.tile] = c;
     }
-    if (capture && pass == 0) {
+    if (capture) {
         // the wave's rows as whole 128-byte lines, two rows per store
         const int base = wave * kWave;
         float* dst = d.J + (size_t)(p0 + base) * 32;
@@ -478,14 +685,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
-        if (pass > 0) {
-            for (int q = lane; q < size / 4; q += kWave) {
-                const float4 a = out[q], c4 = stage4[wave][q];
-                out[q] = make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w);
-            }
-        } else {
-            for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
-        }
+        for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

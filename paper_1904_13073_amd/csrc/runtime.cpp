@@ -169,8 +169,6 @@ size_t carve_workspace(FrameDesc& h, char* base) {
     take(h.rig64, 12 * 8);
     take(h.rig_part, 8 * (size_t)kRigidSums * (size_t)cdiv(h.ns, kRigidSurfels));
     take(h.rig_stats, sizeof(RigidStats) * kMaxIters);
-    take(h.npairs, 4 * (size_t)std::max(1, h.splat ? h.pitch : 1));
-    take(h.max_pairs, 16);
     return off;
 }
 
@@ -633,12 +631,6 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
         launch_fill_i32(s->h.dbg_corr, s->h.npx, -1, st);
     }
     run_stage(ex, kStCorr, ss, its, 0, nullptr, timing, ev);
-    // splats: one more correspondence pass for every pair beyond a surfel's
-    // first (the most pairs of any surfel is read back after the first pass)
-    int passes = 1;
-    for (int i = 0; i < n; ++i)
-        if (its[i] >= 0 && ss[i]->h.splat) passes = std::max(passes, read_scalar(ss[i]->h.max_pairs, st));
-    for (int p = 1; p < passes; ++p) run_stage(ex, kStCorr, ss, its, p, nullptr, timing, ev);
     run_stage(ex, kStAsmSeg, ss, its, 0, nullptr, timing, ev);
     run_stage(ex, kStAsmFold, ss, its, 0, nullptr, timing, ev);
     for (int i = 0; i < n; ++i) {
@@ -760,11 +752,9 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
     std::vector<int> ev;
     int gmax = 0;
     bool any_capture = false;
-    bool any_splat = false;
     for (int i = 0; i < n; ++i) {
         gmax = std::max(gmax, ss[i]->cfg.gn_iters);
         any_capture |= ss[i]->cfg.debug_iter >= 0 && ss[i]->cfg.debug_iter < ss[i]->cfg.gn_iters;
-        any_splat |= ss[i]->cfg.splat != 0;     // its pass count is read back each iteration
     }
     enqueue_depth(ex, ss, depths, on_device, timing, ev);
     enqueue_rigid(ex, ss, timing, ev);
@@ -777,7 +767,7 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
         }
         enqueue_collect(ex, ss);
     };
-    if (ex.graphs && !timing && !any_capture && !any_splat) {
+    if (ex.graphs && !timing && !any_capture) {
         // the iterations and the statistics copy of this exact batch as one
         // graph, captured on first use and replayed while the batch and its
         // streams' buffers are unchanged

@@ -94,8 +94,6 @@ struct FrameDesc {
     const float4* w;
     const int* orig;
     float *radius, *conf;         // surfel attributes (radius, confidence, last observed frame)
-    int* npairs;                  // splat: pixels paired with each surfel (sorted order)
-    int* max_pairs;               // splat: the most pairs of any surfel this iteration
     int* t_obs;
     const int* inv;               // caller index -> sorted position
     // resident: nodes

@@ -53,7 +53,7 @@ def test_splat_index_map_and_pairs_bit_exact(swgn, scene_cache, name):
     assert np.array_equal(Cm, C_ref)
     assert res["n_corr"][0] == k.size
     counts = np.bincount(k, minlength=v.shape[0])
-    assert counts.max() >= 2                         # the extra passes are exercised
+    assert counts.max() >= {"c1": 3, "c2": 5}[name]   # c2: more pairs than the factor's 4 rows
     print(f"{name}: {k.size} pairs, surfels with 2+ pairs {(counts >= 2).sum()}, most {counts.max()}")
 
 
