@@ -120,12 +120,7 @@ __device__ __forceinline__ void splat_render(const FrameDesc& d, float3 v, float
             if (!(t > 0.f)) continue;
             const float ex = t * dx - v.x, ey = t * dy - v.y, ez = t - v.z;
             const float e2 = (ex * ex + ey * ey) + ez * ez;
-            if (!(e2 <= r2)) continue;
-            // keys only decrease, so a key not below the one read leaves the
-            // map unchanged and needs no atomic
-            const unsigned long long key = zkey(t, org);
-            unsigned long long* z = &d.zbuf[y * d.cam.W + x];
-            if (key < __hip_atomic_load(z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(z, key);
+            if (e2 <= r2) atomicMin(&d.zbuf[y * d.cam.W + x], zkey(t, org));
         }
     }
 }
@@ -511,7 +506,8 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
                     const int x = ux + ox;
                     if (x < 0 || x >= d.cam.W) continue;
                     const int u = y * d.cam.W + x;
-                    if ((unsigned)(d.zbuf[u] & 0xffffffffull) != (unsigned)org) continue;
+                    // the index half of the key (its low word)
+                    if (reinterpret_cast<const unsigned*>(d.zbuf)[2 * u] != (unsigned)org) continue;
                     const float4 q = d.nmap[u];
                     if (!(q.w > 0.f)) continue;
                     const float3 dq3 = sub3(wp.v, backproject(d.cam, x, y, q.w));
