@@ -499,15 +499,27 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         if (ok) {
             const float rr = d.radius[ic];
             const int h = rr > 0.f ? splat_half(d.cam, rr, wp.v.z) : 0;
+            const unsigned* zw = reinterpret_cast<const unsigned*>(d.zbuf);   // index half of a key: its low word
             for (int oy = -h; oy <= h; ++oy) {
                 const int y = uy + oy;
                 if (y < 0 || y >= d.cam.H) continue;
-                for (int ox = -h; ox <= h; ++ox) {
-                    const int x = ux + ox;
-                    if (x < 0 || x >= d.cam.W) continue;
+                // the row's index words loaded together, then the pixels this
+                // surfel won visited left to right
+                unsigned won = 0;
+                unsigned wv[2 * kSplatMaxPx + 1];
+#pragma unroll
+                for (int c = 0; c <= 2 * kSplatMaxPx; ++c) {
+                    const int x = ux - h + c;
+                    const bool inb = c <= 2 * h && x >= 0 && x < d.cam.W;
+                    wv[c] = inb ? zw[2 * (y * d.cam.W + x)] : 0xffffffffu;
+                }
+#pragma unroll
+                for (int c = 0; c <= 2 * kSplatMaxPx; ++c) won |= (wv[c] == (unsigned)org) ? 1u << c : 0u;
+                while (won != 0u) {
+                    const int c = __builtin_ctz(won);
+                    won &= won - 1u;
+                    const int x = ux - h + c;
                     const int u = y * d.cam.W + x;
-                    // the index half of the key (its low word)
-                    if (reinterpret_cast<const unsigned*>(d.zbuf)[2 * u] != (unsigned)org) continue;
                     const float4 q = d.nmap[u];
                     if (!(q.w > 0.f)) continue;
                     const float3 dq3 = sub3(wp.v, backproject(d.cam, x, y, q.w));
