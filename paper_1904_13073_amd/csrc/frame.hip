@@ -307,12 +307,13 @@ __device__ __forceinline__ void factor_insert(float (&R)[4][4], int used, float 
     }
 }
 
-// The thread's row in LDS: node block k at its node's position in the segment
-// (threads past the pack capacity are never live and keep no row).
-__device__ __forceinline__ void put_row(const FrameDesc& d, float* rows, bool live, int i, float (&Jw)[4][3],
-                                        float (&Jt)[4][3], float r) {
-    if (threadIdx.x >= kCorrPack) return;
-    float* row = &rows[threadIdx.x * kRowPad];
+// A row in LDS (slot: the thread's own, or a compacted one): node block k at
+// its node's position in the segment (threads past the pack capacity are never
+// live and keep no row).
+__device__ __forceinline__ void put_row(const FrameDesc& d, float* rows, int slot, bool live, int i,
+                                        float (&Jw)[4][3], float (&Jt)[4][3], float r) {
+    if (slot >= kCorrPack) return;
+    float* row = &rows[slot * kRowPad];
     const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
     const int jd = d.jac_dtype;          // uniform: one branch for the whole row
     if (jd != 0) {
@@ -378,23 +379,43 @@ __device__ __forceinline__ void capture_rows(const FrameDesc& d, const float* ro
     }
 }
 
+// Extra splat rows before thread t of the pack: counts 0..3 per thread held as
+// two ballot bit planes per wave (planes[w], planes[4 + w]).
+__device__ __forceinline__ int extra_before(const unsigned long long* planes, int t) {
+    const int w = t / kWave, l = t % kWave;
+    int c = 0;
+    for (int q = 0; q < w; ++q) c += __popcll(planes[q]) + 2 * __popcll(planes[4 + q]);
+    if (w < kCorrBlock / kWave) {
+        const unsigned long long lm = l ? (~0ull >> (kWave - l)) : 0ull;
+        c += __popcll(planes[w] & lm) + 2 * __popcll(planes[4 + w] & lm);
+    }
+    return c;
+}
+
 // Segment Gram matrices of the pack's rows, one wave per segment. Accumulator
 // element t of lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 +
 // t % 4. The output slot of each element: the rank of its node pair among the
 // segment's pairs x 36 + position in the 6x6 sub-block; J^T r and r^T r after
 // the sub-blocks. The whole output is staged in LDS and stored as whole lines;
 // with `more` (later splat rounds) segments without a marked row are skipped
-// and the sums are added to the stored ones (the same lanes stored those words).
+// and the sums are added to the stored ones (the same lanes stored those words);
+// with `planes` the rows are the compacted extra rows from slot `base` on, a
+// segment's being those of its surfels in order.
 __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* rows, float4* stage, int tile, int p0,
-                                              const unsigned long long* more) {
+                                              const unsigned long long* more,
+                                              const unsigned long long* planes = nullptr, int base = 0) {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int comp = lane & 31, half = lane >> 5;
     const int g0 = d.pack_seg[tile], g1 = d.pack_seg[tile + 1];
     float* sg = reinterpret_cast<float*>(stage);
     const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
-        const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
-        if (more != nullptr) {
+        int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
+        if (planes != nullptr) {
+            s0 = min(max(extra_before(planes, s0) - base, 0), kCorrPack);
+            s1 = min(max(extra_before(planes, s1) - base, 0), kCorrPack);
+            if (s0 == s1) continue;                            // uniform over the wave
+        } else if (more != nullptr) {
             bool any = false;
             for (int m = s0 + lane; m < s1; m += kWave) any |= ((more[m / kWave] >> (m % kWave)) & 1ull) != 0;
             if (__ballot(any) == 0) continue;                  // uniform over the wave
@@ -430,7 +451,7 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
-        if (more != nullptr) {
+        if (more != nullptr || planes != nullptr) {
             for (int q = lane; q < size / 4; q += kWave) {
                 const float4 a = out[q], c4 = stage[q];
                 out[q] = make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w);
@@ -450,7 +471,7 @@ template <bool SPLAT>
 __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ double sh[40];
     __shared__ int shi[16];
-    __shared__ unsigned long long more[kCorrBlock / kWave];   // splat rounds: the surfels with a row
+    __shared__ unsigned long long planes[2 * (kCorrBlock / kWave)];   // splat: extra rows per surfel
     __shared__ float rows[kCorrPack * kRowPad + 8];
     __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
     const Where at = locate(b);
@@ -535,39 +556,66 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
             }
         }
         tile_sums(d, rows, sh, shi, at.tile, e_own, npair);
-        // round j: row j of the factor of every surfel with more than j pairs;
-        // later rounds add their Gram sums to the first's outputs and stop at
-        // the first round no surfel of the pack has. The warp is formed again
-        // per round, so that only the factor stays live across rounds.
-#pragma nounroll
-        for (int j = 0; j < 4; ++j) {
-            const bool has = npair > j;
-            if (j > 0 && !__syncthreads_or(has)) break;        // uniform; the rows are free again
+        // round 0: row 0 of the factor of every surfel with a pair
+        {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { Jw[k][c] = 0.f; Jt[k][c] = 0.f; }
             r = 0.f;
-            if (has) {
-                const float nx = j == 0 ? R[0][0] : 0.f;
-                const float ny = j == 0 ? R[0][1] : (j == 1 ? R[1][1] : 0.f);
-                const float nz = j == 0 ? R[0][2] : (j == 1 ? R[1][2] : (j == 2 ? R[2][2] : 0.f));
-                r = j == 0 ? R[0][3] : (j == 1 ? R[1][3] : (j == 2 ? R[2][3] : R[3][3]));
+            if (npair > 0) {
+                r = R[0][3];
                 int i2 = i;
-                asm volatile("" : "+v"(i2));                     // (kept per round, not hoisted)
+                asm volatile("" : "+v"(i2));                     // (not kept from the scan)
                 const int4 id2 = d.idx[i2];
                 const float4 w42 = d.w[i2];
                 const float3 v2 = make_float3(d.px[i2], d.py[i2], d.pz[i2]);
                 const float3 n2 = make_float3(d.nx[i2], d.ny[i2], d.nz[i2]);
                 const Warp w2 = warp_surfel(id2, w42, v2, n2, d.dq);
-                jacobian_rows(d, id2, w42, v2, make_float3(nx, ny, nz), w2, Jw, Jt);
+                jacobian_rows(d, id2, w42, v2, make_float3(R[0][0], R[0][1], R[0][2]), w2, Jw, Jt);
             }
-            const unsigned long long bal = __ballot(has);
-            if (lane == 0) more[wave] = bal;
-            put_row(d, rows, live, i, Jw, Jt, r);
+            put_row(d, rows, threadIdx.x, live, i, Jw, Jt, r);
             __syncthreads();
-            if (j == 0 && capture) capture_rows(d, rows, p0, p1);
-            segment_grams(d, rows, stage4[wave], at.tile, p0, j > 0 ? more : nullptr);
+            if (capture) capture_rows(d, rows, p0, p1);
+            segment_grams(d, rows, stage4[wave], at.tile, p0, nullptr);
+        }
+        // the surfels' further factor rows (1 to 3 each), compacted in surfel
+        // order into the rows, so that a segment's are contiguous; their Gram
+        // sums are added in one more pass over the segments
+        const int extra = live ? max(0, min(npair, 4) - 1) : 0;
+        {
+            const unsigned long long e0 = __ballot((extra & 1) != 0), e1 = __ballot((extra & 2) != 0);
+            if (lane == 0) { planes[wave] = e0; planes[4 + wave] = e1; }
+        }
+        __syncthreads();                                       // (round 0's rows are read too)
+        const int total = extra_before(planes, kCorrBlock);
+        const int slot = extra_before(planes, threadIdx.x);
+        // in chunks of the pack's row capacity (one chunk unless a pack has
+        // more extra rows than surfels)
+#pragma nounroll
+        for (int base = 0; base < total; base += kCorrPack) {
+            if (base > 0) __syncthreads();                     // the previous chunk's rows are read
+            if (extra > 0 && slot + extra > base && slot < base + kCorrPack) {
+                int i2 = i;
+                asm volatile("" : "+v"(i2));                     // (not kept from the scan)
+                const int4 id2 = d.idx[i2];
+                const float4 w42 = d.w[i2];
+                const float3 v2 = make_float3(d.px[i2], d.py[i2], d.pz[i2]);
+                const float3 n2 = make_float3(d.nx[i2], d.ny[i2], d.nz[i2]);
+                const Warp w2 = warp_surfel(id2, w42, v2, n2, d.dq);
+#pragma nounroll
+                for (int j = 1; j <= extra; ++j) {
+                    const int sl = slot + j - 1 - base;
+                    if (sl < 0 || sl >= kCorrPack) continue;
+                    const float ny = j == 1 ? R[1][1] : 0.f;
+                    const float nz = j == 1 ? R[1][2] : (j == 2 ? R[2][2] : 0.f);
+                    const float rj = j == 1 ? R[1][3] : (j == 2 ? R[2][3] : R[3][3]);
+                    jacobian_rows(d, id2, w42, v2, make_float3(0.f, ny, nz), w2, Jw, Jt);
+                    put_row(d, rows, sl, live, i, Jw, Jt, rj);
+                }
+            }
+            __syncthreads();
+            segment_grams(d, rows, stage4[wave], at.tile, p0, nullptr, planes, base);
         }
         return;
     }
