@@ -104,3 +104,48 @@ def test_splat_batch_equals_solo_and_radius_zero_is_the_point_rule(swgn, scene_c
     zero.solve_frame(a.depth)
     assert np.array_equal(zero.node_se3(), point)
     zero.close()
+
+
+def test_splat_many_pairs_per_surfel_overflow_the_pack_rows(swgn, scene_cache):
+    """One surfel in nine with three times the radius: most discs fill the
+    capped 9 x 9 box and win many pixels, so most surfels carry all four rows
+    of their pair factor and a pack's extra rows (up to 3 per surfel) exceed
+    its LDS rows, which are then taken in chunks. The frame must still match
+    the oracle run on the GPU's own pairs."""
+    s = scene_cache("tiny")
+    keep = np.arange(s.surfel_pos.shape[0]) % 9 == 0
+    pos, nrm = s.surfel_pos[keep], s.surfel_nrm[keep]
+    rad = 3.0 * _radii(s)[keep]
+
+    def stream(**cfg):
+        st = swgn.Stream(swgn.config_for(s, splat=1, **cfg))
+        st.set_reference_surfels(pos, nrm)
+        st.set_node_graph(s.node_pos)
+        st.set_surfel_attributes(rad)
+        return st
+
+    st = stream()
+    stats = st.solve_frame(s.depth)
+    got = st.node_se3()
+    st.close()
+    maps = []
+    for k in range(s.params.gn_iters):
+        st = stream(debug_iter=k)
+        st.solve_frame(s.depth)
+        maps.append(st.last_maps()[1])
+        assert np.array_equal(st.node_se3(), got)
+        st.close()
+    counts = np.bincount(maps[0][maps[0] >= 0], minlength=pos.shape[0])
+    paired = counts[counts > 0]
+    # extra rows per surfel min(n, 4) - 1: on average above one per surfel in
+    # every pack means more extra rows than a pack of surfels has LDS rows
+    assert np.mean(np.minimum(counts, 4) - 1 > 0) > 0.5 and np.mean(np.maximum(np.minimum(counts, 4) - 1, 0)) > 1.0
+    print(f"surfels {pos.shape[0]}, paired {paired.size}, mean pairs {paired.mean():.2f}, 4+ pairs {(counts >= 4).sum()}")
+    want, tr = S.oracle_solve(s.cam, pos, nrm, s.node_pos, s.depth, s.params, linear="pcg",
+                              splat_radius=rad, corr_maps=maps)
+    ang, dpos = se3_errors(got, want, s.node_pos)
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
+    assert stats["n_corr"] == tr["n_corr"]
+    e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
+    e_ref = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
+    assert np.max(np.abs(e_gpu - e_ref) / e_ref) < 1e-4
