@@ -82,27 +82,36 @@ def test_splat_frame_matches_oracle_on_its_pairs(swgn, scene_cache):
 
 
 def test_splat_batch_equals_solo_and_radius_zero_is_the_point_rule(swgn, scene_cache):
+    """Two frames each: the batch of two splat streams and a point stream is
+    captured as a graph on the first call and replayed on the second; every
+    stream equals its solo run after each frame, bit for bit."""
     a, b = scene_cache("tiny"), scene_cache("c1")
     ra, rb = _radii(a), _radii(b)
     solo = []
     for s, r in ((a, ra), (b, rb)):
         st = _stream(swgn, s, r)
         st.solve_frame(s.depth)
-        solo.append(st.node_se3())
+        first = st.node_se3()
+        st.solve_frame(s.depth)
+        solo.append((first, st.node_se3()))
         st.close()
     sts = [_stream(swgn, a, ra), _stream(swgn, b, rb), swgn.Stream(swgn.config_for(a))]
     sts[2].set_reference_surfels(a.surfel_pos, a.surfel_nrm)
     sts[2].set_node_graph(a.node_pos)
     bx = swgn.Batch(graph=True)
-    bx.solve(sts, [a.depth, b.depth, a.depth], with_stats=False)
-    assert np.array_equal(sts[0].node_se3(), solo[0]) and np.array_equal(sts[1].node_se3(), solo[1])
-    point = sts[2].node_se3()
+    point = []
+    for f in range(2):
+        bx.solve(sts, [a.depth, b.depth, a.depth], with_stats=False)
+        assert np.array_equal(sts[0].node_se3(), solo[0][f]) and np.array_equal(sts[1].node_se3(), solo[1][f]), f
+        point.append(sts[2].node_se3())
+    assert not np.array_equal(solo[0][0], solo[0][1])                # the second frame moved the state
     bx.close()
     for t in sts:
         t.close()
     zero = _stream(swgn, a, np.zeros_like(ra))
-    zero.solve_frame(a.depth)
-    assert np.array_equal(zero.node_se3(), point)
+    for f in range(2):
+        zero.solve_frame(a.depth)
+        assert np.array_equal(zero.node_se3(), point[f]), f
     zero.close()
 
 
