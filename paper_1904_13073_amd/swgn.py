@@ -8,8 +8,11 @@ a device pointer.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -90,10 +93,35 @@ class SwError(RuntimeError):
 
 _lib = None
 
+# Handles still open at interpreter exit are destroyed by an exit hook, which
+# runs before the HIP runtime and any profiler tear down; servers first (they
+# reference streams), then batches, then streams. After that hook, and while
+# the interpreter finalises, a finalizer makes no library call at all: a HIP
+# call into a runtime that is being torn down can crash the process.
+_open = {"server": weakref.WeakSet(), "batch": weakref.WeakSet(), "stream": weakref.WeakSet()}
+_exiting = False
+
+
+def _no_more_calls() -> bool:
+    return _exiting or sys.is_finalizing()
+
+
+@atexit.register
+def _close_open_handles():
+    global _exiting
+    for kind in ("server", "batch", "stream"):
+        for obj in list(_open[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _exiting = True
+
 EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_stream",
            "sw_destroy_stream", "sw_set_reference_surfels", "sw_set_node_graph", "sw_set_node_se3",
            "sw_solve_frame", "sw_get_node_se3", "sw_get_sizes", "sw_get_skinning",
-           "sw_get_node_graph", "sw_get_pattern", "sw_get_last_maps", "sw_get_last_system",
+           "sw_get_node_graph", "sw_get_pattern", "sw_get_last_maps", "sw_get_last_live_normals",
+           "sw_get_last_system",
            "sw_get_last_jacobian", "sw_create_batch", "sw_destroy_batch", "sw_batch_last_error",
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
@@ -135,6 +163,7 @@ def lib() -> C.CDLL:
         "sw_get_node_graph": (i32, [vp, ip]),
         "sw_get_pattern": (i32, [vp, ip, ip]),
         "sw_get_last_maps": (i32, [vp, ip, ip, fp, fp]),
+        "sw_get_last_live_normals": (i32, [vp, fp]),
         "sw_get_last_system": (i32, [vp, fp, fp, fp]),
         "sw_get_last_jacobian": (i32, [vp, fp, fp]),
         "sw_set_surfel_attributes": (i32, [vp, i64, fp, fp, ip, ip, i32]),
@@ -293,6 +322,7 @@ class Batch:
             raise ValueError(f"pcg must be one of {sorted(modes)}")
         self.h = sw_create_batch(hip_stream, (SW_BATCH_TIMING if timing else 0) | (SW_BATCH_GRAPH if graph else 0)
                                  | modes[pcg])
+        _open["batch"].add(self)
 
     def close(self):
         if self.h:
@@ -300,6 +330,8 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        if _no_more_calls():
+            return
         try:
             self.close()
         except Exception:
@@ -345,6 +377,7 @@ class Server:
             raise SwError(st, lib().sw_status_string(st).decode())
         self.h = h
         self._keep = {}
+        _open["server"].add(self)
 
     def _check(self, st: int):
         if st != SW_OK:
@@ -357,6 +390,8 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
+        if _no_more_calls():
+            return
         try:
             self.close()
         except Exception:
@@ -444,6 +479,13 @@ def sw_get_last_maps(h, width: int, height: int):
     _check(h, lib().sw_get_last_maps(h, I.ctypes.data_as(C.c_void_p), Cm.ctypes.data_as(C.c_void_p),
                                      live.ctypes.data_as(C.c_void_p), nrm.ctypes.data_as(C.c_void_p)))
     return I, Cm, live, nrm
+
+
+def sw_get_last_live_normals(h) -> np.ndarray:
+    ns, _, _ = sw_get_sizes(h)
+    out = np.empty((ns, 3), np.float32)
+    _check(h, lib().sw_get_last_live_normals(h, out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def sw_get_last_system(h):
@@ -561,6 +603,7 @@ class Stream:
         for k, v in overrides.items():
             setattr(self.cfg, k, v)
         self.h = sw_create_stream(self.cfg, hip_stream)
+        _open["stream"].add(self)
 
     def close(self):
         if self.h:
@@ -568,6 +611,8 @@ class Stream:
             self.h = None
 
     def __del__(self):
+        if _no_more_calls():
+            return
         try:
             self.close()
         except Exception:
@@ -611,6 +656,9 @@ class Stream:
 
     def last_maps(self):
         return sw_get_last_maps(self.h, self.cfg.width, self.cfg.height)
+
+    def last_live_normals(self):
+        return sw_get_last_live_normals(self.h)
 
     def last_system(self):
         return sw_get_last_system(self.h)
