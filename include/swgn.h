@@ -197,7 +197,8 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
  * sw_set_reference_surfels); any pointer may be NULL to keep that attribute.
  * Defaults after sw_set_reference_surfels: radius 0, confidence 1,
  * t_observed 0, t_init 0. Setting surfels again resets them. The data is
- * copied. */
+ * copied. A radius must be finite and >= 0 (0 = an unsized point): any other
+ * value returns SW_EINVAL and leaves every attribute unchanged. */
 sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, const float* confidence,
                                    const int32_t* t_observed, const int32_t* t_init, int32_t on_device);
 
@@ -476,6 +477,14 @@ sw_status sw_get_pattern(sw_stream s, int32_t* row_ptr, int32_t* col_idx);
  * SW_ESTATE if nothing was captured. */
 sw_status sw_get_last_maps(sw_stream s, int32_t* index_map, int32_t* corr_map,
                            float* live_pos, float* depth_normals);
+
+/* Live normals of the captured iteration (Sec. 3, Eq. 2: the blended rotation
+ * applied to each reference normal): n_surfels x 3 fp32 in the caller's
+ * surfel order, NaN where the blend is undefined. These, with the live
+ * positions above, are the inputs of every decision the correspondence step
+ * takes (Sec. 7: the normal-angle gate). live_nrm is a host array owned by
+ * the caller. SW_ESTATE if nothing was captured. */
+sw_status sw_get_last_live_normals(sw_stream s, float* live_nrm);
 
 /* Linear system of the captured iteration: blocks (n_blocks x 36, row-major
  * 6x6 blocks of J^T J + mu I in the order of sw_get_pattern; unknowns of node k

@@ -487,7 +487,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     if (s->cfg.debug_iter >= 0) {
         s->dbg_index = G.alloc<int>(h.npx);
         h.dbg_corr = G.alloc<int>(h.npx);
-        h.dbg_live = G.alloc<float>(3 * (size_t)ns);
+        h.dbg_live = G.alloc<float>(6 * (size_t)ns);      // live positions, then live normals
         s->dbg_H = G.alloc<float>(36 * (size_t)h.nb);
         s->dbg_g = G.alloc<float>(6 * (size_t)nn);
         s->dbg_x = G.alloc<float>(6 * (size_t)nn);
@@ -1006,6 +1006,20 @@ sw_status sw_set_surfel_attributes(sw_stream s, int64_t n, const float* radius, 
     if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
     return guarded(s->err, [&]() -> sw_status {
         hipStream_t st = s->exec.st;
+        if (radius) {
+            // a disc needs a radius >= 0 (0 = an unsized point); anything else
+            // is refused before any attribute changes
+            std::vector<float> hr((size_t)n);
+            if (on_device) {
+                SWGN_HIP(hipMemcpyAsync(hr.data(), radius, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+                SWGN_HIP(hipStreamSynchronize(st));
+            } else {
+                std::memcpy(hr.data(), radius, sizeof(float) * n);
+            }
+            for (int64_t i = 0; i < n; ++i)
+                if (!(hr[i] >= 0.f) || !std::isfinite(hr[i]))
+                    return fail(s->err, SW_EINVAL, "radius " + std::to_string(i) + " is negative or not finite");
+        }
         if (radius) copy_in(s->in_rad, radius, sizeof(float) * n, on_device, st);
         if (confidence) copy_in(s->in_conf, confidence, sizeof(float) * n, on_device, st);
         if (t_observed) copy_in(s->in_tobs, t_observed, sizeof(int32_t) * n, on_device, st);
@@ -1431,6 +1445,19 @@ sw_status sw_get_last_maps(sw_stream s, int32_t* index_map, int32_t* corr_map, f
                 depth_normals[2 * npx + i] = nm[i].z;
             }
         }
+        return SW_OK;
+    });
+}
+
+sw_status sw_get_last_live_normals(sw_stream s, float* live_nrm) {
+    if (!s || !live_nrm) return SW_EINVAL;
+    if (s->server) server_quiesce(s->server, s);
+    if (!s->graph_set || !s->captured) return fail(s->err, SW_ESTATE, "no captured iteration");
+    return guarded(s->err, [&]() -> sw_status {
+        hipStream_t st = s->exec.st;
+        SWGN_HIP(hipMemcpyAsync(live_nrm, s->h.dbg_live + 3 * (size_t)s->ns, sizeof(float) * 3 * s->ns,
+                                hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
         return SW_OK;
     });
 }

@@ -92,3 +92,20 @@ def test_second_frame_continues_from_previous_warp(swgn, scene_cache):
     ang, d = se3_errors(first, second, s.node_pos)
     # already converged on this frame: the second solve barely moves
     assert d.max() < 1e-3
+
+
+@pytest.mark.parametrize("bad", [-1e-3, np.nan, np.inf])
+def test_bad_radius_is_refused(swgn, scene_cache, bad):
+    """A disc radius must be finite and >= 0 on both sides of the parity test;
+    anything else is refused and the attributes stay as they were."""
+    s = scene_cache("tiny")
+    st = stream_for(swgn, s, splat=1)
+    good = np.full(s.surfel_pos.shape[0], 0.004, np.float32)
+    st.set_surfel_attributes(good)
+    rad = good.copy()
+    rad[7] = bad
+    with pytest.raises(swgn.SwError) as e:
+        st.set_surfel_attributes(rad)
+    assert e.value.status == swgn.SW_EINVAL
+    assert np.array_equal(st.surfel_attributes()[0], good)
+    st.close()
