@@ -465,6 +465,20 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
     }
 }
 
+// A captured iteration's live surfel (caller order): position in dbg_live[0,
+// 3 ns), normal in dbg_live[3 ns, 6 ns); NaN for a surfel without a valid blend
+__device__ __forceinline__ void capture_live(const FrameDesc& d, int org, const Warp& wp) {
+    const float nanv = __int_as_float(0x7fc00000);
+    float* lp = d.dbg_live + 3 * (size_t)org;
+    float* ln = d.dbg_live + 3 * ((size_t)d.ns + org);
+    lp[0] = wp.ok ? wp.v.x : nanv;
+    lp[1] = wp.ok ? wp.v.y : nanv;
+    lp[2] = wp.ok ? wp.v.z : nanv;
+    ln[0] = wp.ok ? wp.n.x : nanv;
+    ln[1] = wp.ok ? wp.n.y : nanv;
+    ln[2] = wp.ok ? wp.n.z : nanv;
+}
+
 // SPLAT: a launch with a splat stream (the point rule's launches carry none of
 // the splat code)
 template <bool SPLAT>
@@ -504,12 +518,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         // the pixels this surfel won (index part of the key) that have a
         // normal and pass the gates, in row-major order of its box, reduced
         // to the factor R of their rows (a_p = (N_p, r_p))
-        if (live && capture) {
-            const float nanv = __int_as_float(0x7fc00000);
-            d.dbg_live[3 * org + 0] = wp.ok ? wp.v.x : nanv;
-            d.dbg_live[3 * org + 1] = wp.ok ? wp.v.y : nanv;
-            d.dbg_live[3 * org + 2] = wp.ok ? wp.v.z : nanv;
-        }
+        if (live && capture) capture_live(d, org, wp);
         int npair = 0;
         double e_own = 0.0;
         float R[4][4];
@@ -671,10 +680,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         for (int c = 0; c < 8; ++c) rows[kCorrPack * kRowPad + c] = 0.f;
     }
     if (live && capture) {
-        float nanv = __int_as_float(0x7fc00000);
-        d.dbg_live[3 * org + 0] = wp.ok ? wp.v.x : nanv;
-        d.dbg_live[3 * org + 1] = wp.ok ? wp.v.y : nanv;
-        d.dbg_live[3 * org + 2] = wp.ok ? wp.v.z : nanv;
+        capture_live(d, org, wp);
         if (matched) d.dbg_corr[pix] = org;
     }
     double e = block_sum((double)r * (double)r, sh);   // (synchronises the rows too)

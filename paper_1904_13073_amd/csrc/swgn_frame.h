@@ -113,7 +113,7 @@ struct FrameDesc {
     const int *slot_u, *slot_t;   // [nb] ELL slot of each upper block and of its transpose (-1: diagonal)
     // resident: capture of one iteration (null unless requested)
     int* dbg_corr;
-    float* dbg_live;
+    float* dbg_live;              // [6 ns]: live positions, then live normals (caller order)
     float* J;                     // [pitch][32]: 30 Jacobian entries (5 node positions), r, zero
     // workspace of a frame in flight
     float* depth;                 // copy of a host depth image

@@ -1,4 +1,5 @@
-"""Helpers shared by the GPU tests (no solver arithmetic)."""
+"""Helpers shared by the GPU tests (no solver arithmetic of their own: the
+replica maps are the oracle's)."""
 import numpy as np
 import pytest
 
@@ -57,22 +58,68 @@ def expected_pattern(idx, nbr, nn):
     return row_ptr, np.asarray(cols)
 
 
-def solve_with_maps(swgn, scene, **cfg):
-    """One frame solve of a fresh stream, plus the correspondence map of each
-    Gauss-Newton iteration (one captured rerun per iteration, each checked to
-    end where the solve did: capturing does not change a solve)."""
-    st = stream_for(swgn, scene, **cfg)
+def solve_with_captures(swgn, scene, make=None, **cfg):
+    """One frame solve of a fresh stream, plus every Gauss-Newton iteration's
+    capture (one captured rerun per iteration, each checked to end where the
+    solve did: capturing does not change a solve): index map I, correspondence
+    map C, normal map N (3 x H x W) and the live surfels (positions, normals)
+    the iteration's decisions were taken on. `make(**cfg)` builds a stream
+    (default: stream_for on the scene)."""
+    if make is None:
+        def make(**c):
+            return stream_for(swgn, scene, **c)
+    st = make(**cfg)
     stats = st.solve_frame(scene.depth)
     got = st.node_se3()
     st.close()
-    maps = []
+    caps = []
     for k in range(cfg.get("gn_iters", scene.params.gn_iters)):
-        st = stream_for(swgn, scene, debug_iter=k, **cfg)
+        st = make(debug_iter=k, **cfg)
         st.solve_frame(scene.depth)
-        maps.append(st.last_maps()[1])
+        I, Cm, live, N = st.last_maps()
+        caps.append(dict(I=I, C=Cm, N=N, live=live, nrm=st.last_live_normals()))
         assert np.array_equal(st.node_se3(), got), "a captured solve ended elsewhere"
         st.close()
-    return got, stats, maps
+    return got, stats, caps
+
+
+def solve_with_maps(swgn, scene, **cfg):
+    """solve_with_captures, keeping only each iteration's correspondence map."""
+    got, stats, caps = solve_with_captures(swgn, scene, **cfg)
+    return got, stats, [c["C"] for c in caps]
+
+
+def replica_maps(scene, live, nrm, radius=None, visible=None):
+    """The FP32 decision replica's index and correspondence maps at the given
+    FP32 live surfels (the GPU's own): the point rule, or disc splats of
+    `radius` (pixel-driven pairs)."""
+    from oracle import replica32 as R32
+    p, cam = scene.params, scene.cam
+    N32, ok = R32.normal_map(scene.depth, cam, p.edge_gate)
+    C = np.full((cam.height, cam.width), -1, np.int64)
+    if radius is None:
+        I = R32.index_map(live, cam, visible)
+        m, ux, uy = R32.correspondence(live, nrm, I, scene.depth, N32, ok, cam, p.corr_dist, p.corr_normal,
+                                       visible)
+        C[uy[m], ux[m]] = np.flatnonzero(m)
+    else:
+        I = R32.splat_index_map(live, nrm, radius, cam, visible)
+        k, ux, uy = R32.splat_pairs(live, nrm, I, scene.depth, N32, ok, cam, p.corr_dist, p.corr_normal)
+        C[uy, ux] = k
+    return I, C
+
+
+def assert_maps_match_replica(scene, caps, stats=None, radius=None):
+    """Every captured iteration's index and correspondence maps equal the
+    replica's, bit for bit, fed that iteration's GPU live surfels; the
+    iteration's correspondence count is the map's."""
+    for k, c in enumerate(caps):
+        I_ref, C_ref = replica_maps(scene, c["live"], c["nrm"], radius)
+        dI = int(np.count_nonzero(c["I"] != I_ref))
+        dC = int(np.count_nonzero(c["C"] != C_ref))
+        assert dI == 0 and dC == 0, f"iteration {k}: {dI} index-map and {dC} correspondence-map pixels differ"
+        if stats is not None:
+            assert stats["n_corr"][k] == int(np.count_nonzero(C_ref >= 0)), k
 
 
 def map_flips(maps, trace):
@@ -80,3 +127,40 @@ def map_flips(maps, trace):
     oracle's own association (a correspondence that moved by a pixel counts
     twice)."""
     return [int(np.count_nonzero(m != trace["lin"][k]["corr_map"])) for k, m in enumerate(maps)]
+
+
+# Bounds of a whole frame against the oracle's own association (see the
+# parity tests): (flips per iteration, max rad, median rad, max m, median m)
+OWN_BOUNDS_FULL = (400, 5e-3, 2e-5, 5e-4, 2e-6)
+
+
+def check_frame_against_oracle(scene, got, stats, caps, bounds=OWN_BOUNDS_FULL, label=""):
+    """A whole frame's result (transforms `got`, statistics, per-iteration
+    captures) against the FP64 oracle: the association bit for bit against
+    the replica at every iteration; the transforms against the oracle's own
+    association within `bounds`; the arithmetic strictly (1e-4 rad, 1e-5 m,
+    energies 1e-4) against the oracle run on the GPU's correspondences. Both
+    oracle runs use the same 10-iteration FP64 block-Jacobi PCG mode."""
+    from oracle import solve as S
+    assert_maps_match_replica(scene, caps, stats)
+    p = scene.params
+    G = p.gn_iters
+    own_se3, own = S.oracle_solve(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos, scene.depth, p,
+                                  linear="pcg", keep=list(range(G)))
+    flips = map_flips([c["C"] for c in caps], own)
+    ang, dpos = se3_errors(got, own_se3, scene.node_pos)
+    fb, amax, amed, pmax, pmed = bounds
+    print(f"{label}: flips per iteration {flips} of {own['n_corr']}; own association: rotation max "
+          f"{ang.max():.3e} median {np.median(ang):.3e} rad, position max {dpos.max():.3e} "
+          f"median {np.median(dpos):.3e} m")
+    assert max(flips) <= fb, flips
+    assert ang.max() < amax and np.median(ang) < amed, (ang.max(), np.median(ang))
+    assert dpos.max() < pmax and np.median(dpos) < pmed, (dpos.max(), np.median(dpos))
+    want, tr = S.oracle_solve(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos, scene.depth, p,
+                              linear="pcg", corr_maps=[c["C"] for c in caps])
+    ang, dpos = se3_errors(got, want, scene.node_pos)
+    print(f"{label}: on the GPU association: rotation max {ang.max():.3e} rad, position max {dpos.max():.3e} m")
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
+    e_gpu = np.array(stats["e_data"]) + p.lambda_reg * np.array(stats["e_reg"])
+    e_ref = np.array(tr["e_data"]) + p.lambda_reg * np.array(tr["e_reg"])
+    assert np.allclose(e_gpu, e_ref, rtol=1e-4)

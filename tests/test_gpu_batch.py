@@ -5,7 +5,7 @@ frames, with uneven iteration counts, captures and a failing member."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_lib, stream_for
+from gpu_common import check_frame_against_oracle, gpu_lib, stream_for
 
 pytestmark = pytest.mark.gpu
 
@@ -226,3 +226,40 @@ def test_fused_and_split_pcg_schedules_agree_bit_for_bit(swgn, scene_cache):
     _assert_same(*out["split"], *out["fused"])
     solo = _solo(swgn, scenes, frames, cfgs)
     _assert_same(*solo, *out["split"])
+
+
+def test_batched_uneven_member_against_the_oracle(swgn, scene_cache):
+    """A member of uneven-stream shape (a random 640x480 or 320x240 scene of
+    the uneven-streams workload) solved inside a batch of four different
+    streams, against the FP64 oracle: its association at every iteration
+    (captured inside the batch) bit for bit against the replica, its
+    transforms against the oracle's own association and, strictly, against
+    the oracle run on its correspondences."""
+    scenes = _scenes(scene_cache, [("random", 400), ("tiny", None), ("c1", None), ("random", 402)])
+    G = scenes[0].params.gn_iters
+
+    def run(debug):
+        sts = [stream_for(swgn, sc, **({"debug_iter": debug} if i == 0 and debug is not None else {}))
+               for i, sc in enumerate(scenes)]
+        b = swgn.Batch()
+        res, status = b.solve(sts, [s.depth for s in scenes])
+        assert status == [swgn.SW_OK] * len(sts)
+        cap = None
+        if debug is not None:
+            I, Cm, live, N = sts[0].last_maps()
+            cap = dict(I=I, C=Cm, N=N, live=live, nrm=sts[0].last_live_normals())
+        se3 = sts[0].node_se3()
+        for st in sts:
+            st.close()
+        b.close()
+        return se3, res[0], cap
+
+    got, stats, _ = run(None)
+    caps = []
+    for k in range(G):
+        se3, _, cap = run(k)
+        assert np.array_equal(se3, got), "a captured batch ended elsewhere"
+        caps.append(cap)
+    s = scenes[0]
+    check_frame_against_oracle(s, got, stats, caps,
+                               label=f"batched member {s.cam.width}x{s.cam.height}, {s.node_pos.shape[0]} nodes")

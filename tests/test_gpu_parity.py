@@ -9,7 +9,8 @@ from FP32 arithmetic; node transforms after a whole frame within 1e-4 rad and
 import numpy as np
 import pytest
 
-from gpu_common import expected_pattern, gpu_lib, map_flips, se3_errors, solve_with_maps, stream_for
+from gpu_common import (assert_maps_match_replica, expected_pattern, gpu_lib, map_flips, replica_maps,
+                        se3_errors, solve_with_captures, stream_for)
 from oracle import replica32 as R32
 from oracle import skin
 from oracle import solve as S
@@ -99,8 +100,8 @@ def tiny_gt_case(swgn, scene_cache):
     s = scene_cache("tiny")
     st = stream_for(swgn, s, se3=s.gt_se3, debug_iter=0, gn_iters=1)
     st.solve_frame(s.depth)
-    out = dict(maps=st.last_maps(), system=st.last_system(), jac=st.last_jacobian(),
-               pattern=st.pattern())
+    out = dict(maps=st.last_maps(), nrm=st.last_live_normals(), system=st.last_system(),
+               jac=st.last_jacobian(), pattern=st.pattern())
     st.close()
     pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
     R, t = se3_to_rt(s.gt_se3.astype(np.float32).astype(np.float64))
@@ -112,10 +113,16 @@ def tiny_gt_case(swgn, scene_cache):
 def test_warp_and_association_at_non_identity_state(tiny_gt_case):
     s, out, pb, lin, A, g = tiny_gt_case
     I, Cm, live, N = out["maps"]
-    v64 = lin["ws"]["v"]
-    assert np.max(np.abs(live.astype(np.float64) - v64)) < 1e-6
-    # index and correspondence maps: the FP32 decisions agree except where the
-    # FP32 rounding of the live positions crosses a pixel or gate boundary
+    nrm = out["nrm"]
+    ws = lin["ws"]
+    assert np.max(np.abs(live.astype(np.float64) - ws["v"])) < 1e-6
+    assert np.max(np.abs(nrm.astype(np.float64) - ws["n"])) < 1e-6
+    # the index and correspondence maps are the FP32 decisions taken on the
+    # GPU's own FP32 live surfels: bit for bit
+    I_ref, C_ref = replica_maps(s, live, nrm)
+    assert np.array_equal(I, I_ref) and np.array_equal(Cm, C_ref)
+    # against the FP64 live surfels they may differ only where a projection
+    # or a gate lies within FP32 rounding of its boundary
     diff_I = np.count_nonzero(I != lin["I"])
     diff_C = np.count_nonzero(Cm != lin["corr_map"])
     assert diff_I <= 2 and diff_C <= 2, (diff_I, diff_C)
@@ -148,29 +155,129 @@ def test_jacobian_and_system_at_non_identity_state(tiny_gt_case):
     assert np.linalg.norm(gg.ravel() - g) <= 1e-4 * np.linalg.norm(g)
 
 
-@pytest.mark.parametrize("name", ["tiny", "c1"])
-def test_frame_solve_matches_oracle_pcg(swgn, scene_cache, name):
-    """A whole frame against the FP64 oracle with the same 10-iteration PCG.
-    Association is discrete: the GPU's FP32 decisions may fall the other way
-    at a near-tie (a live point on a pixel boundary or a gate at its
-    threshold), and a weakly held node then moves visibly. So the GPU's
-    correspondences at every iteration may differ from the oracle's own in at
-    most 4 pixels (2 surfels), and the arithmetic is compared strictly with
-    the oracle run on the GPU's correspondences."""
+# Whole frames. Each GPU iteration's association is checked bit for bit
+# against the FP32 replica fed that iteration's GPU live surfels. The GPU's
+# FP32 live surfels differ from the oracle's FP64 ones by rounding, so a
+# surfel whose projection lies on a pixel boundary (or a gate value at its
+# threshold) can be matched differently on the two sides ("flips"), and a
+# weakly held node (few surfels; its rotation held mostly by the regulariser
+# and the damping) then moves by up to ~1e-3 rad. The transforms are therefore
+# compared twice: against the oracle's own association within a bound that
+# allows such moves (max) but not a systematic error (median), and strictly
+# (the arithmetic) against the oracle run on the GPU's correspondences.
+#   scene: (flips per iteration, max rad, median rad, max m, median m)
+OWN_BOUNDS = {"tiny": (4, 2e-3, 1e-5, 2e-4, 1e-6), "c1": (8, 2e-3, 1e-5, 2e-4, 1e-6),
+              "c2": (400, 5e-3, 2e-5, 5e-4, 2e-6)}
+
+
+@pytest.fixture(scope="module", params=["tiny", "c1", "c2"])
+def frame_case(request, swgn, scene_cache):
+    name = request.param
     s = scene_cache(name)
     G = s.params.gn_iters
-    got, stats, maps = solve_with_maps(swgn, s)
-    _, own = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
-                            keep=list(range(G)))
-    flips = map_flips(maps, own)
-    assert max(flips) <= 4, flips
-    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
-                              corr_maps=maps)
+    got, stats, caps = solve_with_captures(swgn, s)
+    own_se3, own = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
+                                  linear="pcg", keep=list(range(G)))
+    own["final_se3"] = own_se3
+    return name, s, got, stats, caps, own
+
+
+def test_association_bit_exact_at_every_iteration(frame_case):
+    """Index and correspondence maps of every Gauss-Newton iteration equal the
+    FP32 replica's at the GPU's own live surfels (positions and normals)."""
+    name, s, got, stats, caps, own = frame_case
+    assert_maps_match_replica(s, caps, stats)
+    N32, ok = R32.normal_map(s.depth, s.cam, s.params.edge_gate)
+    assert np.array_equal(np.moveaxis(caps[-1]["N"], 0, -1), N32)
+
+
+def test_frame_against_oracle_own_association(frame_case):
+    """The transforms after the whole frame against the oracle's own run
+    (its own FP64 association at every iteration)."""
+    name, s, got, stats, caps, own = frame_case
+    flips = map_flips([c["C"] for c in caps], own)
+    want = own["final_se3"]
     ang, dpos = se3_errors(got, want, s.node_pos)
-    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max(), flips)
+    fb, amax, amed, pmax, pmed = OWN_BOUNDS[name]
+    print(f"{name}: flips per iteration {flips} of {own['n_corr']}; own association: rotation max "
+          f"{ang.max():.3e} median {np.median(ang):.3e} rad, node position max {dpos.max():.3e} "
+          f"median {np.median(dpos):.3e} m")
+    assert max(flips) <= fb, flips
+    assert ang.max() < amax and np.median(ang) < amed, (ang.max(), np.median(ang))
+    assert dpos.max() < pmax and np.median(dpos) < pmed, (dpos.max(), np.median(dpos))
+    e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
+    e_own = np.array(own["e_data"]) + s.params.lambda_reg * np.array(own["e_reg"])
+    assert np.allclose(e_gpu, e_own, rtol=1e-4)
+
+
+def test_frame_arithmetic_on_the_gpu_association(frame_case):
+    """The arithmetic: the oracle run on the GPU's correspondences (the
+    association already checked bit for bit above) with the same 10-iteration
+    PCG; transforms within 1e-4 rad and 1e-5 m, energies within 1e-4."""
+    name, s, got, stats, caps, own = frame_case
+    want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
+                              corr_maps=[c["C"] for c in caps])
+    ang, dpos = se3_errors(got, want, s.node_pos)
+    print(f"{name}: on the GPU association: rotation max {ang.max():.3e} rad, position max {dpos.max():.3e} m")
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
     e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
     e_ref = np.array(tr["e_data"]) + s.params.lambda_reg * np.array(tr["e_reg"])
     assert np.allclose(e_gpu, e_ref, rtol=1e-4)
-    assert list(stats["n_corr"][:G]) == tr["n_corr"]
-    e_own = np.array(own["e_data"]) + s.params.lambda_reg * np.array(own["e_reg"])
-    assert np.allclose(e_gpu, e_own, rtol=1e-4)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_full_size_system_at_the_identity_state(swgn, scene_cache, name):
+    """At the identity state the association is exact on both sides (the live
+    surfels are the reference ones), so the GPU's whole linear system is
+    compared with the oracle's own: J^T J blocks and J^T r within 1e-5
+    (relative Frobenius), the 10-iteration PCG step within 1e-4 of the
+    oracle's FP64 PCG step. The multi-pack segment Grams, the fold and the
+    PCG all enter at full size."""
+    s = scene_cache(name)
+    st = stream_for(swgn, s, debug_iter=0, gn_iters=1)
+    st.solve_frame(s.depth)
+    blocks, gg, delta = st.last_system()
+    rp, cols = st.pattern()
+    Cm = st.last_maps()[1]
+    st.close()
+    pb = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
+    nn = s.node_pos.shape[0]
+    R, t = se3_to_rt(S.identity_se3(nn))
+    lin = S.linearize(pb, R, t)
+    assert np.array_equal(Cm, lin["corr_map"])           # the same correspondences
+    A, g = S.normal_equations(pb, lin)
+    A = A.tocsr()
+    rows = np.repeat(np.arange(nn), np.diff(rp))
+    ref = np.empty((cols.size, 6, 6))
+    for a in range(6):
+        for b in range(6):
+            ref[:, a, b] = np.asarray(A[6 * rows + a, 6 * cols + b]).ravel()
+    eH = np.linalg.norm(blocks.reshape(-1, 6, 6) - ref) / np.linalg.norm(ref)
+    eg = np.linalg.norm(gg.ravel() - g) / np.linalg.norm(g)
+    want = S.solve_pcg(A, g, s.params.pcg_iters)
+    ed = np.linalg.norm(delta.ravel() - want) / np.linalg.norm(want)
+    print(f"{name}: {cols.size} blocks, H {eH:.2e}, g {eg:.2e}, PCG step {ed:.2e} (relative Frobenius)")
+    assert eH <= 1e-5 and eg <= 1e-5 and ed <= 1e-4, (eH, eg, ed)
+
+
+@pytest.mark.parametrize("name", ["tiny", "c1"])
+def test_converged_pcg_against_cholesky(swgn, scene_cache, name):
+    """G-exact: the GPU PCG run until its residual is at most 1e-6 of |g| in
+    every Gauss-Newton iteration (the smallest count of 100, 200, 400, 800
+    that gets there is reported) against the oracle's dense Cholesky solve of
+    each step, on the GPU's correspondences: 1e-4 rad and 1e-5 m."""
+    s = scene_cache(name)
+    G = s.params.gn_iters
+    for P in (100, 200, 400, 800):
+        got, stats, caps = solve_with_captures(swgn, s, pcg_iters=P)
+        want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
+                                  linear="chol", corr_maps=[c["C"] for c in caps], keep=list(range(G)))
+        gnorm = np.array([np.linalg.norm(tr["lin"][k]["g"]) for k in range(G)])
+        rel = np.array(stats["pcg_resid"]) / gnorm
+        if np.all(rel <= 1e-6):
+            break
+    print(f"{name}: PCG iterations {P}, relative residual per GN iteration {np.array2string(rel, precision=2)}")
+    assert np.all(rel <= 1e-6), rel
+    ang, dpos = se3_errors(got, want, s.node_pos)
+    print(f"{name}: against Cholesky: rotation max {ang.max():.3e} rad, position max {dpos.max():.3e} m")
+    assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())

@@ -7,7 +7,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_common import gpu_lib, stream_for
+from gpu_common import check_frame_against_oracle, gpu_lib, solve_with_captures, stream_for
 
 pytestmark = pytest.mark.gpu
 
@@ -150,3 +150,36 @@ def test_device_frames_and_a_failing_member(swgn, scene_cache):
     sv.close()
     for st in sts:
         st.close()
+
+
+def test_served_frame_against_the_oracle(swgn, scene_cache):
+    """A frame of a stream of the uneven-streams workload, served among frames
+    of other streams, against the FP64 oracle. The served result equals the
+    stream's solo solve bit for bit, so the solo run's per-iteration
+    captures are the served frame's association; that association is checked
+    against the replica and the transforms against the oracle's own
+    association and, strictly, against the oracle on those correspondences."""
+    scenes = [scene_cache(n, s) for n, s in [("random", 402), ("c1", None), ("tiny", None)]]
+    s = scenes[0]
+    solo, stats, caps = solve_with_captures(swgn, s)
+    sv = swgn.Server(max_batch=4)
+    sts = [stream_for(swgn, sc) for sc in scenes]
+    for st in sts:
+        sv.attach(st)
+    tickets = []
+    for i in (1, 0, 2):                    # staggered: the frame joins one in flight
+        tickets.append((i, sv.submit(sts[i], scenes[i].depth)))
+        time.sleep(0.0005)
+    served = {}
+    for i, t in tickets:
+        st_i, info = sv.poll(t, wait_ms=-1)
+        assert info["status"] == swgn.SW_OK
+        served[i] = st_i
+    got = sts[0].node_se3()
+    sv.close()
+    for st in sts:
+        st.close()
+    assert np.array_equal(got, solo)
+    assert served[0]["n_corr"] == stats["n_corr"] and served[0]["e_data"] == stats["e_data"]
+    check_frame_against_oracle(s, got, served[0], caps,
+                               label=f"served frame {s.cam.width}x{s.cam.height}, {s.node_pos.shape[0]} nodes")

@@ -225,7 +225,14 @@ def test_visibility_mask_removes_surfels_from_the_index_map(scene_cache):
     conf = rng.uniform(0.0, 20.0, ns).astype(np.float32)
     tob = rng.integers(0, 10, ns)
     vis = S.visible_surfels(conf, tob, t_now=9, stable_conf=10.0, recent_frames=2)
-    assert np.array_equal(vis, (conf > 10.0) | (tob >= 7))
+    # Table 1: stable means confidence above delta_stable = 10, recent means
+    # observed within delta_recent = 2 frames; cases at each boundary
+    cases = [(10.0, 0, False), (np.nextafter(np.float32(10.0), np.float32(11.0)), 0, True),
+             (0.0, 7, True), (0.0, 6, False), (0.0, 9, True), (25.0, 6, True)]
+    got = S.visible_surfels(np.float32([c for c, _, _ in cases]), np.array([t for _, t, _ in cases]), t_now=9,
+                            stable_conf=10.0, recent_frames=2)
+    assert got.tolist() == [v for _, _, v in cases]
+    assert 0 < vis.sum() < ns
     R, t = Q.se3_to_rt(s.gt_se3.astype(np.float64))
     base = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
     allv = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
@@ -242,3 +249,25 @@ def test_visibility_mask_removes_surfels_from_the_index_map(scene_cache):
     want_I = R32.index_map(ws["v"].astype(np.float32), s.cam, ws["valid"])
     assert np.array_equal(lm["I"], want_I)
     assert 0 < lm["corr_idx"].size < l0["corr_idx"].size
+
+
+def test_nonrigid_gauss_newton_recovers_a_rigid_motion():
+    """Sec. 7 energy, Sec. 8 Gauss-Newton: a box corner moved by one rigid
+    transform T* and ray-cast exactly has its zero-energy optimum at every
+    node = T* (identical node transforms blend to T*, and the regulariser
+    vanishes). The non-rigid solve, with no rigid pre-alignment and exact
+    (Cholesky) steps, must bring every node there: rotation within 0.01 deg,
+    warped node position within 0.1 mm, from a start 2 deg and ~6 mm away."""
+    cam, pos, nrm, nodes, depth, params, Rs, ts = _rigid_scene()
+    se3, tr = S.oracle_solve(cam, pos, nrm, nodes, depth, params, linear="chol", rigid_iters=0,
+                             final_energy=True)
+    R, t = Q.se3_to_rt(se3)
+    ang = Rotation.from_matrix(R @ Rs.T).magnitude()
+    p = nodes.astype(np.float64)
+    dpos = np.linalg.norm(np.einsum("nij,nj->ni", R, p) + t - (p @ Rs.T + ts), axis=1)
+    assert np.rad2deg(ang.max()) < 0.01 and dpos.max() < 1e-4, (np.rad2deg(ang.max()), dpos.max())
+    # the node spread: every node carries the same transform
+    assert np.max(np.abs(R - R.mean(axis=0))) < 1e-6 and np.max(np.abs(t - t.mean(axis=0))) < 1e-6
+    e0 = tr["e_data"][0] + params.lambda_reg * tr["e_reg"][0]
+    ef = tr["e_final"][0] + params.lambda_reg * tr["e_final"][1]
+    assert ef < 1e-8 * e0 and tr["e_final"][2] > 0.8 * tr["n_corr"][0]
