@@ -129,12 +129,46 @@ def map_flips(maps, trace):
     return [int(np.count_nonzero(m != trace["lin"][k]["corr_map"])) for k, m in enumerate(maps)]
 
 
-# Bounds of a whole frame against the oracle's own association (see the
-# parity tests): (flips per iteration, max rad, median rad, max m, median m)
-OWN_BOUNDS_FULL = (400, 5e-3, 2e-5, 5e-4, 2e-6)
+# A whole frame against the oracle's own association. The two sides take
+# their FP32 and FP64 decisions on live surfels that differ by rounding, so
+# a surfel on a pixel boundary or at a gate threshold can be matched
+# differently ("flips"); the GPU's own decisions are checked bit for bit
+# against the replica separately. A flip changes every later step, and the
+# problem has weakly determined directions (point-to-plane does not see
+# tangential sliding; a node held by few surfels keeps its rotation mostly
+# through the regulariser and the damping), so the two trajectories part
+# across the graph. The oracle is as sensitive to its own input: on the
+# 320x240 uneven-streams scene (seed 400) the oracle against itself with
+# every depth scaled by 1 + 1e-6 (far below the sensor noise) flips up to 37
+# correspondences per iteration and moves nodes by a median 2.7e-5 rad, a
+# 99th percentile 3.0e-3 rad and at most 1.6e-2 rad (1.0e-3 m). The bound is
+# set at that scale: flips per iteration (as a fraction of the
+# correspondences), and the median, 99th percentile and worst node:
+#   (flip fraction, median rad, median m, p99 rad, p99 m, max rad, max m)
+OWN_POINT = (0.01, 5e-5, 5e-6, 5e-3, 3e-4, 2e-2, 2e-3)
 
 
-def check_frame_against_oracle(scene, got, stats, caps, bounds=OWN_BOUNDS_FULL, label=""):
+def own_association_report(flips, n_corr, ang, dpos):
+    over = (ang > 1e-4) | (dpos > 1e-5)
+    return dict(flip_frac=max(f / max(n, 1) for f, n in zip(flips, n_corr)), over_frac=float(np.mean(over)),
+                n_over=int(over.sum()), med_rad=float(np.median(ang)), med_m=float(np.median(dpos)),
+                max_rad=float(ang.max()), max_m=float(dpos.max()), p99_rad=float(np.percentile(ang, 99)),
+                p99_m=float(np.percentile(dpos, 99)))
+
+
+def assert_own_bounds(rep, bounds, label=""):
+    ff, mr, mm, pr, pm, xr, xm = bounds
+    print(f"{label}: own association: flips up to {rep['flip_frac']:.2e} of the correspondences; "
+          f"{rep['n_over']} nodes ({rep['over_frac']:.2%}) beyond 1e-4 rad / 1e-5 m; rotation median "
+          f"{rep['med_rad']:.2e} p99 {rep['p99_rad']:.2e} max {rep['max_rad']:.2e} rad; position median "
+          f"{rep['med_m']:.2e} p99 {rep['p99_m']:.2e} max {rep['max_m']:.2e} m")
+    assert rep["flip_frac"] <= ff, rep
+    assert rep["med_rad"] < mr and rep["med_m"] < mm, rep
+    assert rep["p99_rad"] < pr and rep["p99_m"] < pm, rep
+    assert rep["max_rad"] < xr and rep["max_m"] < xm, rep
+
+
+def check_frame_against_oracle(scene, got, stats, caps, bounds=OWN_POINT, label=""):
     """A whole frame's result (transforms `got`, statistics, per-iteration
     captures) against the FP64 oracle: the association bit for bit against
     the replica at every iteration; the transforms against the oracle's own
@@ -149,18 +183,15 @@ def check_frame_against_oracle(scene, got, stats, caps, bounds=OWN_BOUNDS_FULL, 
                                   linear="pcg", keep=list(range(G)))
     flips = map_flips([c["C"] for c in caps], own)
     ang, dpos = se3_errors(got, own_se3, scene.node_pos)
-    fb, amax, amed, pmax, pmed = bounds
-    print(f"{label}: flips per iteration {flips} of {own['n_corr']}; own association: rotation max "
-          f"{ang.max():.3e} median {np.median(ang):.3e} rad, position max {dpos.max():.3e} "
-          f"median {np.median(dpos):.3e} m")
-    assert max(flips) <= fb, flips
-    assert ang.max() < amax and np.median(ang) < amed, (ang.max(), np.median(ang))
-    assert dpos.max() < pmax and np.median(dpos) < pmed, (dpos.max(), np.median(dpos))
+    print(f"{label}: flips per iteration {flips} of {own['n_corr']}")
+    assert_own_bounds(own_association_report(flips, own["n_corr"], ang, dpos), bounds, label)
+    e_gpu = np.array(stats["e_data"]) + p.lambda_reg * np.array(stats["e_reg"])
+    e_own = np.array(own["e_data"]) + p.lambda_reg * np.array(own["e_reg"])
+    assert np.allclose(e_gpu, e_own, rtol=1e-4), np.max(np.abs(e_gpu - e_own) / e_own)
     want, tr = S.oracle_solve(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos, scene.depth, p,
                               linear="pcg", corr_maps=[c["C"] for c in caps])
     ang, dpos = se3_errors(got, want, scene.node_pos)
     print(f"{label}: on the GPU association: rotation max {ang.max():.3e} rad, position max {dpos.max():.3e} m")
     assert ang.max() < 1e-4 and dpos.max() < 1e-5, (ang.max(), dpos.max())
-    e_gpu = np.array(stats["e_data"]) + p.lambda_reg * np.array(stats["e_reg"])
     e_ref = np.array(tr["e_data"]) + p.lambda_reg * np.array(tr["e_reg"])
     assert np.allclose(e_gpu, e_ref, rtol=1e-4)

@@ -8,8 +8,9 @@ rounding 2^-12. The Gauss-Newton step built from them moves by about that
 fraction of its size, so the warped node positions and the energies stay
 close to the FP32 run's; the rotation of a node seen by few surfels is held
 mainly by the damping and the regulariser (a weak direction of the system)
-and can move much more, so its bound is on the median and, loosely, the
-maximum."""
+and can move much more. The bounds are about four times the measured errors.
+The Jacobian rows live only in LDS, so the 16-bit formats save no HBM bytes
+in this design: this is a precision study."""
 import numpy as np
 import pytest
 
@@ -18,8 +19,16 @@ from oracle import solve as S
 
 pytestmark = pytest.mark.gpu
 
-# dtype: (max rotation rad, median rotation rad, max position m, energy rel)
-BOUNDS = {0: (1e-4, 1e-5, 1e-5, 1e-4), 1: (5e-2, 5e-4, 5e-4, 1e-2), 2: (1e-2, 1e-4, 1e-4, 2e-3)}
+# scene: {dtype: (max rotation rad, median rotation rad, max position m,
+# energy rel)}. FP32 carries the strict frame tolerance; BF16 and FP16 about
+# four times the errors measured on the MI355X (the solve is deterministic,
+# so a change of these numbers is a change of the arithmetic). The 80x60
+# scene's BF16 rotation is the loosest: a node seen by a handful of surfels.
+BOUNDS = {
+    "tiny": {0: (1e-4, 1e-5, 1e-5, 1e-4), 1: (1e-2, 5e-5, 2.5e-5, 1e-4), 2: (6e-4, 1.2e-5, 6e-6, 2.5e-5)},
+    "c1": {0: (1e-4, 1e-5, 1e-5, 1e-4), 1: (5e-4, 1.6e-5, 1.5e-5, 1e-5), 2: (5e-5, 3e-6, 2.5e-6, 1e-5)},
+    "c2": {0: (1e-4, 1e-5, 1e-5, 1e-4), 1: (5e-4, 2.5e-5, 5e-6, 2.6e-5), 2: (6.5e-5, 3.5e-6, 1e-6, 2.5e-6)},
+}
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +46,7 @@ def test_jacobian_precision_against_the_oracle(swgn, scene_cache, name):
     _, own = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
                             keep=list(range(G)))
     res = {}
-    for dt in BOUNDS:
+    for dt in BOUNDS[name]:
         got, stats, maps = solve_with_maps(swgn, s, jac_dtype=dt)
         flips = map_flips(maps, own)
         want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params,
@@ -50,4 +59,4 @@ def test_jacobian_precision_against_the_oracle(swgn, scene_cache, name):
         print(f"{name} jac_dtype={dt}: rot max {ang.max():.3e} median {np.median(ang):.3e} rad, "
               f"pos max {dpos.max():.3e} m, energy {rel:.3e}; association flips per iteration {flips}")
     for dt, got in res.items():
-        assert all(g < b for g, b in zip(got, BOUNDS[dt])), (dt, got, BOUNDS[dt])
+        assert all(g < b for g, b in zip(got, BOUNDS[name][dt])), (dt, got, BOUNDS[name][dt])

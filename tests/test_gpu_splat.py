@@ -10,7 +10,8 @@ the point rule; batches and radius 0 are checked bit for bit."""
 import numpy as np
 import pytest
 
-from gpu_common import assert_maps_match_replica, gpu_lib, map_flips, se3_errors, solve_with_captures
+from gpu_common import (assert_maps_match_replica, assert_own_bounds, gpu_lib, map_flips, own_association_report,
+                        se3_errors, solve_with_captures)
 from oracle import replica32 as R32
 from oracle import solve as S
 
@@ -59,10 +60,17 @@ def test_splat_index_map_and_pairs_bit_exact(swgn, scene_cache, name):
     print(f"{name}: {k.size} pairs, surfels with 2+ pairs {(counts >= 2).sum()}, most {counts.max()}")
 
 
-# scene: (flips per iteration, max rad, median rad, max m, median m) against
-# the oracle's own splat association (the point rule's reasoning holds: a pair
-# whose FP32 and FP64 decisions differ moves a weakly held node)
-OWN_BOUNDS = {"c1": (12, 2e-3, 1e-5, 2e-4, 1e-6), "c2": (600, 5e-3, 2e-5, 5e-4, 2e-6)}
+# Against the oracle's own splat association the bound is much wider than
+# the point rule's, by the nature of the rule: discs of one surface overlap,
+# and a pixel near the line where two neighbouring discs' planes cross is a
+# near-tie of their hit depths, so live surfels that differ by FP32 rounding
+# hand many such pixels to the other disc ("flips": 0 at the identity state,
+# then ~0.2% of the pairs after one iteration, growing to 5-7% as the two
+# trajectories part). The association itself is checked bit for bit against
+# the replica at every iteration, and the arithmetic strictly on the GPU's
+# pairs; this bound only says the two trajectories stay close:
+#   (flip fraction, median rad, median m, p99 rad, p99 m, max rad, max m)
+OWN_SPLAT = (0.15, 3e-3, 2e-4, 2e-2, 1e-3, 5e-2, 2e-3)
 
 
 @pytest.fixture(scope="module", params=["c1", "c2"])
@@ -82,8 +90,8 @@ def test_splat_association_bit_exact_at_every_iteration(splat_case):
 
 
 def test_splat_frame_against_oracle(splat_case):
-    """The whole frame against the oracle's own splat association (bounded as
-    for the point rule), and strictly (1e-4 rad, 1e-5 m, energies 1e-4)
+    """The whole frame against the oracle's own splat association (within the
+    bound above), and strictly (1e-4 rad, 1e-5 m, energies 1e-4)
     against the oracle run on the GPU's pairs."""
     name, s, rad, got, stats, caps = splat_case
     G = s.params.gn_iters
@@ -91,13 +99,14 @@ def test_splat_frame_against_oracle(splat_case):
                                   linear="pcg", splat_radius=rad, keep=list(range(G)))
     flips = map_flips([c["C"] for c in caps], own)
     ang, dpos = se3_errors(got, own_se3, s.node_pos)
-    fb, amax, amed, pmax, pmed = OWN_BOUNDS[name]
-    print(f"{name} splats: flips per iteration {flips} of {own['n_corr']}; own association: rotation max "
-          f"{ang.max():.3e} median {np.median(ang):.3e} rad, position max {dpos.max():.3e} "
-          f"median {np.median(dpos):.3e} m")
-    assert max(flips) <= fb, flips
-    assert ang.max() < amax and np.median(ang) < amed, (ang.max(), np.median(ang))
-    assert dpos.max() < pmax and np.median(dpos) < pmed, (dpos.max(), np.median(dpos))
+    print(f"{name} splats: flips per iteration {flips} of {own['n_corr']}")
+    assert_own_bounds(own_association_report(flips, own["n_corr"], ang, dpos), OWN_SPLAT, f"{name} splats")
+    e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
+    e_own = np.array(own["e_data"]) + s.params.lambda_reg * np.array(own["e_reg"])
+    rel_own = np.abs(e_gpu - e_own) / e_own
+    print(f"{name} splats: energy against the own association, relative, per iteration "
+          f"{np.array2string(rel_own, precision=2)}")
+    assert rel_own.max() < 2e-2, rel_own
     want, tr = S.oracle_solve(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params, linear="pcg",
                               splat_radius=rad, corr_maps=[c["C"] for c in caps])
     ang, dpos = se3_errors(got, want, s.node_pos)
