@@ -143,9 +143,12 @@ def map_flips(maps, trace):
 # correspondences per iteration and moves nodes by a median 2.7e-5 rad, a
 # 99th percentile 3.0e-3 rad and at most 1.6e-2 rad (1.0e-3 m). The bound is
 # set at that scale: flips per iteration (as a fraction of the
-# correspondences), and the median, 99th percentile and worst node:
+# correspondences), and the median, 99th percentile and worst node. The
+# energies differ by what the flipped matches carry (a few tens of ~8k
+# matches of a converged frame: up to ~1e-3 relative):
 #   (flip fraction, median rad, median m, p99 rad, p99 m, max rad, max m)
 OWN_POINT = (0.01, 5e-5, 5e-6, 5e-3, 3e-4, 2e-2, 2e-3)
+OWN_ENERGY = 5e-3
 
 
 def own_association_report(flips, n_corr, ang, dpos):
@@ -187,7 +190,9 @@ def check_frame_against_oracle(scene, got, stats, caps, bounds=OWN_POINT, label=
     assert_own_bounds(own_association_report(flips, own["n_corr"], ang, dpos), bounds, label)
     e_gpu = np.array(stats["e_data"]) + p.lambda_reg * np.array(stats["e_reg"])
     e_own = np.array(own["e_data"]) + p.lambda_reg * np.array(own["e_reg"])
-    assert np.allclose(e_gpu, e_own, rtol=1e-4), np.max(np.abs(e_gpu - e_own) / e_own)
+    rel = np.abs(e_gpu - e_own) / e_own
+    print(f"{label}: energy against the own association, relative, max {rel.max():.2e}")
+    assert rel.max() < OWN_ENERGY, rel
     want, tr = S.oracle_solve(scene.cam, scene.surfel_pos, scene.surfel_nrm, scene.node_pos, scene.depth, p,
                               linear="pcg", corr_maps=[c["C"] for c in caps])
     ang, dpos = se3_errors(got, want, scene.node_pos)

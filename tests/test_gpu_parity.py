@@ -9,8 +9,9 @@ from FP32 arithmetic; node transforms after a whole frame within 1e-4 rad and
 import numpy as np
 import pytest
 
-from gpu_common import (OWN_POINT, assert_maps_match_replica, assert_own_bounds, expected_pattern, gpu_lib, map_flips,
-                        own_association_report, replica_maps, se3_errors, solve_with_captures, stream_for)
+from gpu_common import (OWN_ENERGY, OWN_POINT, assert_maps_match_replica, assert_own_bounds, expected_pattern,
+                        gpu_lib, map_flips, own_association_report, replica_maps, se3_errors, solve_with_captures,
+                        stream_for)
 from oracle import replica32 as R32
 from oracle import skin
 from oracle import solve as S
@@ -193,7 +194,9 @@ def test_frame_against_oracle_own_association(frame_case):
     assert_own_bounds(own_association_report(flips, own["n_corr"], ang, dpos), OWN_POINT, name)
     e_gpu = np.array(stats["e_data"]) + s.params.lambda_reg * np.array(stats["e_reg"])
     e_own = np.array(own["e_data"]) + s.params.lambda_reg * np.array(own["e_reg"])
-    assert np.allclose(e_gpu, e_own, rtol=1e-4)
+    rel = np.abs(e_gpu - e_own) / e_own
+    print(f"{name}: energy against the own association, relative, max {rel.max():.2e}")
+    assert rel.max() < OWN_ENERGY, rel
 
 
 def test_frame_arithmetic_on_the_gpu_association(frame_case):
