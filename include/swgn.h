@@ -190,6 +190,23 @@ sw_status sw_set_node_se3(sw_stream s, const float* node_se3, int32_t n, int32_t
 sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device,
                          sw_frame_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solve as sw_solve_frame, with the same results bit for bit, whose per-frame
+ * workspace (normal map, index map, Gram partials, blocks, PCG vectors,
+ * statistics) is taken from a static device array of 64 MiB held by the
+ * library on each GPU it runs on until the process ends, instead of the
+ * stream's own workspace. The call allocates nothing. Inputs and outputs
+ * are as for sw_solve_frame; the stream's resident state (surfels, nodes,
+ * graph) is its own as always. Returns SW_EINVAL if the stream's frame
+ * workspace (sw_get_footprint) exceeds 64 MiB, SW_EHIP if the array's
+ * device address cannot be found. Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (each call initialises what it
+ * reads): calls that overlap on one GPU (from several host threads or on
+ * several HIP streams at once) race and must not be made. Synchronous. */
+sw_status sw_solve_frame_noalloc(sw_stream s, const float* depth, int32_t on_device,
+                                 sw_frame_stats* stats);
+
 /* ---- surfel attributes and depth-map fusion (Sec. 5, Sec. 6.1, Sec. 6.4) ---- */
 
 /* Radius (m), confidence, last observed frame and initialisation frame of

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -817,6 +818,44 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
 }  // namespace rt
 }  // namespace swgn
 
+// The allocation-free solve (sw_solve_frame_noalloc) takes a frame's workspace
+// from a static array instead of the stream's own.
+namespace {
+
+// One array per GPU, held until the process ends; its size is the largest
+// frame workspace this entry point accepts.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch[kScratchDevices] = {};   // device address of each GPU's copy
+
+// The device address of `scratch` on the GPU that runs hip stream st, looked
+// up once per device with that device current (the host-side name is not a
+// device address).
+static sw_status scratch_on(hipStream_t st, std::string& err, char** out) {
+    int dev = -1;
+    if (hipStreamGetDevice(st, &dev) != hipSuccess || dev < 0 || dev >= kScratchDevices)
+        return fail(err, SW_EHIP, "cannot tell the device of the stream");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return fail(err, SW_EHIP, "hipGetDevice failed");
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return fail(err, SW_EHIP, "hipSetDevice failed");
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(err, SW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch[dev];
+    return SW_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sw_config_default(sw_config* c) {
@@ -976,6 +1015,44 @@ sw_status sw_solve_frame(sw_stream s, const float* depth, int32_t on_device, sw_
         std::vector<sw_stream> one{s};
         sw_status st1 = SW_OK;
         return solve_frames(s->exec, one, &depth, on_device, s->cfg.stage_timing != 0, stats, &st1);
+    });
+}
+
+// ---- the solve without allocation (the scratch array is defined above) ----
+
+sw_status sw_solve_frame_noalloc(sw_stream s, const float* depth, int32_t on_device, sw_frame_stats* stats) {
+    if (!s) return SW_EINVAL;
+    if (s->server) return fail(s->err, SW_ESTATE, "the stream is attached to a server");
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "surfels and node graph must be set before solving");
+    if (!depth) return fail(s->err, SW_EINVAL, "depth must not be NULL");
+    if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
+    if (s->ws_bytes > kScratchBytes)
+        return fail(s->err, SW_EINVAL, "the frame workspace (" + std::to_string(s->ws_bytes) +
+                                           " bytes) exceeds the static scratch (" + std::to_string(kScratchBytes) +
+                                           " bytes)");
+    char* base = nullptr;
+    if (scratch_on(s->exec.st, s->err, &base) != SW_OK) return SW_EHIP;
+    return guarded(s->err, [&]() -> sw_status {
+        // the frame's workspace carved from the scratch for this call; the
+        // stream's descriptor points back at its own workspace afterwards
+        const FrameDesc own = s->h;
+        carve_workspace(s->h, base);
+        publish_desc(s);
+        sw_status r = SW_OK;
+        try {
+            std::vector<sw_stream> one{s};
+            sw_status st1 = SW_OK;
+            r = solve_frames(s->exec, one, &depth, on_device, s->cfg.stage_timing != 0, stats, &st1);
+        } catch (...) {
+            (void)hipStreamSynchronize(s->exec.st);
+            s->h = own;
+            publish_desc(s);
+            throw;
+        }
+        SWGN_HIP(hipStreamSynchronize(s->exec.st));
+        s->h = own;
+        publish_desc(s);
+        return r;
     });
 }
 

@@ -119,7 +119,7 @@ def _close_open_handles():
 
 EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_stream",
            "sw_destroy_stream", "sw_set_reference_surfels", "sw_set_node_graph", "sw_set_node_se3",
-           "sw_solve_frame", "sw_get_node_se3", "sw_get_sizes", "sw_get_skinning",
+           "sw_solve_frame", "sw_solve_frame_noalloc", "sw_get_node_se3", "sw_get_sizes", "sw_get_skinning",
            "sw_get_node_graph", "sw_get_pattern", "sw_get_last_maps", "sw_get_last_live_normals",
            "sw_get_last_system",
            "sw_get_last_jacobian", "sw_create_batch", "sw_destroy_batch", "sw_batch_last_error",
@@ -157,6 +157,7 @@ def lib() -> C.CDLL:
         "sw_set_node_graph": (i32, [vp, i32, fp, fp, i32]),
         "sw_set_node_se3": (i32, [vp, fp, i32, i32]),
         "sw_solve_frame": (i32, [vp, fp, i32, C.POINTER(SwFrameStats)]),
+        "sw_solve_frame_noalloc": (i32, [vp, fp, i32, C.POINTER(SwFrameStats)]),
         "sw_get_node_se3": (i32, [vp, fp, i32]),
         "sw_get_sizes": (i32, [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
         "sw_get_skinning": (i32, [vp, ip, fp]),
@@ -271,6 +272,13 @@ def sw_solve_frame(h, depth, with_stats: bool = True):
     p, dev, ka = _ptr(depth, np.float32)
     stats = SwFrameStats()
     _check(h, lib().sw_solve_frame(h, p, dev, C.byref(stats) if with_stats else None))
+    return stats.as_dict() if with_stats else None
+
+
+def sw_solve_frame_noalloc(h, depth, with_stats: bool = True):
+    p, dev, ka = _ptr(depth, np.float32)
+    stats = SwFrameStats()
+    _check(h, lib().sw_solve_frame_noalloc(h, p, dev, C.byref(stats) if with_stats else None))
     return stats.as_dict() if with_stats else None
 
 
@@ -629,6 +637,9 @@ class Stream:
 
     def solve_frame(self, depth, with_stats: bool = True):
         return sw_solve_frame(self.h, depth, with_stats)
+
+    def solve_frame_noalloc(self, depth, with_stats: bool = True):
+        return sw_solve_frame_noalloc(self.h, depth, with_stats)
 
     def node_se3(self) -> np.ndarray:
         return sw_get_node_se3(self.h)
