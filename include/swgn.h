@@ -68,7 +68,9 @@ typedef struct sw_config {
                                   stable_conf) or recently observed ones (t_now - t_observed
                                   <= recent_frames); unsized points either way */
     float stable_conf;         /* delta_stable, 10 (Table 1) */
-    int32_t recent_frames;     /* delta_recent, 2 (Table 1) */
+    int32_t recent_frames;     /* delta_recent, 2 (Table 1); -1 = the recent clause off, only
+                                  stable surfels render (Sec. 7 adds the recent ones only in
+                                  the first frames and after a reinitialisation) */
     float fusion_dist;         /* depth fusion distance gate delta_distance, 0.001 m (Table 1) */
     float fusion_normal;       /* depth fusion normal gate delta_normal, 0.85 (Table 1) */
     float warp_eps;            /* intrinsic deformation bound epsilon of live skinning and of

@@ -57,9 +57,13 @@ def visible_surfels(conf: np.ndarray, t_observed: np.ndarray, t_now: int, stable
                     recent_frames: int) -> np.ndarray:
     """Sec. 7: only stable surfels (confidence > delta_stable) and surfels
     observed within the last delta_recent frames are rendered (FP32
-    confidence comparison)."""
+    confidence comparison). The paper adds the recent ones only in the first
+    frames and after a reinitialisation: recent_frames < 0 leaves them out."""
     c = np.asarray(conf, np.float32)
-    return (c > np.float32(stable_conf)) | (int(t_now) - np.asarray(t_observed, np.int64) <= int(recent_frames))
+    stable = c > np.float32(stable_conf)
+    if recent_frames < 0:
+        return stable
+    return stable | (int(t_now) - np.asarray(t_observed, np.int64) <= int(recent_frames))
 
 
 def make_problem(cam, surfel_pos, surfel_nrm, node_pos, depth, params,

@@ -211,7 +211,7 @@ sw_status check_config(const sw_config* c, std::string& why) {
     if (c->rigid_iters < 0 || c->rigid_iters > kMaxIters) { why = "rigid_iters must be in [0, 16]"; return SW_EINVAL; }
     if (c->visibility != 0 && c->visibility != 1) { why = "visibility must be 0 or 1"; return SW_EINVAL; }
     if (!finite(c->stable_conf)) { why = "stable_conf must be finite"; return SW_EINVAL; }
-    if (c->recent_frames < 0) { why = "recent_frames must be >= 0"; return SW_EINVAL; }
+    if (c->recent_frames < -1) { why = "recent_frames must be >= -1"; return SW_EINVAL; }
     if (!(finite(c->fusion_dist) && c->fusion_dist > 0)) { why = "fusion_dist must be > 0"; return SW_EINVAL; }
     if (!(finite(c->fusion_normal) && c->fusion_normal >= -1 && c->fusion_normal <= 1)) {
         why = "fusion_normal must be in [-1, 1]"; return SW_EINVAL;

@@ -149,7 +149,8 @@ struct FrameDesc {
 // Whether sorted surfel i is rendered into the solver's index map (Sec. 7:
 // stable surfels, or recently observed ones, when the stream asks for it).
 __device__ __forceinline__ bool visible(const FrameDesc& d, int i) {
-    return d.vis_mode == 0 || d.conf[i] > d.stable_conf || d.t_now - d.t_obs[i] <= d.recent;
+    // recent < 0: the recent clause is off (only stable surfels render)
+    return d.vis_mode == 0 || d.conf[i] > d.stable_conf || (d.recent >= 0 && d.t_now - d.t_obs[i] <= d.recent);
 }
 
 // Tiles (workgroups) of each per-frame stage for one stream.

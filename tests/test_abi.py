@@ -57,7 +57,7 @@ def test_defaults_and_status_strings():
     ("node_sigma", 0.0), ("corr_dist", 0.0), ("corr_normal", 1.5), ("edge_gate", -0.1),
     ("damping", float("nan")), ("jac_dtype", 7), ("debug_iter", -2), ("stage_timing", 2),
     ("rigid_iters", 17), ("rigid_iters", -1), ("visibility", 2), ("stable_conf", float("inf")),
-    ("recent_frames", -1), ("fusion_dist", 0.0), ("fusion_normal", 1.5),
+    ("recent_frames", -2), ("fusion_dist", 0.0), ("fusion_normal", 1.5),
     ("warp_eps", 0.0), ("warp_eps", 1.0), ("append_nn", -0.1), ("append_nn", float("nan")), ("t_low_confid", -1), ("splat", 2),
 ])
 def test_create_rejects_bad_config(field, value):

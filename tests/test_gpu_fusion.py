@@ -33,18 +33,18 @@ def _attributes(ns, seed):
     return rad, conf, tob
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
-def test_visibility_filter_maps_bit_exact(swgn, scene_cache, name):
+@pytest.mark.parametrize("name,recent", [("c1", 2), ("c2", 2), ("c1", -1)])
+def test_visibility_filter_maps_bit_exact(swgn, scene_cache, name, recent):
     s = scene_cache(name)
     ns = s.surfel_pos.shape[0]
     rad, conf, tob = _attributes(ns, 5)
-    st = stream_for(swgn, s, debug_iter=0, gn_iters=1, visibility=1, stable_conf=10.0, recent_frames=2)
+    st = stream_for(swgn, s, debug_iter=0, gn_iters=1, visibility=1, stable_conf=10.0, recent_frames=recent)
     st.set_surfel_attributes(rad, conf, tob)
     st.set_frame_time(9)
     st.solve_frame(s.depth)
     I, Cm, live, N = st.last_maps()
     st.close()
-    vis = S.visible_surfels(conf, tob, 9, 10.0, 2)
+    vis = S.visible_surfels(conf, tob, 9, 10.0, recent)
     assert 0 < vis.sum() < ns
     I_ref = R32.index_map(s.surfel_pos, s.cam, vis)     # identity state: live = reference exactly
     assert np.array_equal(I, I_ref)

@@ -232,6 +232,9 @@ def test_visibility_mask_removes_surfels_from_the_index_map(scene_cache):
     got = S.visible_surfels(np.float32([c for c, _, _ in cases]), np.array([t for _, t, _ in cases]), t_now=9,
                             stable_conf=10.0, recent_frames=2)
     assert got.tolist() == [v for _, _, v in cases]
+    settled = S.visible_surfels(np.float32([c for c, _, _ in cases]), np.array([t for _, t, _ in cases]), t_now=9,
+                                stable_conf=10.0, recent_frames=-1)
+    assert settled.tolist() == [False, True, False, False, False, True]     # stable ones only
     assert 0 < vis.sum() < ns
     R, t = Q.se3_to_rt(s.gt_se3.astype(np.float64))
     base = S.make_problem(s.cam, s.surfel_pos, s.surfel_nrm, s.node_pos, s.depth, s.params)
