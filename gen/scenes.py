@@ -337,6 +337,19 @@ def blend_motion(points: np.ndarray, node_pos: np.ndarray, se3: np.ndarray,
 # Rendering the deformed surface
 # ----------------------------------------------------------------------------
 
+def surface_grid(cam: Camera, prims: List, ss: int = 2):
+    """The reference surface sampled on an ss-times supersampled pixel grid
+    (ray depth, hit point, primitive id per sample): the mesh that
+    raster_deformed deforms. It depends on the camera and the scene only, so a
+    stream's frames share it."""
+    W2, H2 = cam.width * ss, cam.height * ss
+    gy, gx = np.mgrid[0:H2, 0:W2].astype(np.float64)
+    px = (gx + 0.5) / ss - 0.5
+    py = (gy + 0.5) / ss - 0.5
+    t, p, _, pid = ray_cast(cam, prims, px, py)
+    return dict(ss=ss, t=t, p=p, pid=pid)
+
+
 def render_deformed(cam: Camera, prims: List, node_pos: np.ndarray, se3: np.ndarray,
                     sigma: float, edge_gate: float, ss: int = 2,
                     max_edge_px: float = 3.0) -> np.ndarray:
@@ -345,11 +358,14 @@ def render_deformed(cam: Camera, prims: List, node_pos: np.ndarray, se3: np.ndar
     z-buffer rasterised at pixel centres. Triangles spanning a silhouette
     (vertices on different primitives or a depth jump above edge_gate) or whose
     projected edges exceed max_edge_px are dropped. Uncovered pixels are 0."""
+    return raster_deformed(cam, surface_grid(cam, prims, ss), node_pos, se3, sigma, edge_gate, max_edge_px)
+
+
+def raster_deformed(cam: Camera, grid: Dict, node_pos: np.ndarray, se3: np.ndarray,
+                    sigma: float, edge_gate: float, max_edge_px: float = 3.0) -> np.ndarray:
+    """render_deformed on a surface grid already sampled (surface_grid)."""
+    ss, t, p, pid = grid["ss"], grid["t"], grid["p"], grid["pid"]
     W2, H2 = cam.width * ss, cam.height * ss
-    gy, gx = np.mgrid[0:H2, 0:W2].astype(np.float64)
-    px = (gx + 0.5) / ss - 0.5
-    py = (gy + 0.5) / ss - 0.5
-    t, p, _, pid = ray_cast(cam, prims, px, py)
     hit = np.isfinite(t)
     verts = p.reshape(-1, 3)
     vhit = hit.ravel()
@@ -538,8 +554,44 @@ def scene_random(seed: int, size: Optional[Tuple[int, int]] = None,
     depth = add_sensor_noise(live, 0.0015, 0.05, rng)
     info = {"n_surfels": float(pos.shape[0]), "n_nodes": float(node_pos.shape[0]),
             "valid_depth": float(np.count_nonzero(depth)), "spacing": spacing}
+    info["prims"] = prims
     return Scene(f"random{seed}", seed, cam, params, pos, nrm, node_pos, gt, depth,
                  ref_depth, pix, info)
+
+
+def motion_walk(scene: Scene, n_frames: int, seed: int, max_deg: float = 2.0,
+                max_trans: float = 0.005) -> List[np.ndarray]:
+    """Ground truth of a stream's frames: frame 0 is the scene's, and frame f
+    is a fresh smoothed random step (rotation <= max_deg about each node's
+    live position, translation <= max_trans) composed after frame f - 1's.
+    Returns the (Nn,12) [R|t] of every frame."""
+    rng = np.random.default_rng(seed)
+    M = [scene.gt_se3.reshape(-1, 3, 4)]
+    p = scene.node_pos.astype(np.float64)
+    for _ in range(1, n_frames):
+        prev = M[-1]
+        live = np.einsum("nij,nj->ni", prev[:, :, :3], p) + prev[:, :, 3]
+        step = random_node_motion(live, max_deg, max_trans, rng).reshape(-1, 3, 4)
+        R = step[:, :, :3] @ prev[:, :, :3]
+        t = np.einsum("nij,nj->ni", step[:, :, :3], prev[:, :, 3]) + step[:, :, 3]
+        M.append(np.concatenate([R, t[:, :, None]], axis=2))
+    return [m.reshape(-1, 12) for m in M]
+
+
+def stream_frames(scene: Scene, n_frames: int, seed: int) -> List[np.ndarray]:
+    """Depth frames of a stream of the uneven-streams workload (a scene made by
+    scene_random): frame 0 is the scene's depth, frames 1.. render the walk of
+    motion_walk with the same sensor noise and dropout, each with its own
+    noise draw."""
+    prims = scene.info["prims"]
+    grid = surface_grid(scene.cam, prims)
+    rng = np.random.default_rng(seed + 7919)
+    out = [scene.depth]
+    for se3 in motion_walk(scene, n_frames, seed)[1:]:
+        live = raster_deformed(scene.cam, grid, scene.node_pos, se3, scene.params.node_sigma,
+                               scene.params.edge_gate)
+        out.append(add_sensor_noise(live, 0.0015, 0.05, rng))
+    return out
 
 
 SCENES = {"tiny": scene_tiny, "c1": scene_c1, "c2": scene_c2, "random": scene_random}

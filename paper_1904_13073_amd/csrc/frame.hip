@@ -244,9 +244,9 @@ __device__ __forceinline__ void jacobian_rows(const FrameDesc& d, int4 id, float
     const float wk[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const Q4 rk = q4(d.dq[2 * ids[k]]);
-        const Q4 dk = q4(d.dq[2 * ids[k] + 1]);
-        const float4 c4 = d.cl[ids[k]];
+        const Q4 rk = q4(gld4(d.dq + 2 * ids[k]));
+        const Q4 dk = q4(gld4(d.dq + 2 * ids[k] + 1));
+        const float4 c4 = gld4(d.cl + ids[k]);
         const float a = wk[k] * wp.sgn[k] * wp.inv_beta;
         const float3 h = vec_mul_conj_c(P, rk);
         const float3 g1 = vec_mul_conj_c(P, dk);
@@ -314,7 +314,7 @@ __device__ __forceinline__ void put_row(const FrameDesc& d, float* rows, int slo
                                         float (&Jw)[4][3], float (&Jt)[4][3], float r) {
     if (slot >= kCorrPack) return;
     float* row = &rows[slot * kRowPad];
-    const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
+    const int p4 = live ? (int)gld(d.pos4 + i) : (0 | (1 << 3) | (2 << 6) | (3 << 9));
     const int jd = d.jac_dtype;          // uniform: one branch for the whole row
     if (jd != 0) {
 #pragma unroll
@@ -360,8 +360,8 @@ __device__ __forceinline__ void tile_sums(const FrameDesc& d, float* rows, doubl
     if (threadIdx.x == 0) {
         int c = 0;
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
-        d.part_e[tile] = e;
-        d.part_n[tile] = c;
+        gst(d.part_e + tile, e);
+        gst(d.part_n + tile, c);
     }
 }
 
@@ -406,11 +406,11 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
                                               const unsigned long long* planes = nullptr, int base = 0) {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int comp = lane & 31, half = lane >> 5;
-    const int g0 = d.pack_seg[tile], g1 = d.pack_seg[tile + 1];
+    const int g0 = gld(d.pack_seg + tile), g1 = gld(d.pack_seg + tile + 1);
     float* sg = reinterpret_cast<float*>(stage);
     const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
-        int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
+        int s0 = gld(d.seg_start + seg) - p0, s1 = gld(d.seg_start + seg + 1) - p0;
         if (planes != nullptr) {
             s0 = min(max(extra_before(planes, s0) - base, 0), kCorrPack);
             s1 = min(max(extra_before(planes, s1) - base, 0), kCorrPack);
@@ -433,11 +433,12 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
         }
-        const uint32_t mask = d.seg_mask[seg];
+        const uint32_t mask = gld(d.seg_mask + seg);
         const int npr = __builtin_popcount(mask);
         const int size = 36 * npr + 32;
         const uint4 q0 = codes[0], q1 = codes[1];
         const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        // the whole output staged in LDS, then stored as whole float4 lines
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
@@ -450,14 +451,14 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
+        float4* out = reinterpret_cast<float4*>(d.part + gld(d.seg_off + seg));
         if (more != nullptr || planes != nullptr) {
             for (int q = lane; q < size / 4; q += kWave) {
-                const float4 a = out[q], c4 = stage[q];
-                out[q] = make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w);
+                const float4 a = gld4(out + q), c4 = stage[q];
+                gst4(out + q, make_float4(a.x + c4.x, a.y + c4.y, a.z + c4.z, a.w + c4.w));
             }
         } else {
-            for (int q = lane; q < size / 4; q += kWave) out[q] = stage[q];
+            for (int q = lane; q < size / 4; q += kWave) gst4(out + q, stage[q]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -491,7 +492,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     const Where at = locate(b);
     const FrameDesc& d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;
-    const int p0 = d.pack_start[at.tile], p1 = d.pack_start[at.tile + 1];
+    const int p0 = gld(d.pack_start + at.tile), p1 = gld(d.pack_start + at.tile + 1);
     const int i = p0 + (int)threadIdx.x;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const bool live = i < p1;
@@ -505,11 +506,11 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     // rows of unmatched lanes are formed once); lanes past the pack take its
     // last surfel and are masked, lanes that fail early read pixel 0
     const int ic = live ? i : p1 - 1;
-    const int4 id = d.idx[ic];
-    const int org = d.orig[ic];
-    const float4 w4 = d.w[ic];
-    const float3 v = make_float3(d.px[ic], d.py[ic], d.pz[ic]);
-    const float3 n = make_float3(d.nx[ic], d.ny[ic], d.nz[ic]);
+    const int4 id = gld4(d.idx + ic);
+    const int org = gld(d.orig + ic);
+    const float4 w4 = gld4(d.w + ic);
+    const float3 v = make_float3(gld(d.px + ic), gld(d.py + ic), gld(d.pz + ic));
+    const float3 n = make_float3(gld(d.nx + ic), gld(d.ny + ic), gld(d.nz + ic));
     const Warp wp = warp_surfel(id, w4, v, n, d.dq);
     int ux, uy;
     const bool in = project(d.cam, wp.v, ux, uy);
@@ -629,8 +630,8 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         return;
     }
     const int pix = ok ? uy * d.cam.W + ux : 0;
-    ok = ok & (d.zbuf[pix] == zkey(wp.v.z, org));   // (loaded beside the normal map)
-    const float4 nm = d.nmap[pix];
+    ok = ok & (gld(d.zbuf + pix) == zkey(wp.v.z, org));   // (loaded beside the normal map)
+    const float4 nm = gld4(d.nmap + pix);
     ok = ok & (nm.w > 0.f);
     const float3 V = backproject(d.cam, ux, uy, nm.w);
     const float3 dv = sub3(wp.v, V);
@@ -645,7 +646,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
         // the row: node block k at its node's position in the segment
         // (threads past the pack capacity are never live and keep no row)
         float* row = &rows[threadIdx.x * kRowPad];
-        const int p4 = live ? (int)d.pos4[i] : (0 | (1 << 3) | (2 << 6) | (3 << 9));
+        const int p4 = live ? (int)gld(d.pos4 + i) : (0 | (1 << 3) | (2 << 6) | (3 << 9));
         const int jd = d.jac_dtype;          // uniform: one branch for the whole row
         if (jd != 0) {
 #pragma unroll
@@ -690,8 +691,8 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     if (threadIdx.x == 0) {
         int c = 0;
         for (int q = 0; q < (int)(blockDim.x / kWave); ++q) c += shi[q];
-        d.part_e[at.tile] = e;
-        d.part_n[at.tile] = c;
+        gst(d.part_e + at.tile, e);
+        gst(d.part_n + at.tile, c);
     }
     if (capture) {
         // the wave's rows as whole 128-byte lines, two rows per store
@@ -703,55 +704,8 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
             if (rr < nrow) dst[rr * 32 + c] = c < 31 ? rows[(base + rr) * kRowPad + c] : 0.f;
         }
     }
-    // segment Gram matrices, one wave per segment. Accumulator element t of
-    // lane l is G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4.
-    const int comp = lane & 31, half = lane >> 5;
-    const int g0 = d.pack_seg[at.tile], g1 = d.pack_seg[at.tile + 1];
-    float* sg = reinterpret_cast<float*>(stage4[wave]);
-    const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
-    for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
-        const int s0 = d.seg_start[seg] - p0, s1 = d.seg_start[seg + 1] - p0;
-        f32x16 acc;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = 0.f;
-        for (int m0 = s0; m0 < s1; m0 += 16) {
-            float v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int sr = m0 + 2 * q + half;   // surfel of this half-wave
-                v[q] = sr < s1 ? rows[sr * kRowPad + comp] : 0.f;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
-        }
-        // output slot of each accumulator element: the rank of its node pair
-        // among the segment's pairs x 36 + position in the 6x6 sub-block;
-        // J^T r and r^T r after the sub-blocks. The whole output is staged in
-        // LDS and stored as whole lines.
-        const uint32_t mask = d.seg_mask[seg];
-        const int npair = __builtin_popcount(mask);
-        const int size = 36 * npair + 32;
-        const uint4 q0 = codes[0], q1 = codes[1];
-        const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-            const uint32_t bit = code & 15u, off = code >> 4;
-            const bool tail = bit == 15u;
-            const bool keep = code != 0xffffu && (tail || ((mask >> bit) & 1u));
-            const int sl = tail ? 36 * npair + (int)off
-                                : 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (int)off;
-            if (keep) sg[sl] = acc[t];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float4* out = reinterpret_cast<float4*>(d.part + d.seg_off[seg]);
-        for (int q = lane; q < size / 4; q += kWave) out[q] = stage4[wave][q];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    // segment Gram matrices, one wave per segment
+    segment_grams(d, rows, stage4[wave], at.tile, p0, nullptr);
 }
 
 // ---------------------------------------------------------------------------

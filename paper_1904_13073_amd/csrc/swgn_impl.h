@@ -31,6 +31,50 @@
 
 namespace swgn {
 
+// ---------------------------------------------------------------------------
+// Global-memory accesses through a descriptor's pointers. Those pointers are
+// generic, so a plain access compiles to a flat instruction, which counts
+// against the LDS counter as well: every later LDS access or cross-lane
+// shuffle (ds_bpermute) would then wait for the memory access to complete.
+// These compile to global instructions, which only the memory counter tracks.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    typedef __attribute__((address_space(1))) const T GT;
+    return *(GT*)(p);
+}
+// (HIP's vector types cannot be copied out of another address space: a
+// float2 is loaded as one 64-bit word)
+__device__ __forceinline__ float2 gld2(const float2* p) {
+    typedef __attribute__((address_space(1))) const unsigned long long GU;
+    const unsigned long long w = *(GU*)(p);
+    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    typedef __attribute__((address_space(1))) T GT;
+    *(GT*)(p) = v;
+}
+typedef float f32x4n __attribute__((ext_vector_type(4)));
+typedef int i32x4n __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gld4(const float4* p) {
+    typedef __attribute__((address_space(1))) const f32x4n G;
+    const f32x4n v = *(G*)(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int4 gld4(const int4* p) {
+    typedef __attribute__((address_space(1))) const i32x4n G;
+    const i32x4n v = *(G*)(p);
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst4(float4* p, float4 v) {
+    typedef __attribute__((address_space(1))) f32x4n G;
+    f32x4n w;
+    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+    *(G*)(p) = w;
+}
+
+
 constexpr int kWave = 64;
 constexpr uint32_t kTransposed = 0x80000000u;
 constexpr float kBlendEps = 1e-12f;
@@ -113,12 +157,12 @@ __device__ __forceinline__ Warp warp_surfel(int4 idx, float4 w, float3 v, float3
     Warp out;
     const int id[4] = {idx.x, idx.y, idx.z, idx.w};
     const float wk[4] = {w.x, w.y, w.z, w.w};
-    Q4 r0 = q4(dq[2 * id[0]]);
+    Q4 r0 = q4(gld4(dq + 2 * id[0]));
     Q4 br = {0.f, 0.f, 0.f, 0.f}, bd = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Q4 rk = q4(dq[2 * id[k]]);
-        Q4 dk = q4(dq[2 * id[k] + 1]);
+        Q4 rk = q4(gld4(dq + 2 * id[k]));
+        Q4 dk = q4(gld4(dq + 2 * id[k] + 1));
         float dt = ((r0.w * rk.w + r0.x * rk.x) + r0.y * rk.y) + r0.z * rk.z;
         float s = dt >= 0.f ? 1.f : -1.f;
         out.sgn[k] = s;
@@ -169,9 +213,9 @@ __device__ __forceinline__ void node_tables(float4 p, Q4 r, float3 t, float4* dq
     float3 u = make_float3(r.x, r.y, r.z);
     float3 c = add3(qrot(r.w, u, make_float3(p.x, p.y, p.z)), t);
     Q4 d = qmul(Q4{0.f, t.x, t.y, t.z}, r);
-    dq[2 * k] = f4(r);
-    dq[2 * k + 1] = make_float4(0.5f * d.w, 0.5f * d.x, 0.5f * d.y, 0.5f * d.z);
-    cl[k] = make_float4(c.x, c.y, c.z, 0.f);
+    gst4(dq + 2 * k, f4(r));
+    gst4(dq + 2 * k + 1, make_float4(0.5f * d.w, 0.5f * d.x, 0.5f * d.y, 0.5f * d.z));
+    gst4(cl + k, make_float4(c.x, c.y, c.z, 0.f));
 }
 
 // Per Gauss-Newton iteration statistics written by the device.

@@ -337,10 +337,10 @@ class Batch:
             sw_destroy_batch(self.h)
             self.h = None
 
-    def __del__(self):
-        if _no_more_calls():
-            return
+    def __del__(self, _stop=_no_more_calls):
         try:
+            if _stop():
+                return
             self.close()
         except Exception:
             pass
@@ -397,10 +397,10 @@ class Server:
             self.h = None
             self._keep.clear()
 
-    def __del__(self):
-        if _no_more_calls():
-            return
+    def __del__(self, _stop=_no_more_calls):
         try:
+            if _stop():
+                return
             self.close()
         except Exception:
             pass
@@ -618,10 +618,10 @@ class Stream:
             sw_destroy_stream(self.h)
             self.h = None
 
-    def __del__(self):
-        if _no_more_calls():
-            return
+    def __del__(self, _stop=_no_more_calls):
         try:
+            if _stop():
+                return
             self.close()
         except Exception:
             pass
