@@ -82,6 +82,7 @@ __device__ __forceinline__ float max_eig_sym3(float m00, float m01, float m02, f
 
 __global__ void __launch_bounds__(256) k_append_eval(AppendArgs a) {
     __shared__ float4 tile[kAppendTile];
+    __shared__ int tid[kAppendTile];
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const int npx = a.cam.W * a.cam.H;
     const bool in = u < npx;
@@ -95,16 +96,23 @@ __global__ void __launch_bounds__(256) k_append_eval(AppendArgs a) {
     for (int base = 0; base < a.nn; base += kAppendTile) {
         const int cnt = min(kAppendTile, a.nn - base);
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = a.cl[base + t];
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            tile[t] = a.cl[base + t];
+            tid[t] = a.node_id[base + t];
+        }
         __syncthreads();
         if (cand) {
             for (int t = 0; t < cnt; ++t) {
                 const float4 c = tile[t];
                 const float dx = V.x - c.x, dy = V.y - c.y, dz = V.z - c.z;
-                knn_insert<4>(kd, ki, (dx * dx + dy * dy) + dz * dz, base + t);
+                knn_insert_lex<4>(kd, ki, (dx * dx + dy * dy) + dz * dz, tid[t]);
             }
         }
     }
+    // the nearest set, found in the caller's node numbering (ties to the
+    // lower caller index), back in the library's
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ki[k] = cand ? a.node_inv[ki[k]] : 0;
     bool far = false, comp = false;
     float3 vr = make_float3(0.f, 0.f, 0.f), nr = make_float3(0.f, 0.f, 0.f);
     if (cand) {

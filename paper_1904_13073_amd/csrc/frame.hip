@@ -1078,6 +1078,11 @@ __global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_map_ids(int* __restrict__ p, int n, const int* __restrict__ map) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = map[p[i]];
+}
+
 __global__ void k_tables_from_state(int nn, const float4* __restrict__ pref, const float4* __restrict__ rq,
                                     const float4* __restrict__ tt, float4* __restrict__ dq, float4* __restrict__ cl) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1088,6 +1093,10 @@ __global__ void k_tables_from_state(int nn, const float4* __restrict__ pref, con
 
 void launch_fill_i32(int* p, int n, int v, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+}
+
+void launch_map_ids(int* p, int n, const int* map, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_map_ids, dim3((n + 255) / 256), dim3(256), 0, st, p, n, map);
 }
 
 void launch_tables_from_state(int nn, const float4* pref, const float4* rq, const float4* tt, float4* dq, float4* cl,

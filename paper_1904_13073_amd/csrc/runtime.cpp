@@ -99,7 +99,11 @@ int Executor::variant_of(int stage, int64_t rows) const {
                       (stage == kStUpdate && rows >= 256 * 2 * 2 * kSolveNodes);
     // fused PCG steps while the product launch is too small to fill the chip
     const bool fused = stage == kStSpmv && rows <= kFusedRows;
-    return (wide ? kVarWide : 0) | (fused ? kVarFused : 0);
+    // the PCG's tiles XCD-contiguous: with nodes in spatial order, an XCD's
+    // rows then share their columns (measured: a faster fused step; the fold
+    // and the initialisation were slower so)
+    const bool xcd = stage == kStSpmv || stage == kStUpdate || stage == kStPcgStep;
+    return (wide ? kVarWide : 0) | (fused ? kVarFused : 0) | (xcd ? kVarXcd : 0);
 }
 
 // Shape bucket of a batch: the stream count and the powers of two of its total
@@ -314,8 +318,47 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* s
     s->nent = (int64_t)L.ent_sub.size();
 }
 
+// The library's node order: ascending Morton code of the reference positions
+// (10 bits per axis over their bounding box), ties by the caller's index.
+// Consecutive nodes are then near each other, and so are a block row's
+// columns (its graph neighbours and the nodes sharing its surfels).
+static std::vector<int> morton_order(const std::vector<float>& pos, int nn) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < nn; ++k)
+        for (int a = 0; a < 3; ++a) {
+            const float v = pos[3 * k + a];
+            if (std::isfinite(v)) { lo[a] = std::min(lo[a], v); hi[a] = std::max(hi[a], v); }
+        }
+    auto spread = [](uint32_t v) {      // 10 bits -> every third bit
+        v &= 1023u;
+        v = (v | (v << 16)) & 0x030000FFu;
+        v = (v | (v << 8)) & 0x0300F00Fu;
+        v = (v | (v << 4)) & 0x030C30C3u;
+        v = (v | (v << 2)) & 0x09249249u;
+        return v;
+    };
+    std::vector<std::pair<uint32_t, int>> key((size_t)nn);
+    for (int k = 0; k < nn; ++k) {
+        uint32_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            const float ext = hi[a] - lo[a];
+            const float v = pos[3 * k + a];
+            const float t = (ext > 0.f && std::isfinite(v)) ? (v - lo[a]) / ext : 0.f;
+            q[a] = (uint32_t)std::min(1023.f, std::max(0.f, t * 1023.f));
+        }
+        key[(size_t)k] = {spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), k};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> perm((size_t)nn);
+    for (int k = 0; k < nn; ++k) perm[(size_t)k] = key[(size_t)k].second;
+    return perm;
+}
+
+// keep_order: node_pos is in the library's order and the numbering stays (a
+// rebuild after a geometry update; the node state keep_rq / keep_tt is in
+// that order too).
 void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_se3, int32_t on_device,
-                 const float4* keep_rq, const float4* keep_tt) {
+                 const float4* keep_rq, const float4* keep_tt, bool keep_order) {
     hipStream_t st = s->exec.st;
     s->graph_mem.release();
     s->ws_mem.release();
@@ -348,11 +391,42 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     s->fz4 = nullptr;
     s->fused = false;
 
-    // nodes
+    // nodes: positions in the caller's order on the host, the library's order
+    std::vector<float> hin(3 * (size_t)nn), hcall(3 * (size_t)nn), hlib(3 * (size_t)nn);
+    if (on_device) {
+        SWGN_HIP(hipMemcpyAsync(hin.data(), node_pos, sizeof(float) * 3 * nn, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(hin.data(), node_pos, sizeof(float) * 3 * nn);
+    }
+    if (!keep_order) s->node_perm = morton_order(hin, nn);
+    const std::vector<int>& perm = s->node_perm;
+    s->node_inv.assign((size_t)nn, 0);
+    for (int k = 0; k < nn; ++k) s->node_inv[(size_t)perm[k]] = k;
+    for (int k = 0; k < nn; ++k)
+        for (int a = 0; a < 3; ++a) {
+            if (keep_order) {
+                hlib[3 * k + a] = hin[3 * k + a];
+                hcall[3 * (size_t)perm[k] + a] = hin[3 * k + a];
+            } else {
+                hcall[3 * k + a] = hin[3 * k + a];
+                hlib[3 * k + a] = hin[3 * (size_t)perm[k] + a];
+            }
+        }
+    int* d_id = G.alloc<int>(nn);
+    int* d_inv = G.alloc<int>(nn);
+    SWGN_HIP(hipMemcpyAsync(d_id, perm.data(), sizeof(int) * nn, hipMemcpyHostToDevice, st));
+    SWGN_HIP(hipMemcpyAsync(d_inv, s->node_inv.data(), sizeof(int) * nn, hipMemcpyHostToDevice, st));
+    s->d_node_id = d_id;
+    s->d_node_inv = d_inv;
     float* pos_in = tmp.alloc<float>(3 * (size_t)nn);
-    copy_in(pos_in, node_pos, sizeof(float) * 3 * nn, on_device, st);
+    SWGN_HIP(hipMemcpyAsync(pos_in, hlib.data(), sizeof(float) * 3 * nn, hipMemcpyHostToDevice, st));
     float4* pref = G.alloc<float4>(nn);
     launch_positions_to_f4(nn, pos_in, pref, st);
+    float* pos_call = tmp.alloc<float>(3 * (size_t)nn);
+    SWGN_HIP(hipMemcpyAsync(pos_call, hcall.data(), sizeof(float) * 3 * nn, hipMemcpyHostToDevice, st));
+    float4* pcall = tmp.alloc<float4>(nn);
+    launch_positions_to_f4(nn, pos_call, pcall, st);
     h.pref = pref;
     h.rq = G.alloc<float4>(nn);
     h.tt = G.alloc<float4>(nn);
@@ -360,8 +434,18 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.cl = G.alloc<float4>(nn);
     float* se3_in = nullptr;
     if (node_se3) {
+        std::vector<float> hse((size_t)12 * nn), hsl((size_t)12 * nn);
+        if (on_device) {
+            SWGN_HIP(hipMemcpyAsync(hse.data(), node_se3, sizeof(float) * 12 * nn, hipMemcpyDeviceToHost, st));
+            SWGN_HIP(hipStreamSynchronize(st));
+        } else {
+            std::memcpy(hse.data(), node_se3, sizeof(float) * 12 * nn);
+        }
+        for (int k = 0; k < nn; ++k)
+            std::memcpy(&hsl[12 * (size_t)k], &hse[12 * (size_t)perm[k]], 12 * sizeof(float));
         se3_in = tmp.alloc<float>(12 * (size_t)nn);
-        copy_in(se3_in, node_se3, sizeof(float) * 12 * nn, on_device, st);
+        SWGN_HIP(hipMemcpyAsync(se3_in, hsl.data(), sizeof(float) * 12 * nn, hipMemcpyHostToDevice, st));
+        SWGN_HIP(hipStreamSynchronize(st));                  // (the host copy goes out of scope)
     }
     if (keep_rq) {
         // the node state as it is (a rebuild after a geometry update)
@@ -372,13 +456,25 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
         launch_nodes_from_se3(nn, se3_in, pref, h.rq, h.tt, h.dq, h.cl, st);
     }
 
-    // skinning and node graph
+    // skinning and node graph, searched in the caller's node order (so that
+    // equal distances go to the lower caller index), then renumbered
     int4* idx_in = tmp.alloc<int4>(ns);
     float4* w_in = tmp.alloc<float4>(ns);
     const float sig = s->cfg.node_sigma;
-    launch_knn_skin(ns, s->in_pos, nn, pref, 1.0f / (2.0f * sig * sig), idx_in, w_in, st);
+    launch_knn_skin(ns, s->in_pos, nn, pcall, 1.0f / (2.0f * sig * sig), idx_in, w_in, st);
+    launch_map_ids(reinterpret_cast<int*>(idx_in), 4 * ns, d_inv, st);
+    int* nbr_call = tmp.alloc<int>(8 * (size_t)nn);
+    launch_node_graph(nn, pcall, nbr_call, st);
     int* nbr = G.alloc<int>(8 * (size_t)nn);
-    launch_node_graph(nn, pref, nbr, st);
+    {
+        std::vector<int> hn((size_t)8 * nn), hl((size_t)8 * nn);
+        SWGN_HIP(hipMemcpyAsync(hn.data(), nbr_call, sizeof(int) * 8 * nn, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < nn; ++k)
+            for (int q = 0; q < 8; ++q) hl[8 * (size_t)k + q] = s->node_inv[(size_t)hn[8 * (size_t)perm[k] + q]];
+        SWGN_HIP(hipMemcpyAsync(nbr, hl.data(), sizeof(int) * 8 * nn, hipMemcpyHostToDevice, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+    }
     h.nbr = nbr;
 
     // order surfels by node set
@@ -818,6 +914,45 @@ sw_status solve_frames(Executor& ex, const std::vector<sw_stream>& ss, const flo
 }  // namespace rt
 }  // namespace swgn
 
+// The upper block pattern in the caller's node order (the library keeps its
+// own): row_ptr / col_idx as for the library's, and for each caller block the
+// library block it comes from and whether the two orders transpose it.
+struct CallerPattern {
+    std::vector<int> row_ptr, col_idx, src;
+    std::vector<char> transposed;
+};
+
+static CallerPattern caller_pattern(sw_stream s) {
+    const int nn = s->h.nn, nb = s->h.nb;
+    std::vector<int> rp(nn + 1), ci(nb);
+    hipStream_t st = s->exec.st;
+    SWGN_HIP(hipMemcpyAsync(rp.data(), s->h.row_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(ci.data(), s->h.col_idx, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipStreamSynchronize(st));
+    const std::vector<int>& pm = s->node_perm;
+    struct Ent { int a, b, src; char tr; };
+    std::vector<Ent> e((size_t)nb);
+    for (int k = 0; k < nn; ++k)
+        for (int q = rp[k]; q < rp[k + 1]; ++q) {
+            const int A = pm[k], B = pm[ci[q]];
+            e[(size_t)q] = A <= B ? Ent{A, B, q, 0} : Ent{B, A, q, 1};
+        }
+    std::sort(e.begin(), e.end(), [](const Ent& x, const Ent& y) { return x.a < y.a || (x.a == y.a && x.b < y.b); });
+    CallerPattern out;
+    out.row_ptr.assign(nn + 1, 0);
+    out.col_idx.resize(nb);
+    out.src.resize(nb);
+    out.transposed.resize(nb);
+    for (int q = 0; q < nb; ++q) {
+        ++out.row_ptr[e[(size_t)q].a + 1];
+        out.col_idx[q] = e[(size_t)q].b;
+        out.src[q] = e[(size_t)q].src;
+        out.transposed[q] = e[(size_t)q].tr;
+    }
+    for (int k = 0; k < nn; ++k) out.row_ptr[k + 1] += out.row_ptr[k];
+    return out;
+}
+
 // The allocation-free solve (sw_solve_frame_noalloc) takes a frame's workspace
 // from a static array instead of the stream's own.
 namespace {
@@ -982,7 +1117,7 @@ sw_status sw_set_node_graph(sw_stream s, int32_t n_nodes, const float* node_pos,
     if (!node_pos) return fail(s->err, SW_EINVAL, "node positions must not be NULL");
     if (on_device != 0 && on_device != 1) return fail(s->err, SW_EINVAL, "on_device must be 0 or 1");
     return guarded(s->err, [&]() -> sw_status {
-        build_graph(s, n_nodes, node_pos, node_se3, on_device, nullptr, nullptr);
+        build_graph(s, n_nodes, node_pos, node_se3, on_device, nullptr, nullptr, false);
         return SW_OK;
     });
 }
@@ -997,7 +1132,16 @@ sw_status sw_set_node_se3(sw_stream s, const float* node_se3, int32_t n, int32_t
         Arena tmp;
         float* d = tmp.alloc<float>(12 * (size_t)n);
         const FrameDesc& h = s->h;
-        copy_in(d, node_se3, sizeof(float) * 12 * n, on_device, s->exec.st);
+        std::vector<float> in((size_t)12 * n), lib((size_t)12 * n);
+        if (on_device) {
+            SWGN_HIP(hipMemcpyAsync(in.data(), node_se3, sizeof(float) * 12 * n, hipMemcpyDeviceToHost, s->exec.st));
+            SWGN_HIP(hipStreamSynchronize(s->exec.st));
+        } else {
+            std::memcpy(in.data(), node_se3, sizeof(float) * 12 * n);
+        }
+        for (int k = 0; k < n; ++k)             // into the library's node order
+            std::memcpy(&lib[12 * (size_t)k], &in[12 * (size_t)s->node_perm[k]], 12 * sizeof(float));
+        SWGN_HIP(hipMemcpyAsync(d, lib.data(), sizeof(float) * 12 * n, hipMemcpyHostToDevice, s->exec.st));
         launch_nodes_from_se3(n, d, h.pref, h.rq, h.tt, h.dq, h.cl, s->exec.st);
         SWGN_HIP(hipGetLastError());
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
@@ -1066,8 +1210,11 @@ sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity) {
         const int nn = s->h.nn;
         float* d = tmp.alloc<float>(12 * (size_t)nn);
         launch_node_se3_out(nn, s->h.rq, s->h.tt, d, s->exec.st);
-        SWGN_HIP(hipMemcpyAsync(out, d, sizeof(float) * 12 * nn, hipMemcpyDeviceToHost, s->exec.st));
+        std::vector<float> lib((size_t)12 * nn);
+        SWGN_HIP(hipMemcpyAsync(lib.data(), d, sizeof(float) * 12 * nn, hipMemcpyDeviceToHost, s->exec.st));
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
+        for (int k = 0; k < nn; ++k)            // back to the caller's node order
+            std::memcpy(out + 12 * (size_t)s->node_perm[k], &lib[12 * (size_t)k], 12 * sizeof(float));
         return SW_OK;
     });
 }
@@ -1274,6 +1421,8 @@ void run_append(sw_stream s, int32_t max_out, int32_t* pixel, float* pos, float*
     a.match = s->fmatch;
     a.cl = h.cl;
     a.pref = h.pref;
+    a.node_id = s->d_node_id;
+    a.node_inv = s->d_node_inv;
     a.dq = h.dq;
     a.flag = s->aflag;
     a.sv = s->asv;
@@ -1391,7 +1540,7 @@ sw_status sw_update_geometry(sw_stream s, sw_geometry_stats* stats) {
         s->ns = nnew;
         s->in_pos = c.dpos; s->in_nrm = c.dnrm; s->in_rad = c.drad; s->in_conf = c.dconf;
         s->in_tobs = c.dtobs; s->in_tinit = c.dtinit;
-        build_graph(s, nn, np3, nullptr, 1, rq, tt);
+        build_graph(s, nn, np3, nullptr, 1, rq, tt, true);
         SWGN_HIP(hipStreamSynchronize(st));
         if (stats) {
             stats->n_removed = ns - nkeep;
@@ -1414,9 +1563,10 @@ sw_status sw_get_live_nodes(sw_stream s, float* pos) {
         SWGN_HIP(hipMemcpyAsync(c.data(), s->h.cl, sizeof(float4) * nn, hipMemcpyDeviceToHost, st));
         SWGN_HIP(hipStreamSynchronize(st));
         for (int k = 0; k < nn; ++k) {
-            pos[3 * k + 0] = c[k].x;
-            pos[3 * k + 1] = c[k].y;
-            pos[3 * k + 2] = c[k].z;
+            const size_t o = (size_t)s->node_perm[k];
+            pos[3 * o + 0] = c[k].x;
+            pos[3 * o + 1] = c[k].y;
+            pos[3 * o + 2] = c[k].z;
         }
         return SW_OK;
     });
@@ -1467,7 +1617,11 @@ sw_status sw_get_skinning(sw_stream s, int32_t* idx4, float* w4) {
         SWGN_HIP(hipStreamSynchronize(st));
         for (size_t i = 0; i < ns; ++i) {
             const size_t o = (size_t)orig[i];
-            if (idx4) { idx4[4 * o] = idx[i].x; idx4[4 * o + 1] = idx[i].y; idx4[4 * o + 2] = idx[i].z; idx4[4 * o + 3] = idx[i].w; }
+            if (idx4) {
+                const std::vector<int>& pm = s->node_perm;
+                idx4[4 * o] = pm[idx[i].x]; idx4[4 * o + 1] = pm[idx[i].y];
+                idx4[4 * o + 2] = pm[idx[i].z]; idx4[4 * o + 3] = pm[idx[i].w];
+            }
             if (w4) { w4[4 * o] = w[i].x; w4[4 * o + 1] = w[i].y; w4[4 * o + 2] = w[i].z; w4[4 * o + 3] = w[i].w; }
         }
         return SW_OK;
@@ -1479,8 +1633,13 @@ sw_status sw_get_node_graph(sw_stream s, int32_t* nbr8) {
     if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
     if (!nbr8) return fail(s->err, SW_EINVAL, "NULL output");
     return guarded(s->err, [&]() -> sw_status {
-        SWGN_HIP(hipMemcpyAsync(nbr8, s->h.nbr, sizeof(int) * 8 * s->h.nn, hipMemcpyDeviceToHost, s->exec.st));
+        const int nn = s->h.nn;
+        std::vector<int> lib((size_t)8 * nn);
+        SWGN_HIP(hipMemcpyAsync(lib.data(), s->h.nbr, sizeof(int) * 8 * nn, hipMemcpyDeviceToHost, s->exec.st));
         SWGN_HIP(hipStreamSynchronize(s->exec.st));
+        const std::vector<int>& pm = s->node_perm;
+        for (int k = 0; k < nn; ++k)
+            for (int q = 0; q < 8; ++q) nbr8[8 * (size_t)pm[k] + q] = pm[lib[8 * (size_t)k + q]];
         return SW_OK;
     });
 }
@@ -1489,10 +1648,9 @@ sw_status sw_get_pattern(sw_stream s, int32_t* row_ptr, int32_t* col_idx) {
     if (!s) return SW_EINVAL;
     if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
     return guarded(s->err, [&]() -> sw_status {
-        hipStream_t st = s->exec.st;
-        if (row_ptr) SWGN_HIP(hipMemcpyAsync(row_ptr, s->h.row_ptr, sizeof(int) * (s->h.nn + 1), hipMemcpyDeviceToHost, st));
-        if (col_idx) SWGN_HIP(hipMemcpyAsync(col_idx, s->h.col_idx, sizeof(int) * s->h.nb, hipMemcpyDeviceToHost, st));
-        SWGN_HIP(hipStreamSynchronize(st));
+        const CallerPattern cp = caller_pattern(s);
+        if (row_ptr) std::memcpy(row_ptr, cp.row_ptr.data(), sizeof(int) * cp.row_ptr.size());
+        if (col_idx) std::memcpy(col_idx, cp.col_idx.data(), sizeof(int) * cp.col_idx.size());
         return SW_OK;
     });
 }
@@ -1545,10 +1703,28 @@ sw_status sw_get_last_system(sw_stream s, float* blocks, float* g, float* delta)
     if (!s->graph_set || !s->captured) return fail(s->err, SW_ESTATE, "no captured iteration");
     return guarded(s->err, [&]() -> sw_status {
         hipStream_t st = s->exec.st;
-        if (blocks) SWGN_HIP(hipMemcpyAsync(blocks, s->dbg_H, sizeof(float) * 36 * s->h.nb, hipMemcpyDeviceToHost, st));
-        if (g) SWGN_HIP(hipMemcpyAsync(g, s->dbg_g, sizeof(float) * 6 * s->h.nn, hipMemcpyDeviceToHost, st));
-        if (delta) SWGN_HIP(hipMemcpyAsync(delta, s->dbg_x, sizeof(float) * 6 * s->h.nn, hipMemcpyDeviceToHost, st));
+        const int nn = s->h.nn, nb = s->h.nb;
+        std::vector<float> hb((size_t)36 * nb), hg((size_t)6 * nn), hx((size_t)6 * nn);
+        SWGN_HIP(hipMemcpyAsync(hb.data(), s->dbg_H, sizeof(float) * 36 * nb, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(hg.data(), s->dbg_g, sizeof(float) * 6 * nn, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(hx.data(), s->dbg_x, sizeof(float) * 6 * nn, hipMemcpyDeviceToHost, st));
         SWGN_HIP(hipStreamSynchronize(st));
+        // the caller's node order: node rows permuted, each upper block taken
+        // from its library block, transposed where the two orders disagree
+        const std::vector<int>& pm = s->node_perm;
+        if (blocks) {
+            const CallerPattern cp = caller_pattern(s);
+            for (size_t b = 0; b < cp.src.size(); ++b) {
+                const float* m = &hb[36 * (size_t)cp.src[b]];
+                float* o = blocks + 36 * b;
+                for (int r = 0; r < 6; ++r)
+                    for (int c = 0; c < 6; ++c) o[6 * r + c] = cp.transposed[b] ? m[6 * c + r] : m[6 * r + c];
+            }
+        }
+        for (int k = 0; k < nn; ++k) {
+            if (g) std::memcpy(g + 6 * (size_t)pm[k], &hg[6 * (size_t)k], 6 * sizeof(float));
+            if (delta) std::memcpy(delta + 6 * (size_t)pm[k], &hx[6 * (size_t)k], 6 * sizeof(float));
+        }
         return SW_OK;
     });
 }

@@ -157,6 +157,14 @@ struct sw_stream_s {
     int nsets = 0;                        // distinct node sets
     int64_t nent = 0;                     // block-fold entries
 
+    // node numbering: the library keeps nodes in a spatially local order
+    // (Morton order of their reference positions), so that a block row's
+    // columns lie near it; every export is in the caller's order
+    std::vector<int> node_perm;           // library index k -> caller index
+    std::vector<int> node_inv;            // caller index -> library index
+    int* d_node_id = nullptr;             // [nn] node_perm on the device
+    int* d_node_inv = nullptr;            // [nn] node_inv on the device
+
     // captured iteration (allocated only when the config asks for a capture)
     int* dbg_index = nullptr;
     float *dbg_H = nullptr, *dbg_g = nullptr, *dbg_x = nullptr, *dbg_J = nullptr;

@@ -53,6 +53,8 @@ struct AppendArgs {
     const float4* cl;             // live node positions
     const float4* pref;           // reference node positions
     const float4* dq;             // node dual quaternions
+    const int* node_id;           // [nn] the caller's index of each node (ties go to the lower)
+    const int* node_inv;          // [nn] the library's index of each caller index
     int* flag;                    // [npx + 1] survivor flags (the last stays 0)
     float4 *sv, *sn;              // [npx] reference position / normal of survivors
     int* counts;                  // [0] candidates, [1] far, [2] compressive

@@ -140,6 +140,24 @@ __device__ __forceinline__ void knn_insert(float (&kd)[K], int (&ki)[K], float k
     ki[p] = j;
 }
 
+// Insert (key, j) into the K-nearest list ascending in (key, j), whatever the
+// order the candidates come in.
+template <int K>
+__device__ __forceinline__ void knn_insert_lex(float (&kd)[K], int (&ki)[K], float key, int j) {
+    if (!(key < kd[K - 1] || (key == kd[K - 1] && j < ki[K - 1]))) return;
+    int p = K - 1;
+#pragma unroll
+    for (int q = K - 1; q > 0; --q) {
+        if (key < kd[q - 1] || (key == kd[q - 1] && j < ki[q - 1])) {
+            kd[q] = kd[q - 1];
+            ki[q] = ki[q - 1];
+            p = q - 1;
+        }
+    }
+    kd[p] = key;
+    ki[p] = j;
+}
+
 // Result of warping one surfel by the blend of its 4 nodes.
 struct Warp {
     Q4 cr, cd;        // normalised blend c = b / |b_r|

@@ -53,6 +53,8 @@ void launch_positions_to_f4(int n, const float* pos, float4* out, hipStream_t st
 
 namespace swgn {
 void launch_fill_i32(int* p, int n, int v, hipStream_t st);
+// p[i] <- map[p[i]] for i < n (indices from one numbering to another)
+void launch_map_ids(int* p, int n, const int* map, hipStream_t st);
 void launch_tables_from_state(int nn, const float4* pref, const float4* rq, const float4* tt, float4* dq, float4* cl,
                               hipStream_t st);
 }  // namespace swgn
