@@ -409,13 +409,19 @@ def generate(jobs, workers):
     import multiprocessing as mp
     n = max(1, min(workers, len(jobs), os.cpu_count() or 1))
     if n == 1:
-        return [_generate_one(j) for j in jobs]
+        out = []
+        for j in jobs:
+            out.append(_generate_one(j))
+            print(f"[bench] scenes generated: {len(out)} of {len(jobs)}", file=sys.stderr, flush=True)
+        return out
     out = []
-    with mp.get_context("fork").Pool(n) as pool:
-        for r in pool.imap(_generate_one, jobs, chunksize=1):
-            out.append(r)
-            if len(out) % 8 == 0 or len(out) == len(jobs):
-                print(f"[bench] scenes generated: {len(out)} of {len(jobs)}", file=sys.stderr, flush=True)
+    pool = mp.get_context("fork").Pool(n)
+    for r in pool.imap(_generate_one, jobs, chunksize=1):
+        out.append(r)
+        if len(out) % 8 == 0 or len(out) == len(jobs):
+            print(f"[bench] scenes generated: {len(out)} of {len(jobs)}", file=sys.stderr, flush=True)
+    pool.close()                      # workers leave on their own (no signal to them)
+    pool.join()
     return out
 
 
