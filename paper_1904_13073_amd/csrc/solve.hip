@@ -306,8 +306,8 @@ struct RowAcc {
 };
 
 struct SlotData {
-    int n;                        // slots loaded: 0, 1 or 2 (slots fl and fl + 8)
-    float h[2][6];                // the block's row sub
+    int n;                        // slots in use: 0, 1 or 2 (slots fl and fl + 8)
+    float h[2][6];                // the block's row sub (zero for an unused slot)
     float c[2][5];                // column: z_{i-1}, p_{i-2}, u_{i-1}, v_{i-1}, r_{i-1} (FUSED), else z_i, p_{i-1}
     double m[2][6];               // FUSED: row sub of the column's inverse
 };
@@ -318,23 +318,27 @@ __device__ __forceinline__ void load_slot(const FrameDesc& a, int i, int row, in
     const int cur = i & 1, prv = cur ^ 1;
     const int sl = sub < 6 ? sub : 0;
     const float2* B = reinterpret_cast<const float2*>(a.Hf + ((size_t)row * a.ell_w + f) * 36 + sl * 6);
-    const float2 h01 = B[0], h23 = B[1], h45 = B[2];
+    const float2 h01 = gld2(B), h23 = gld2(B + 1), h45 = gld2(B + 2);
     h[0] = h01.x; h[1] = h01.y; h[2] = h23.x; h[3] = h23.y; h[4] = h45.x; h[5] = h45.y;
     const int t = 6 * col + sl;
     if (FUSED) {
-        cv[0] = by_parity(a.z, prv)[t];
-        cv[1] = by_parity(a.p, cur)[t];
-        cv[2] = by_parity(a.u, prv)[t];
-        cv[3] = by_parity(a.v, prv)[t];
-        cv[4] = by_parity(a.r, prv)[t];
+        cv[0] = gld(by_parity(a.z, prv) + t);
+        cv[1] = gld(by_parity(a.p, cur) + t);
+        cv[2] = gld(by_parity(a.u, prv) + t);
+        cv[3] = gld(by_parity(a.v, prv) + t);
+        cv[4] = gld(by_parity(a.r, prv) + t);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) m[j] = a.Minv[(size_t)col * 36 + sl * 6 + j];
+        for (int j = 0; j < 6; ++j) m[j] = gld(a.Minv + (size_t)col * 36 + sl * 6 + j);
     } else {
-        cv[0] = by_parity(a.z, cur)[t];
-        cv[1] = by_parity(a.p, prv)[t];
+        cv[0] = gld(by_parity(a.z, cur) + t);
+        cv[1] = gld(by_parity(a.p, prv) + t);
     }
 }
 
+// The first two slots of each lane group are loaded without a branch (a
+// padding slot reads slot 0's column and an in-bounds block, and its block
+// is zeroed), so that no load waits for the padding test: the block loads
+// go out at once, the column loads after the column index.
 template <bool FUSED>
 __device__ __forceinline__ void row_prefetch(const FrameDesc& a, int i, int row, int lane, SlotData& sd) {
     const int sub = lane & 7, fl = lane >> 3;
@@ -342,13 +346,20 @@ __device__ __forceinline__ void row_prefetch(const FrameDesc& a, int i, int row,
     if (row >= a.nn) return;
     const uint32_t* eb = a.ell_blk + (size_t)row * a.ell_w;
     const int* ec = a.ell_col + (size_t)row * a.ell_w;
+    bool use[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int f = fl + 8 * q;
-        if (f >= a.ell_w || eb[f] == 0xffffffffu) break;
-        load_slot<FUSED>(a, i, row, f, ec[f], sub, sd.h[q], sd.c[q], sd.m[q]);
-        sd.n = q + 1;
+        const int fc = f < a.ell_w ? f : 0;
+        use[q] = f < a.ell_w && gld(eb + fc) != 0xffffffffu;
+        load_slot<FUSED>(a, i, row, fc, gld(ec + fc), sub, sd.h[q], sd.c[q], sd.m[q]);
     }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sd.h[q][c] = use[q] ? sd.h[q][c] : 0.f;
+    // slots are used from the front (padding only at a row's end)
+    sd.n = use[1] ? 2 : (use[0] ? 1 : 0);
 }
 
 // the column's z and p of one slot (FUSED: its finish of iteration i - 1)
