@@ -44,3 +44,41 @@ def test_random_stream_ranges():
     assert s.depth.shape == (240, 320)
     assert s.surfel_pos.shape[0] == 5000
     assert s.node_pos.shape[0] == 300
+
+
+def test_motion_walk_steps_are_fresh_and_bounded():
+    """The served streams' frames: every step of the walk is a rotation of at
+    most 2 deg about each node's live position plus a translation of at most
+    5 mm, composed after the previous frame's motion; frame 0 is the scene's."""
+    from scipy.spatial.transform import Rotation
+
+    from gen.scenes import motion_walk
+    s = scene_random(401, size=(320, 240), n_nodes=300, n_surfels=6000)
+    walk = motion_walk(s, 4, seed=11)
+    assert len(walk) == 4 and np.array_equal(walk[0], s.gt_se3.reshape(-1, 12))
+    p = s.node_pos.astype(np.float64)
+    for a, b in zip(walk[:-1], walk[1:]):
+        A, B = a.reshape(-1, 3, 4), b.reshape(-1, 3, 4)
+        # the step D = B A^-1 as a transform of live points
+        Ra, ta, Rb, tb = A[:, :, :3], A[:, :, 3], B[:, :, :3], B[:, :, 3]
+        Rd = Rb @ np.transpose(Ra, (0, 2, 1))
+        td = tb - np.einsum("nij,nj->ni", Rd, ta)
+        ang = np.degrees(Rotation.from_matrix(Rd).magnitude())
+        assert ang.max() <= 2.0 + 1e-6 and ang.max() > 0.5
+        live = np.einsum("nij,nj->ni", Ra, p) + ta                     # each node's live position
+        moved = np.einsum("nij,nj->ni", Rd, live) + td - live          # the step's translation there
+        assert np.linalg.norm(moved, axis=1).max() <= 0.005 + 1e-9
+    assert not np.array_equal(walk[1], walk[2])
+
+
+def test_ping_pong_playback_steps_one_frame_at_a_time():
+    import bench
+    seq = [bench.ping_pong(k, 4) for k in range(13)]
+    assert seq[:7] == [1, 2, 3, 2, 1, 0, 1]
+    assert all(abs(a - b) == 1 for a, b in zip(seq[:-1], seq[1:]))
+    assert all(bench.ping_pong(k, 1) == 0 for k in range(3))
+    tr = bench.arrival_trace(3, 30.0, 1.0, seed=2)
+    assert all(t0 <= t1 for (t0, _, _), (t1, _, _) in zip(tr[:-1], tr[1:]))
+    for i in range(3):
+        ks = [k for _, s, k in tr if s == i]
+        assert ks == list(range(len(ks)))                         # each stream's arrivals in order
