@@ -135,6 +135,10 @@ def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": scale * kb[name], "avg_launch_us": round(float(replay[name]), 3),
             "launches_per_frame": int(launches[KERNELS.index(name)])}
+    if traffic is not None:
+        # the bytes the kernel moves beyond L2 (counters) per launch time, beside the algorithmic rate
+        roof["traffic_gbs"] = round(traffic / (replay[name] * 1e-6) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_gbs"] / HBM_PEAK_GBS, 4)
     return roof, {k: round(v, 1) for k, v in rates.items()}
 
 
