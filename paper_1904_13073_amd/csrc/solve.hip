@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     for (int c = 0; c < 6; ++c) {
         double pr[12];
 #pragma unroll
-        for (int j = 0; j < 12; ++j) pr[j] = __shfl(m[j], base + c, kWave);
+        for (int j = 0; j < 12; ++j) pr[j] = bcast8(m[j], c);
         const double piv = pr[c];
         ok = ok && (piv > 0.0);
         const double inv = 1.0 / (piv > 0.0 ? piv : 1.0);
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     double zc = 0.0;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const float rj = __shfl(rc, base + j, kWave);
+        const float rj = bcast8(rc, j);
         const double mj = ok ? m[6 + j] : (j == row ? 1.0 : 0.0);
         zc += mj * (double)rj;
         if (on) a.Minv[(size_t)k * 36 + row * 6 + j] = mj;
@@ -123,8 +123,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
         rr = (double)rc * (double)rc;
     }
     // partials per 8 nodes: one wave's sums
-    rho = wave_sum(rho);
-    rr = wave_sum(rr);
+    rho = wave_sum_x(rho);
+    rr = wave_sum_x(rr);
     const int part = gid / kWave;
     if (lane == 0 && part < solve_parts(a)) {
         a.part_rho.b0[part] = rho;
@@ -139,7 +139,7 @@ __device__ __forceinline__ double reduce_parts256(const double* __restrict__ par
     double v = 0.0;
     if (threadIdx.x < 256)
         for (int i = threadIdx.x; i < n; i += 256) v += part[i];
-    v = wave_sum(v);
+    v = wave_sum_x(v);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0 && w < 4) sh[w] = v;
     __syncthreads();
@@ -185,7 +185,7 @@ __device__ __forceinline__ Sum4 reduce4_parts256(const double* __restrict__ p0, 
         }
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
+    for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0 && w < 4) {
 #pragma unroll
@@ -234,7 +234,7 @@ __device__ __forceinline__ Finished finish_lane(float zk, float pprev, float uk,
     f.r = rk - s.alpha * q;
     double zc = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) zc += mrow[j] * (double)__shfl(f.r, base + j, kWave);
+    for (int j = 0; j < 6; ++j) zc += mrow[j] * (double)bcast8(f.r, j);
     f.z = (float)zc;
     return f;
 }
@@ -283,8 +283,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
             rz = (double)f.r * (double)f.z;
             rr = (double)f.r * (double)f.r;
         }
-        rz = wave_sum(rz);
-        rr = wave_sum(rr);
+        rz = wave_sum_x(rz);
+        rr = wave_sum_x(rr);
         const int part = (at.tile * NPG * kSolveNodes + g * kSolveNodes) / kSolvePart + wave;
         if (lane == 0 && part < solve_parts(a)) {
             by_parity(a.part_rho, nxt)[part] = rz;
@@ -385,8 +385,8 @@ __device__ __forceinline__ void slot_products(const float (&h)[6], float zv, flo
                                               float& av) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const float zc = __shfl(zv, base + c, kWave);
-        const float pc = __shfl(pv, base + c, kWave);
+        const float zc = bcast8(zv, c);
+        const float pc = bcast8(pv, c);
         au = fmaf(h[c], zc, au);
         av = fmaf(h[c], pc, av);
     }
@@ -421,12 +421,12 @@ __device__ __forceinline__ RowAcc row_products(const FrameDesc& a, int i, int ro
         }
         if (sub >= 6) { au = 0.f; av = 0.f; }
     }
-    au += __shfl_xor(au, 8, kWave);
-    au += __shfl_xor(au, 16, kWave);
-    au += __shfl_xor(au, 32, kWave);
-    av += __shfl_xor(av, 8, kWave);
-    av += __shfl_xor(av, 16, kWave);
-    av += __shfl_xor(av, 32, kWave);
+    au += xchg<8>(au);
+    au += xchg<16>(au);
+    au += xchg<32>(au);
+    av += xchg<8>(av);
+    av += xchg<16>(av);
+    av += xchg<32>(av);
     return RowAcc{au, av};
 }
 
@@ -447,7 +447,7 @@ __device__ __forceinline__ RowProducts store_row(const FrameDesc& a, int i, int 
         c2 = (double)zo * (double)ra.v + (double)po * (double)ra.u;
         c3 = (double)po * (double)ra.v;
     }
-    return RowProducts{wave_sum(c1), wave_sum(c2), wave_sum(c3)};
+    return RowProducts{wave_sum_x(c1), wave_sum_x(c2), wave_sum_x(c3)};
 }
 
 // Partial of a workgroup's 8 rows (kSpmvPart): the in-order sum of its rows'
@@ -547,8 +547,8 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
         }
         own_z[lane] = on ? f.z : 0.f;
         own_p[lane] = on ? f.p : 0.f;
-        rz = wave_sum(rz);
-        rr = wave_sum(rr);
+        rz = wave_sum_x(rz);
+        rr = wave_sum_x(rr);
         if (lane == 0 && n0 / kSolvePart < solve_parts(a)) {
             by_parity(a.part_rho, nxt)[n0 / kSolvePart] = rz;
             by_parity(a.part_rr, nxt)[n0 / kSolvePart] = rr;
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
 #pragma unroll 4
         for (int t = threadIdx.x; t < solve_parts(a); t += kNodeBlock) v[3] += prr[t];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
+        for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
         const int w = threadIdx.x / kWave;
         if ((threadIdx.x % kWave) == 0) {
 #pragma unroll

@@ -243,6 +243,105 @@ struct IterStats {
 };
 
 // ---------------------------------------------------------------------------
+// Lane exchanges on the VALU (DPP and the gfx950 permlane swaps) instead of
+// the LDS crossbar (ds_bpermute): no LDS instruction, no wait on the LDS
+// counter, a few cycles of latency. They move values only, so a sum built
+// from them equals, bit for bit, the same sum built from __shfl_xor.
+//   xchg<M>(v)    the value of lane (lane ^ M), M in {1, 2, 4, 8, 16, 32};
+//                 M >= 16 needs every lane of the wave active, M <= 8 every
+//                 lane of the lane's 16-lane row
+//   bcast8(v, c)  the value of lane c of the lane's 8-lane group, c in [0, 8)
+//                 a compile-time constant once unrolled; needs the group's
+//                 lanes active
+// DPP controls (gfx9): quad_perm [a,b,c,d] = a | b << 2 | c << 4 | d << 6,
+// row_shl:n = 0x100 + n (lane i takes lane i + n of its 16-lane row),
+// row_shr:n = 0x110 + n (lane i takes lane i - n), row_ror:n = 0x120 + n;
+// a bank is 4 lanes of a row, and lanes of banks left out of the bank mask
+// keep the first operand.
+// ---------------------------------------------------------------------------
+template <int CTRL, int BANKS = 0xF>
+__device__ __forceinline__ int dpp_mov(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, BANKS, false);
+}
+
+template <int M>
+__device__ __forceinline__ int xchg_i(int v) {
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32, "xor mask");
+    if constexpr (M == 1) {
+        return dpp_mov<0xB1>(0, v);                     // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        return dpp_mov<0x4E>(0, v);                     // quad_perm [2,3,0,1]
+    } else if constexpr (M == 4) {
+        const int t = dpp_mov<0x104, 0x5>(v, v);        // banks 0, 2: lane + 4
+        return dpp_mov<0x114, 0xA>(t, v);               // banks 1, 3: lane - 4
+    } else if constexpr (M == 8) {
+        return dpp_mov<0x128>(0, v);                    // row_ror:8
+    } else if constexpr (M == 16) {
+        // odd rows of the first operand trade places with even rows of the second
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? (int)p[0] : (int)p[1];
+    } else {
+        // rows 2, 3 of the first operand trade places with rows 0, 1 of the second
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? (int)p[0] : (int)p[1];
+    }
+}
+
+template <int M>
+__device__ __forceinline__ float xchg(float v) {
+    return __int_as_float(xchg_i<M>(__float_as_int(v)));
+}
+template <int M>
+__device__ __forceinline__ double xchg(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)xchg_i<M>((int)(unsigned)b);
+    const unsigned hi = (unsigned)xchg_i<M>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int C>
+__device__ __forceinline__ int bcast8_i(int v) {
+    if constexpr (C < 4) {
+        const int q = dpp_mov<C * 0x55>(0, v);          // lane C of each quad
+        return dpp_mov<0x114, 0xA>(q, q);               // the group's upper quad from its lower
+    } else {
+        const int q = dpp_mov<(C - 4) * 0x55>(0, v);
+        return dpp_mov<0x104, 0x5>(q, q);               // the group's lower quad from its upper
+    }
+}
+__device__ __forceinline__ int bcast8_i(int v, int c) {
+    switch (c) {
+        case 0: return bcast8_i<0>(v);
+        case 1: return bcast8_i<1>(v);
+        case 2: return bcast8_i<2>(v);
+        case 3: return bcast8_i<3>(v);
+        case 4: return bcast8_i<4>(v);
+        case 5: return bcast8_i<5>(v);
+        case 6: return bcast8_i<6>(v);
+        default: return bcast8_i<7>(v);
+    }
+}
+__device__ __forceinline__ float bcast8(float v, int c) { return __int_as_float(bcast8_i(__float_as_int(v), c)); }
+__device__ __forceinline__ double bcast8(double v, int c) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)bcast8_i((int)(unsigned)b, c);
+    const unsigned hi = (unsigned)bcast8_i((int)(unsigned)(b >> 32), c);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the wave in the butterfly order 32, 16, 8, 4, 2, 1 (every lane
+// active; every lane ends with the same value).
+__device__ __forceinline__ double wave_sum_x(double v) {
+    v += xchg<32>(v);
+    v += xchg<16>(v);
+    v += xchg<8>(v);
+    v += xchg<4>(v);
+    v += xchg<2>(v);
+    v += xchg<1>(v);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // Wave and block reductions (fixed butterfly order)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
