@@ -115,10 +115,11 @@ def replay_us(bx, streams, pcg_iters, reps=200):
 
 def launches_per_frame(G, P, fused):
     """Launches of each kernel per frame: one fused step per PCG iteration
-    after the first products, or a product and a finish launch."""
+    after the first products, or a product and a finish launch; the node
+    update rides on the last finish (its own launch only without PCG)."""
     import numpy as np
-    return np.array([1, G, G, G * P if fused else 0, G, G if fused else G * P, 0 if fused else G * P, G, G],
-                    dtype=float)
+    return np.array([1, G, G, G * P if fused else 0, G, G if fused else G * P, 0 if fused else G * P,
+                     0 if P > 0 else G, G], dtype=float)
 
 
 def stage_roofline(per_frame_us, launches, kb, replay, scale=1.0, streams=1):

@@ -132,8 +132,12 @@ __device__ __forceinline__ void splat_render(const FrameDesc& d, float3 v, float
 // the splat code)
 template <bool SPLAT>
 __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
+    static_assert(kWarpBlock == 256, "the statistics sums have the shape of a 256-thread workgroup");
     const Where at = locate(b);
     const FrameDesc d = *b.d[at.s];
+    // the previous iteration's statistics, before this iteration's
+    // correspondence launch overwrites its partials
+    if (at.tile == 0 && b.it[at.s] >= 1) iteration_stats(d, b.it[at.s] - 1);
     const int i = at.tile * kWarpBlock + threadIdx.x;
     if (i >= d.ns || !visible(d, i)) return;     // (the correspondence test needs the surfel in the map)
     float3 v = make_float3(d.px[i], d.py[i], d.pz[i]);

@@ -374,6 +374,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     h.npx = s->cam.W * s->cam.H;
     h.cam = s->cam;
     h.pcg_iters = s->cfg.pcg_iters;
+    h.gn_iters = s->cfg.gn_iters;
     h.debug_iter = s->cfg.debug_iter;
     h.jac_dtype = s->cfg.jac_dtype;
     h.rigid_iters = s->cfg.rigid_iters;
@@ -625,10 +626,11 @@ namespace rt {
 // One launch of `stage` over the streams; a stream contributes no tiles when
 // it has no work in it (its Gauss-Newton or PCG iterations are done).
 void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const std::vector<int>& its, int pcg_it,
-               const DepthIn* depth, bool timing, std::vector<int>& ev_stage) {
+               const DepthIn* depth, bool timing, std::vector<int>& ev_stage, bool update) {
     Batch b{};
     b.n = (int)ss.size();
     b.pcg_it = pcg_it;
+    b.update = update ? 1 : 0;
     int64_t rows = 0;
     for (int i = 0; i < b.n; ++i)
         if (its[i] >= 0) rows += ss[i]->h.nn;
@@ -646,6 +648,8 @@ void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const 
         // products of iteration pcg_it, finish of pcg_it, fused finish of pcg_it - 1 + products
         if ((stage == kStSpmv || stage == kStUpdate) && pcg_it >= h.pcg_iters) t = 0;
         if (stage == kStPcgStep && (pcg_it < 1 || pcg_it > h.pcg_iters)) t = 0;
+        // streams with PCG iterations are moved by their last finish
+        if (stage == kStNodeUpdate && h.pcg_iters > 0) t = 0;
         off += t;
     }
     b.off[b.n] = off;
@@ -748,9 +752,9 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
     for (int pit = 1; pit <= pmax; ++pit) {
         if (fused) {
             // finish of pit - 1 and, for streams with more iterations, products of pit
-            run_stage(ex, kStPcgStep, ss, its, pit, nullptr, timing, ev);
+            run_stage(ex, kStPcgStep, ss, its, pit, nullptr, timing, ev, true);
         } else {
-            run_stage(ex, kStUpdate, ss, its, pit - 1, nullptr, timing, ev);
+            run_stage(ex, kStUpdate, ss, its, pit - 1, nullptr, timing, ev, true);
             if (pit < pmax) run_stage(ex, kStSpmv, ss, its, pit, nullptr, timing, ev);
         }
     }

@@ -178,8 +178,10 @@ struct sw_stream_s {
 
 namespace swgn {
 namespace rt {
+// update: a PCG finish or fused step launch that also performs the node
+// update of every stream whose last finish it holds (not for replays)
 void run_stage(Executor& ex, int stage, const std::vector<sw_stream>& ss, const std::vector<int>& its, int pcg_it,
-               const DepthIn* depth, bool timing, std::vector<int>& ev_stage);
+               const DepthIn* depth, bool timing, std::vector<int>& ev_stage, bool update = false);
 void enqueue_depth(Executor& ex, const std::vector<sw_stream>& ss, const float* const* depths, int32_t on_device,
                    bool timing, std::vector<int>& ev);
 void enqueue_rigid(Executor& ex, const std::vector<sw_stream>& ss, bool timing, std::vector<int>& ev);

@@ -12,9 +12,12 @@
 //                (8 lanes per node)
 //   pcg_step     finish of iteration i - 1 and products of iteration i in one
 //                launch: the products re-form their columns' z_i and p_{i-1}
-//   node_update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
-//                the reset of the index map for the next iteration and the
-//                iteration's energy statistics
+//   node update  T_k <- Delta_k(xi_k) o T_k, Delta_k(x) = Exp(w)(x - c_k) + c_k + tau,
+//                and the reset of the index map for the next iteration: done
+//                by a stream's last PCG finish (fused step or finish launch),
+//                by k_node_update only for streams without PCG iterations;
+//                the iteration's energy statistics are summed by the next
+//                iteration's warp launch or, for the last, the statistics copy
 //
 // This is standard preconditioned CG (the same iterates in exact arithmetic)
 // with the application of beta deferred: the product kernel needs only
@@ -35,8 +38,7 @@ namespace swgn {
 namespace {
 
 
-__device__ void update_node(const FrameDesc& a, int k) {
-    const float* x = a.x + 6 * k;
+__device__ void update_node_x(const FrameDesc& a, int k, const float (&x)[6]) {
     float3 w = make_float3(x[0], x[1], x[2]);
     float3 tau = make_float3(x[3], x[4], x[5]);
     float th = sqrtf(dot3(w, w));
@@ -66,6 +68,31 @@ __device__ void update_node(const FrameDesc& a, int k) {
     a.rq[k] = f4(rn);
     a.tt[k] = make_float4(tn.x, tn.y, tn.z, 0.f);
     node_tables(p, rn, tn, a.dq, a.cl, k);
+}
+
+__device__ void update_node(const FrameDesc& a, int k) {
+    float x[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = a.x[6 * k + j];
+    update_node_x(a, k, x);
+}
+
+// Index map of the next iteration: tile `tile` of a launch with `ntiles`
+// tiles for the stream clears its share of the pixels.
+__device__ __forceinline__ void reset_index_map(const FrameDesc& a, int tile, int ntiles) {
+    const int chunk = cdiv(a.npx, ntiles);
+    const int p0 = tile * chunk, p1 = min(a.npx, p0 + chunk);
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += (int)blockDim.x) a.zbuf[p] = ~0ull;
+}
+
+// The node update of a stream's last PCG finish, inside the finishing lane
+// group (lane c holds component c of x_k): the group's 6 entries of x to
+// every lane, lane 0 moves node k.
+__device__ __forceinline__ void update_from_lanes(const FrameDesc& a, int k, int c, float xc) {
+    float x[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = bcast8(xc, j);
+    if (c == 0 && k < a.nn) update_node_x(a, k, x);
 }
 
 
@@ -241,7 +268,9 @@ __device__ __forceinline__ Finished finish_lane(float zk, float pprev, float uk,
 
 // Finish of iteration k = b.pcg_it: x_{k+1}, r_{k+1}, z_{k+1}, p_k; partials
 // of rho_{k+1} and r_{k+1}.r_{k+1}. NPG nodes per lane group (k, k + 32, ...
-// of the workgroup's 32 NPG); each wave's 8 nodes give one partial.
+// of the workgroup's 32 NPG); each wave's 8 nodes give one partial. A
+// stream's last finish (b.update) also moves its nodes by x and clears its
+// share of the index map.
 template <int NPG>
 __global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
     __shared__ double sh[40];
@@ -290,7 +319,9 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
             by_parity(a.part_rho, nxt)[part] = rz;
             by_parity(a.part_rr, nxt)[part] = rr;
         }
+        if (b.update && k == a.pcg_iters - 1) update_from_lanes(a, n, c, f.x);
     }
+    if (b.update && k == a.pcg_iters - 1) reset_index_map(a, at.tile, cdiv(a.nn, NPG * kSolveNodes));
 }
 
 // Products of one block row with z_i and with p_{i-1} (u_i and v_i of the
@@ -501,7 +532,9 @@ __global__ void __launch_bounds__(64 * kSpmvRows / RPW) k_pcg_spmv(Batch b) {
 // i - 1 for them (as k_pcg_finish), then, if i < pcg_iters, wave w forms the
 // products of iteration i for row 8 tile + w, computing the columns' z_i and
 // p_{i-1} itself (row_products<true>). One launch per PCG iteration instead of
-// two, at the cost of re-reading each column's state and inverse.
+// two, at the cost of re-reading each column's state and inverse. The
+// stream's last step (i = pcg_iters, with b.update) moves its nodes and
+// clears its share of the index map instead of forming products.
 __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
     __shared__ double sh[40];
     __shared__ double rs[kStepNodes][3];
@@ -553,8 +586,12 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
             by_parity(a.part_rho, nxt)[n0 / kSolvePart] = rz;
             by_parity(a.part_rr, nxt)[n0 / kSolvePart] = rr;
         }
+        if (!prod && b.update) update_from_lanes(a, n, c, f.x);
     }
-    if (!prod) return;
+    if (!prod) {
+        if (b.update) reset_index_map(a, at.tile, cdiv(a.nn, kStepNodes));
+        return;
+    }
     __syncthreads();
     const RowAcc ra = row_products<true>(a, i, row, lane, s, sd);
     const float zo = lane < 6 ? own_z[wave * 8 + lane] : 0.f;
@@ -569,63 +606,33 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
     store_row_parts(a, i, n0 / kSpmvPart, rs);
 }
 
+// The node update of streams without PCG iterations (x = 0) and the reset
+// of their index map; streams with PCG iterations are updated by their last
+// finish.
 __global__ void __launch_bounds__(kNodeBlock) k_node_update(Batch b) {
-    __shared__ double sh[4 * (kNodeBlock / kWave)];
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
     const int gid = at.tile * kNodeBlock + threadIdx.x;
     if (gid < a.nn) update_node(a, gid);
     if (gid < a.npx) a.zbuf[gid] = ~0ull;     // index map of the next iteration
-    if (at.tile == 0) {
-        // energies at this iteration's linearisation point and |r| of the
-        // last PCG residual: each a strided per-thread sum, then the wave
-        // sums, then the 4 waves in order, all four in one pass
-        const int nparts = corr_tiles(a);
-        IterStats* stats = a.stats + b.it[at.s];
-        const double* prr = by_parity(a.part_rr, a.pcg_iters & 1);
-        double v[4] = {0.0, 0.0, 0.0, 0.0};     // e, n, e_reg, r.r
-#pragma unroll 4
-        for (int t = threadIdx.x; t < nparts; t += kNodeBlock) { v[0] += a.part_e[t]; v[1] += (double)a.part_n[t]; }
-#pragma unroll 4
-        for (int t = threadIdx.x; t < a.nn; t += kNodeBlock) v[2] += (double)a.ereg[t];
-#pragma unroll 4
-        for (int t = threadIdx.x; t < solve_parts(a); t += kNodeBlock) v[3] += prr[t];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
-        const int w = threadIdx.x / kWave;
-        if ((threadIdx.x % kWave) == 0) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) sh[4 * w + m] = v[m];
-        }
-        __syncthreads();
-        double tot[4] = {0.0, 0.0, 0.0, 0.0};
-        if (threadIdx.x == 0)
-            for (int q = 0; q < kNodeBlock / kWave; ++q)
-                for (int m = 0; m < 4; ++m) tot[m] += sh[4 * q + m];
-        const double e = tot[0], n = tot[1], er = tot[2], rr = tot[3];
-        if (threadIdx.x == 0) {
-            stats->pcg_resid = sqrt(rr);
-            stats->e_data = e;
-            stats->e_reg = er;
-            stats->n_corr = (int)n;
-            if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
-        }
-    }
 }
 
-// Copies each stream's iteration statistics and failure flags to slot s of
-// `out` (kStatsOutBytes per stream), so one copy brings a whole batch's back.
-__global__ void __launch_bounds__(64) k_stats_out(Batch b, char* __restrict__ out) {
+// Sums the statistics of each stream's last Gauss-Newton iteration (the
+// earlier ones were summed by the warp launch of the next iteration) and
+// copies its iteration statistics and failure flags to slot s of `out`
+// (kStatsOutBytes per stream), so one copy brings a whole batch's back.
+__global__ void __launch_bounds__(256) k_stats_out(Batch b, char* __restrict__ out) {
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
+    if (a.gn_iters > 0) iteration_stats(a, a.gn_iters - 1);
     int* dst = reinterpret_cast<int*>(out + (size_t)at.s * kStatsOutBytes);
     const int* src = reinterpret_cast<const int*>(a.stats);
     constexpr int nw = (int)(sizeof(IterStats) * kMaxIters / 4);
     constexpr int nr = (int)(sizeof(RigidStats) * kMaxIters / 4);
-    for (int t = threadIdx.x; t < nw; t += 64) dst[t] = src[t];
+    for (int t = threadIdx.x; t < nw; t += blockDim.x) dst[t] = src[t];
     if (threadIdx.x < 4) dst[nw + threadIdx.x] = a.flags[threadIdx.x];
     const int* rsrc = reinterpret_cast<const int*>(a.rig_stats);
-    for (int t = threadIdx.x; t < nr; t += 64) dst[nw + 4 + t] = rsrc[t];
+    for (int t = threadIdx.x; t < nr; t += blockDim.x) dst[nw + 4 + t] = rsrc[t];
 }
 
 }  // namespace
@@ -646,7 +653,7 @@ void launch_solve_stage(int stage, const Batch& b, void* stats_out, hipStream_t 
         case kStPcgStep: hipLaunchKernelGGL(k_pcg_step, dim3(grid), dim3(kStepBlock), 0, st, b); break;
         case kStNodeUpdate: hipLaunchKernelGGL(k_node_update, dim3(grid), dim3(kNodeBlock), 0, st, b); break;
         case kStStatsOut:
-            hipLaunchKernelGGL(k_stats_out, dim3(grid), dim3(64), 0, st, b, static_cast<char*>(stats_out));
+            hipLaunchKernelGGL(k_stats_out, dim3(grid), dim3(256), 0, st, b, static_cast<char*>(stats_out));
             break;
         default: break;
     }

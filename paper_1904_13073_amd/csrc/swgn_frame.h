@@ -80,6 +80,7 @@ struct FrameDesc {
     int npack;                    // packs: consecutive whole segments, at most kCorrPack surfels
     int64_t part_floats;          // floats of all segments' Gram sub-blocks
     int pcg_iters, debug_iter;
+    int gn_iters;                 // Gauss-Newton iterations of a frame
     int jac_dtype;                // Jacobian entries kept as 0 fp32, 1 bf16, 2 fp16
     int rigid_iters;              // rigid alignment steps before the non-rigid ones
     int vis_mode;                 // 1: only stable or recently observed surfels are rendered
@@ -212,6 +213,7 @@ struct Batch {
     int order;                    // kOrderXcd: tiles in XCD-contiguous order
     int wide;                     // the stage's wider geometry (kVarWide)
     int splat;                    // some stream renders splats (the kernels with splat code run)
+    int update;                   // a stream's last PCG finish in this launch also moves its nodes
     int off[kMaxBatch + 1];       // stream s owns tiles [off[s], off[s+1])
     const FrameDesc* d[kMaxBatch];
     int8_t it[kMaxBatch];         // Gauss-Newton iteration of each stream
@@ -251,6 +253,47 @@ __device__ __forceinline__ Where locate(const Batch& b) {
         if (b.off[mid] <= t) lo = mid; else hi = mid - 1;
     }
     return Where{lo, t - b.off[lo]};
+}
+
+// Statistics of Gauss-Newton iteration `it` of a stream, by one workgroup of
+// 256 threads: the data energy and correspondence count of its linearisation
+// point (the correspondence tiles' partials), the regulariser energy (per
+// node) and |r| of its last PCG residual, each a strided per-thread sum, then
+// the wave sums, then the 4 waves in order; a non-finite energy sets failure
+// bit 2. Runs after the iteration's node update and before the next
+// iteration's correspondence kernel overwrites the partials.
+__device__ __forceinline__ void iteration_stats(const FrameDesc& a, int it) {
+    __shared__ double sh[16];
+    const int nparts = corr_tiles(a);
+    const double* prr = by_parity(a.part_rr, a.pcg_iters & 1);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};     // e, n, e_reg, r.r
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nparts; t += 256) { v[0] += a.part_e[t]; v[1] += (double)a.part_n[t]; }
+#pragma unroll 4
+    for (int t = threadIdx.x; t < a.nn; t += 256) v[2] += (double)a.ereg[t];
+#pragma unroll 4
+    for (int t = threadIdx.x; t < solve_parts(a); t += 256) v[3] += prr[t];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sh[4 * w + m] = v[m];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < 4; ++q)
+            for (int m = 0; m < 4; ++m) tot[m] += sh[4 * q + m];
+        const double e = tot[0], n = tot[1], er = tot[2], rr = tot[3];
+        IterStats* stats = a.stats + it;
+        stats->pcg_resid = sqrt(rr);
+        stats->e_data = e;
+        stats->e_reg = er;
+        stats->n_corr = (int)n;
+        if (!(e < INFINITY) || !(er < INFINITY)) atomicOr(a.flags, 2);
+    }
+    __syncthreads();
 }
 
 // Launchers (one per kernel file); grid = b.off[b.n] workgroups.
