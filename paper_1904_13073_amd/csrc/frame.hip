@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(kWarpBlock) k_warp_zbuf(Batch b) {
 // only feeds Gram entries with an index of 31, which are discarded.
 constexpr int kRowPad = 31;
 constexpr int kStageFloats = 576;    // per wave: a segment's whole output (at most 36 x 15 + 32 floats)
+constexpr int kStageSlots = kStageFloats + kWave;   // and one discard word per lane
 
 // Code of accumulator element t of lane l in a segment's Gram tile (element
 // G[i][j], j = l % 32, i = (t / 4) * 8 + (l / 32) * 4 + t % 4): for a node-pair
@@ -411,10 +412,34 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int comp = lane & 31, half = lane >> 5;
     const int g0 = gld(d.pack_seg + tile), g1 = gld(d.pack_seg + tile + 1);
+    // the descriptor's pointers read once (the stores below could alias it)
+    const int* seg_start = d.seg_start;
+    const uint16_t* seg_mask = d.seg_mask;
+    const uint32_t* seg_off = d.seg_off;
+    float* part = d.part;
     float* sg = reinterpret_cast<float*>(stage);
-    const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
+    // this lane's 16 accumulator elements: the pair's bit as a mask (bit 31
+    // for J^T r and r^T r, which follow the sub-blocks; 0 for an element that
+    // is not kept) and the offset. An element's output slot is then
+    // 36 x (pairs of the segment below its pair) + offset, where the pairs
+    // below bit 31 are all of them; a dropped element goes to the lane's
+    // discard word, so every element is one unconditional LDS store.
+    uint32_t bm[16];
+    int off[16];
+    {
+        const uint4* codes = reinterpret_cast<const uint4*>(kGramCodes.c[lane]);
+        const uint4 q0 = codes[0], q1 = codes[1];
+        const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+            const uint32_t bit = code & 15u;
+            bm[t] = code == 0xffffu ? 0u : (bit == 15u ? 0x80000000u : (1u << bit));
+            off[t] = (int)(code >> 4);
+        }
+    }
     for (int seg = g0 + wave; seg < g1; seg += kCorrBlock / kWave) {
-        int s0 = gld(d.seg_start + seg) - p0, s1 = gld(d.seg_start + seg + 1) - p0;
+        int s0 = gld(seg_start + seg) - p0, s1 = gld(seg_start + seg + 1) - p0;
         if (planes != nullptr) {
             s0 = min(max(extra_before(planes, s0) - base, 0), kCorrPack);
             s1 = min(max(extra_before(planes, s1) - base, 0), kCorrPack);
@@ -424,6 +449,8 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
             for (int m = s0 + lane; m < s1; m += kWave) any |= ((more[m / kWave] >> (m % kWave)) & 1ull) != 0;
             if (__ballot(any) == 0) continue;                  // uniform over the wave
         }
+        const uint32_t mask = gld(seg_mask + seg);          // (issued before the sums)
+        float4* out = reinterpret_cast<float4*>(part + gld(seg_off + seg));
         f32x16 acc;
 #pragma unroll
         for (int t = 0; t < 16; ++t) acc[t] = 0.f;
@@ -432,30 +459,24 @@ __device__ __forceinline__ void segment_grams(const FrameDesc& d, const float* r
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int sr = m0 + 2 * q + half;   // surfel of this half-wave
-                v[q] = sr < s1 ? rows[sr * kRowPad + comp] : 0.f;
+                const float e = rows[(sr < s1 ? sr : s0) * kRowPad + comp];   // (a row of the segment)
+                v[q] = sr < s1 ? e : 0.f;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(v[q], v[q], acc, 0, 0, 0);
         }
-        const uint32_t mask = gld(d.seg_mask + seg);
         const int npr = __builtin_popcount(mask);
         const int size = 36 * npr + 32;
-        const uint4 q0 = codes[0], q1 = codes[1];
-        const uint32_t cw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const uint32_t mk = mask | 0x80000000u;
         // the whole output staged in LDS, then stored as whole float4 lines
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            const uint32_t code = (cw[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-            const uint32_t bit = code & 15u, off = code >> 4;
-            const bool tail = bit == 15u;
-            const bool keep = code != 0xffffu && (tail || ((mask >> bit) & 1u));
-            const int sl = tail ? 36 * npr + (int)off : 36 * __builtin_popcount(mask & ((1u << bit) - 1u)) + (int)off;
-            if (keep) sg[sl] = acc[t];
+            const int sl = 36 * __builtin_popcount(mask & (bm[t] - 1u)) + off[t];
+            sg[(mk & bm[t]) != 0u ? sl : kStageFloats + lane] = acc[t];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float4* out = reinterpret_cast<float4*>(d.part + gld(d.seg_off + seg));
         if (more != nullptr || planes != nullptr) {
             for (int q = lane; q < size / 4; q += kWave) {
                 const float4 a = gld4(out + q), c4 = stage[q];
@@ -492,7 +513,7 @@ __global__ void __launch_bounds__(kCorrBlock, 4) k_corr_gram(Batch b) {
     __shared__ int shi[16];
     __shared__ unsigned long long planes[2 * (kCorrBlock / kWave)];   // splat: extra rows per surfel
     __shared__ float rows[kCorrPack * kRowPad + 8];
-    __shared__ float4 stage4[kCorrBlock / kWave][kStageFloats / 4];
+    __shared__ float4 stage4[kCorrBlock / kWave][kStageSlots / 4];
     const Where at = locate(b);
     const FrameDesc& d = *b.d[at.s];
     const bool capture = (b.it[at.s] == d.debug_iter) && d.dbg_corr != nullptr;

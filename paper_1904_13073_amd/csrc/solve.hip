@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
         rr = (double)rc * (double)rc;
     }
     // partials per 8 nodes: one wave's sums
-    rho = wave_sum_x(rho);
-    rr = wave_sum_x(rr);
+    rho = wave_sum(rho);
+    rr = wave_sum(rr);
     const int part = gid / kWave;
     if (lane == 0 && part < solve_parts(a)) {
         a.part_rho.b0[part] = rho;
@@ -166,7 +166,7 @@ __device__ __forceinline__ double reduce_parts256(const double* __restrict__ par
     double v = 0.0;
     if (threadIdx.x < 256)
         for (int i = threadIdx.x; i < n; i += 256) v += part[i];
-    v = wave_sum_x(v);
+    v = wave_sum(v);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0 && w < 4) sh[w] = v;
     __syncthreads();
@@ -212,7 +212,7 @@ __device__ __forceinline__ Sum4 reduce4_parts256(const double* __restrict__ p0, 
         }
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
+    for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0 && w < 4) {
 #pragma unroll
@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_finish(Batch b) {
             rz = (double)f.r * (double)f.z;
             rr = (double)f.r * (double)f.r;
         }
-        rz = wave_sum_x(rz);
-        rr = wave_sum_x(rr);
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
         const int part = (at.tile * NPG * kSolveNodes + g * kSolveNodes) / kSolvePart + wave;
         if (lane == 0 && part < solve_parts(a)) {
             by_parity(a.part_rho, nxt)[part] = rz;
@@ -478,7 +478,7 @@ __device__ __forceinline__ RowProducts store_row(const FrameDesc& a, int i, int 
         c2 = (double)zo * (double)ra.v + (double)po * (double)ra.u;
         c3 = (double)po * (double)ra.v;
     }
-    return RowProducts{wave_sum_x(c1), wave_sum_x(c2), wave_sum_x(c3)};
+    return RowProducts{wave_sum(c1), wave_sum(c2), wave_sum(c3)};
 }
 
 // Partial of a workgroup's 8 rows (kSpmvPart): the in-order sum of its rows'
@@ -580,8 +580,8 @@ __global__ void __launch_bounds__(kStepBlock) k_pcg_step(Batch b) {
         }
         own_z[lane] = on ? f.z : 0.f;
         own_p[lane] = on ? f.p : 0.f;
-        rz = wave_sum_x(rz);
-        rr = wave_sum_x(rr);
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
         if (lane == 0 && n0 / kSolvePart < solve_parts(a)) {
             by_parity(a.part_rho, nxt)[n0 / kSolvePart] = rz;
             by_parity(a.part_rr, nxt)[n0 / kSolvePart] = rr;

@@ -274,7 +274,7 @@ __device__ __forceinline__ void iteration_stats(const FrameDesc& a, int it) {
 #pragma unroll 4
     for (int t = threadIdx.x; t < solve_parts(a); t += 256) v[3] += prr[t];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = wave_sum_x(v[m]);
+    for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0) {
 #pragma unroll

@@ -329,9 +329,14 @@ __device__ __forceinline__ double bcast8(double v, int c) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the wave in the butterfly order 32, 16, 8, 4, 2, 1 (every lane
-// active; every lane ends with the same value).
-__device__ __forceinline__ double wave_sum_x(double v) {
+// ---------------------------------------------------------------------------
+// Wave and block reductions (fixed butterfly order)
+// ---------------------------------------------------------------------------
+// Sums over the wave in the butterfly order 32, 16, 8, 4, 2, 1 through the
+// lane exchanges above (every lane active; every lane ends with the same
+// value, the one a __shfl_xor butterfly gives).
+template <class T>
+__device__ __forceinline__ T wave_sum_t(T v) {
     v += xchg<32>(v);
     v += xchg<16>(v);
     v += xchg<8>(v);
@@ -340,23 +345,15 @@ __device__ __forceinline__ double wave_sum_x(double v) {
     v += xchg<1>(v);
     return v;
 }
-
-// ---------------------------------------------------------------------------
-// Wave and block reductions (fixed butterfly order)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ __forceinline__ float wave_sumf(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_t(v); }
+__device__ __forceinline__ float wave_sumf(float v) { return wave_sum_t(v); }
 __device__ __forceinline__ int wave_sumi(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    v += xchg_i<32>(v);
+    v += xchg_i<16>(v);
+    v += xchg_i<8>(v);
+    v += xchg_i<4>(v);
+    v += xchg_i<2>(v);
+    v += xchg_i<1>(v);
     return v;
 }
 
