@@ -8,10 +8,11 @@
 // rows (Sec. 7, E_regulation = sum_j sum_{m in N_j} |T_j p_j - T_m p_j|^2) are
 // formed here from the node state.
 //
-// A 16-lane group per block sums its segments' sub-blocks in a fixed order,
-// adds the regulariser terms (edges spread over the lanes) and the damping,
-// and finishes with a DPP row reduction. No atomics; results are
-// reproducible.
+// A group of lanes per block (16 for a diagonal block, 4 for an off-diagonal
+// one, which has few segments) sums its segments' sub-blocks in a fixed
+// order, adds the regulariser terms (edges spread over the lanes) and the
+// damping, and finishes with a DPP reduction over the group. No atomics;
+// results are reproducible.
 #include "swgn_frame.h"
 #include "swgn_impl.h"
 #include "swgn_launch.h"
@@ -38,17 +39,50 @@ __device__ __forceinline__ bool has_edge(const int* __restrict__ nbr, int j, int
 }
 
 
-// One 16-lane group per block; diagonal blocks first (node order),
-// then the off-diagonal ones.
-__global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
-    const Where at = locate(wl);
-    const FrameDesc in = *wl.d[at.s];
-    const bool capture = wl.it[at.s] == in.debug_iter;
-    const int lane = threadIdx.x % kWave, g = lane & 15;
-    const int gi = at.tile * kFoldGroups + (threadIdx.x >> 4);
-    const bool active = gi < in.nn + in.noff;
-    const bool diag = gi < in.nn;
-    const int b = !active ? 0 : (diag ? in.row_ptr[gi] : in.offlist[gi - in.nn]);
+// Sum over the L lanes of a block's group (every lane ends with it): a
+// 16-lane row with DPP mirror, half-mirror and two quad permutations, a quad
+// with the two quad permutations.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+    if constexpr (L == 16) {
+        return row16_sum(v);
+    } else {
+        static_assert(L == 4, "groups of 16 or 4 lanes");
+        v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+        v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+        return v;
+    }
+}
+
+// float4 number v (a lane-dependent value in [s L, min(9, s L + L))) of the
+// block (T: of its transpose), row-major; the selects keep every register
+// index a compile-time constant.
+template <int L, bool T>
+__device__ __forceinline__ float4 pick4(const float (&acc)[36], int v, int s) {
+    float r[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int v0 = s * L;
+        float x = 0.f;
+#pragma unroll
+        for (int w = v0; w < (v0 + L < 9 ? v0 + L : 9); ++w) {
+            const int q = 4 * w + e;                       // element q of the (transposed) block
+            const float y = T ? acc[6 * (q % 6) + q / 6] : acc[q];
+            x = (w == v0 || v == w) ? y : x;
+        }
+        r[e] = x;
+    }
+    return make_float4(r[0], r[1], r[2], r[3]);
+}
+
+// One block by a group of L lanes (lane g of the group): its segments'
+// sub-blocks summed by the lanes in a fixed order, the regulariser terms
+// spread over the lanes, the group sums, the damping; then the block into
+// its row of the explicit rows (and its transpose into the column's row), the
+// upper copy H for the diagonal (all blocks when captured), g and the
+// regulariser energy for the diagonal.
+template <int L>
+__device__ __forceinline__ void fold_block(const FrameDesc& in, bool capture, bool active, bool diag, int b, int g) {
     const int k = in.blk_row[b], l = in.col_idx[b];
     const float lam = in.lambda;
     float acc[36];
@@ -59,7 +93,7 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
 #pragma unroll
     for (int t = 0; t < 6; ++t) gacc[t] = 0.f;
     const int e0 = active ? in.ent_ptr[b] : 0, e1 = active ? in.ent_ptr[b + 1] : 0;
-    for (int e = e0 + g; e < e1; e += 16) {
+    for (int e = e0 + g; e < e1; e += L) {
         const float4* blk = reinterpret_cast<const float4*>(in.part + in.ent_sub[e]);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -73,14 +107,14 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
         }
     }
     if (active && diag) {
-        if (g < 8) {                          // out-edge k -> m: J_k = [0 | I]
+        for (int q = g; q < 8; q += L) {      // out-edge k -> m: J_k = [0 | I]
             float3 y, r;
-            arap_edge(in, k, in.nbr[8 * k + g], y, r);
+            arap_edge(in, k, in.nbr[8 * k + q], y, r);
             acc[21] += lam; acc[28] += lam; acc[35] += lam;
             gacc[3] += lam * r.x; gacc[4] += lam * r.y; gacc[5] += lam * r.z;
             er += dot3(r, r);
         }
-        for (int f = in.in_ptr[k] + g; f < in.in_ptr[k + 1]; f += 16) {   // in-edge j -> k: J_k = [[y]x | -I]
+        for (int f = in.in_ptr[k] + g; f < in.in_ptr[k + 1]; f += L) {   // in-edge j -> k: J_k = [[y]x | -I]
             float3 y, r;
             arap_edge(in, in.in_list[f], k, y, r);
             const float yy = dot3(y, y);
@@ -118,10 +152,12 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
         }
     }
 #pragma unroll
-    for (int t = 0; t < 36; ++t) acc[t] = row16_sum(acc[t]);
+    for (int t = 0; t < 36; ++t) acc[t] = group_sum<L>(acc[t]);
+    if (diag) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) gacc[t] = row16_sum(gacc[t]);
-    er = row16_sum(er);
+        for (int t = 0; t < 6; ++t) gacc[t] = group_sum<L>(gacc[t]);
+        er = group_sum<L>(er);
+    }
     if (active && diag) {
 #pragma unroll
         for (int a = 0; a < 6; ++a) acc[7 * a] += in.mu;
@@ -132,31 +168,39 @@ __global__ void __launch_bounds__(16 * kFoldGroups) k_asm_fold(Batch wl) {
         }
     }
     if (active) {
-        // every lane of the group holds the block: lane g stores float4 g of
-        // the block into its row of the product (g < 9) and float4 g - 9 of
-        // the transpose into the column's row (9 <= g; g < 2 take float4 7, 8);
-        // the selects keep every register index a compile-time constant
-        const int vu = g < 9 ? g : 0;
-        const int vt = g < 9 ? 7 + g : g - 9;   // g < 2: float4 7 or 8; 9 <= g: float4 0..6
-        float u4[4], t4[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float su = acc[e], st = acc[6 * e];
-#pragma unroll
-            for (int v = 1; v < 9; ++v) {
-                const int q = 4 * v + e;             // element q of the block, row-major
-                su = (vu == v) ? acc[q] : su;
-                st = (vt == v) ? acc[6 * (q % 6) + q / 6] : st;
-            }
-            u4[e] = su;
-            t4[e] = st;
-        }
-        const float4 fu4 = make_float4(u4[0], u4[1], u4[2], u4[3]);
-        const float4 ft4 = make_float4(t4[0], t4[1], t4[2], t4[3]);
+        // every lane of the group holds the block: lane g stores float4s g,
+        // g + L, ... of the block into its row of the product and (off the
+        // diagonal) those of the transpose into the column's row
         float* Hf = in.Hf;
-        if (g < 9) reinterpret_cast<float4*>(Hf + (size_t)in.slot_u[b] * 36)[g] = fu4;
-        if (!diag && (g >= 9 || g < 2)) reinterpret_cast<float4*>(Hf + (size_t)in.slot_t[b] * 36)[vt] = ft4;
-        if ((diag || capture) && g < 9) reinterpret_cast<float4*>(in.H + (size_t)b * 36)[g] = fu4;
+#pragma unroll
+        for (int s = 0; s * L < 9; ++s) {
+            const int v = g + s * L;
+            if (v < 9) {
+                const float4 fu4 = pick4<L, false>(acc, v, s);
+                reinterpret_cast<float4*>(Hf + (size_t)in.slot_u[b] * 36)[v] = fu4;
+                if (diag || capture) reinterpret_cast<float4*>(in.H + (size_t)b * 36)[v] = fu4;
+                if (!diag) reinterpret_cast<float4*>(Hf + (size_t)in.slot_t[b] * 36)[v] = pick4<L, true>(acc, v, s);
+            }
+        }
+    }
+}
+
+// Diagonal blocks first, one per 16-lane group (node order, kFoldGroups per
+// workgroup); then the off-diagonal ones, which have few segments each, one
+// per 4-lane group (kFoldOffGroups per workgroup).
+__global__ void __launch_bounds__(256) k_asm_fold(Batch wl) {
+    const Where at = locate(wl);
+    const FrameDesc in = *wl.d[at.s];
+    const bool capture = wl.it[at.s] == in.debug_iter;
+    const int dtiles = cdiv(in.nn, kFoldGroups);
+    if (at.tile < dtiles) {
+        const int gi = at.tile * kFoldGroups + (threadIdx.x >> 4);
+        const bool active = gi < in.nn;
+        fold_block<16>(in, capture, active, true, active ? in.row_ptr[gi] : 0, threadIdx.x & 15);
+    } else {
+        const int gi = (at.tile - dtiles) * kFoldOffGroups + (threadIdx.x >> 2);
+        const bool active = gi < in.noff;
+        fold_block<kFoldOffLanes>(in, capture, active, false, active ? in.offlist[gi] : 0, threadIdx.x & 3);
     }
 }
 
@@ -177,7 +221,7 @@ void launch_offlist(int nb, const int* blk_row, const int* col_idx, int* offlist
 void launch_asm_stage(int stage, const Batch& b, hipStream_t st) {
     const int grid = b.off[b.n];
     if (grid <= 0) return;
-    if (stage == kStAsmFold) hipLaunchKernelGGL(k_asm_fold, dim3(grid), dim3(16 * kFoldGroups), 0, st, b);
+    if (stage == kStAsmFold) hipLaunchKernelGGL(k_asm_fold, dim3(grid), dim3(256), 0, st, b);
 }
 
 }  // namespace swgn

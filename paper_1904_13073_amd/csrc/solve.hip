@@ -461,8 +461,21 @@ __device__ __forceinline__ RowAcc row_products(const FrameDesc& a, int i, int ro
     return RowAcc{au, av};
 }
 
+// Sum of a value that only lanes 0-5 hold (every other lane holds +0): the
+// value the wave butterfly 32, 16, ..., 1 gives, valid in lanes 0-7. Its
+// first three steps only add +0, which turns -0 into +0, as one addition of
+// +0 does.
+__device__ __forceinline__ double low6_sum(double v) {
+    v += 0.0;
+    v += xchg<4>(v);
+    v += xchg<2>(v);
+    v += xchg<1>(v);
+    return v;
+}
+
 // Stores u_i, v_i of a row and returns the row's three products
-// (z.u, z.v + p.u, p.v over its 6 entries, summed over the wave).
+// (z.u, z.v + p.u, p.v over its 6 entries, summed over lanes 0-5; valid in
+// lane 0).
 struct RowProducts {
     double c1, c2, c3;
 };
@@ -478,7 +491,7 @@ __device__ __forceinline__ RowProducts store_row(const FrameDesc& a, int i, int 
         c2 = (double)zo * (double)ra.v + (double)po * (double)ra.u;
         c3 = (double)po * (double)ra.v;
     }
-    return RowProducts{wave_sum(c1), wave_sum(c2), wave_sum(c3)};
+    return RowProducts{low6_sum(c1), low6_sum(c2), low6_sum(c3)};
 }
 
 // Partial of a workgroup's 8 rows (kSpmvPart): the in-order sum of its rows'

@@ -25,11 +25,13 @@ constexpr int kMaxPcg = 4096;
 constexpr int kDepthTile = 16;        // 16 x 16 pixels per workgroup
 constexpr int kWarpBlock = 256;       // surfels per workgroup
 constexpr int kCorrBlock = 256;
-// Surfels per correspondence pack (and at most per segment): small enough that
-// the pack's Jacobian rows and output staging stay under 32 KB of LDS, so five
+// Surfels per correspondence pack (and at most per segment): the pack's
+// Jacobian rows (28.8 KB) and the waves' output staging (10 KB) let four
 // workgroups share a CU.
 constexpr int kCorrPack = 232;
-constexpr int kFoldGroups = 16;       // blocks per workgroup (16 lanes each)
+constexpr int kFoldGroups = 16;       // diagonal blocks per fold workgroup (16 lanes each)
+constexpr int kFoldOffLanes = 4;      // lanes per off-diagonal block
+constexpr int kFoldOffGroups = 256 / kFoldOffLanes;   // off-diagonal blocks per fold workgroup
 constexpr int kSolveBlock = 256;      // 32 nodes x 8 lanes; the finish may take 2 nodes per lane group
 constexpr int kSolveNodes = 32;       // nodes per initialisation / finishing workgroup
 constexpr int kSpmvRows = 8;          // product workgroup: 8 block rows, 8 waves of 1 or 4 waves of 2
@@ -190,7 +192,7 @@ inline int stage_tiles(int stage, const FrameDesc& d, int variant = 0) {
         case kStWarp: return cdiv(d.ns, kWarpBlock);
         case kStCorr: return corr_tiles(d);
         case kStAsmSeg: return 0;     // the segment Gram matrices are formed by the correspondence kernel
-        case kStAsmFold: return cdiv(d.nn + d.noff, kFoldGroups);
+        case kStAsmFold: return cdiv(d.nn, kFoldGroups) + cdiv(d.noff, kFoldOffGroups);
         case kStPcgInit: return solve_tiles(d);
         case kStSpmv: return cdiv(d.nn, kSpmvRows);
         case kStUpdate: return cdiv(d.nn, (variant & kVarWide) ? 2 * kSolveNodes : kSolveNodes);
