@@ -87,8 +87,10 @@ def kernel_bytes(ns, nn, nb, npx, lay):
         "pcg_step": 144.0 * nb + 288.0 * nn + 12 * 24.0 * nn,
         # per entry: sub-block 144 and its two offsets 8; per diagonal block its
         # J^T r pieces (24 per entry, counted once per node); blocks out (upper
-        # and both explicit-row copies), gradient out
-        "asm_fold": 152.0 * lay["fold_entries"] + 24.0 * nn * 4 + 144.0 * (2 * nb - nn) + 144.0 * nn + 28.0 * nn,
+        # and both explicit-row copies), gradient out; the start of PCG: FP64
+        # inverse and r, z, p, x out
+        "asm_fold": 152.0 * lay["fold_entries"] + 24.0 * nn * 4 + 144.0 * (2 * nb - nn) + 144.0 * nn + 28.0 * nn
+                    + 288.0 * nn + 4 * 24.0 * nn,
         # diagonal blocks and gradient in; FP64 inverses and r, z, p, x out
         "pcg_init": 144.0 * nn + 24.0 * nn + 288.0 * nn + 4 * 24.0 * nn,
         # upper blocks once (each is used for a row and, transposed, a column),
@@ -115,10 +117,11 @@ def replay_us(bx, streams, pcg_iters, reps=200):
 
 def launches_per_frame(G, P, fused):
     """Launches of each kernel per frame: one fused step per PCG iteration
-    after the first products, or a product and a finish launch; the node
-    update rides on the last finish (its own launch only without PCG)."""
+    after the first products, or a product and a finish launch; the start of
+    PCG rides on the fold and the node update on the last finish (its own
+    launch only without PCG)."""
     import numpy as np
-    return np.array([1, G, G, G * P if fused else 0, G, G if fused else G * P, 0 if fused else G * P,
+    return np.array([1, G, G, G * P if fused else 0, 0, G if fused else G * P, 0 if fused else G * P,
                      0 if P > 0 else G, G], dtype=float)
 
 

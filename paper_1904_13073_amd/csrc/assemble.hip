@@ -82,7 +82,8 @@ __device__ __forceinline__ float4 pick4(const float (&acc)[36], int v, int s) {
 // upper copy H for the diagonal (all blocks when captured), g and the
 // regulariser energy for the diagonal.
 template <int L>
-__device__ __forceinline__ void fold_block(const FrameDesc& in, bool capture, bool active, bool diag, int b, int g) {
+__device__ __forceinline__ void fold_block(const FrameDesc& in, bool capture, bool active, bool diag, int b, int g,
+                                           double& rho, double& rr) {
     const int k = in.blk_row[b], l = in.col_idx[b];
     const float lam = in.lambda;
     float acc[36];
@@ -183,6 +184,27 @@ __device__ __forceinline__ void fold_block(const FrameDesc& in, bool capture, bo
             }
         }
     }
+    rho = 0.0;
+    rr = 0.0;
+    if (diag) {
+        // the start of PCG for node k: lanes 0-5 of the group take the rows
+        // of the block (lanes 8-15 form an 8-lane group of their own with no
+        // rows); every lane holds the whole block, so a lane's row is picked
+        // by selects
+        const bool on = active && g < 6;
+        float hrow[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float v = acc[c];
+#pragma unroll
+            for (int q = 1; q < 6; ++q) v = (g == q) ? acc[6 * q + c] : v;
+            hrow[c] = on ? v : 0.f;
+        }
+        float gk = gacc[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q) gk = (g == q) ? gacc[q] : gk;
+        pcg_start_lane(in, active ? k : in.nn, g, on, hrow, on ? gk : 0.f, rho, rr);
+    }
 }
 
 // Diagonal blocks first, one per 16-lane group (node order, kFoldGroups per
@@ -193,14 +215,36 @@ __global__ void __launch_bounds__(256) k_asm_fold(Batch wl) {
     const FrameDesc in = *wl.d[at.s];
     const bool capture = wl.it[at.s] == in.debug_iter;
     const int dtiles = cdiv(in.nn, kFoldGroups);
+    double rho, rr;
     if (at.tile < dtiles) {
-        const int gi = at.tile * kFoldGroups + (threadIdx.x >> 4);
+        __shared__ double stg[2][kFoldGroups][8];
+        const int grp = threadIdx.x >> 4, g = threadIdx.x & 15;
+        const int gi = at.tile * kFoldGroups + grp;
         const bool active = gi < in.nn;
-        fold_block<16>(in, capture, active, true, active ? in.row_ptr[gi] : 0, threadIdx.x & 15);
+        fold_block<16>(in, capture, active, true, active ? in.row_ptr[gi] : 0, g, rho, rr);
+        // partials of r_0.z_0 and r_0.r_0 per 8 nodes, summed in the layout of
+        // a wave of 8 nodes x 8 lanes (the start kernel's)
+        if (g < 8) {
+            stg[0][grp][g] = rho;
+            stg[1][grp][g] = rr;
+        }
+        __syncthreads();
+        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+        if (wave < kFoldGroups / 8) {
+            double s0 = stg[0][8 * wave + (lane >> 3)][lane & 7];
+            double s1 = stg[1][8 * wave + (lane >> 3)][lane & 7];
+            s0 = wave_sum(s0);
+            s1 = wave_sum(s1);
+            const int part = at.tile * (kFoldGroups / 8) + wave;
+            if (lane == 0 && part < solve_parts(in)) {
+                in.part_rho.b0[part] = s0;
+                in.part_rr.b0[part] = s1;
+            }
+        }
     } else {
         const int gi = (at.tile - dtiles) * kFoldOffGroups + (threadIdx.x >> 2);
         const bool active = gi < in.noff;
-        fold_block<kFoldOffLanes>(in, capture, active, false, active ? in.offlist[gi] : 0, threadIdx.x & 3);
+        fold_block<kFoldOffLanes>(in, capture, active, false, active ? in.offlist[gi] : 0, threadIdx.x & 3, rho, rr);
     }
 }
 

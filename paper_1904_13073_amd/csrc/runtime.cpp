@@ -742,7 +742,7 @@ void enqueue_iteration(Executor& ex, const std::vector<sw_stream>& ss, const std
         SWGN_HIP(hipMemcpyAsync(s->dbg_H, h.H, sizeof(float) * 36 * h.nb, hipMemcpyDeviceToDevice, st));
         SWGN_HIP(hipMemcpyAsync(s->dbg_g, h.g, sizeof(float) * 6 * h.nn, hipMemcpyDeviceToDevice, st));
     }
-    run_stage(ex, kStPcgInit, ss, its, 0, nullptr, timing, ev);
+    // (the fold also starts PCG: block-Jacobi inverses, r_0, z_0, x = 0)
     int64_t rows = 0;
     for (int i = 0; i < n; ++i)
         if (its[i] >= 0) rows += ss[i]->h.nn;

@@ -96,59 +96,23 @@ __device__ __forceinline__ void update_from_lanes(const FrameDesc& a, int k, int
 }
 
 
-// 8 lanes per node: lane a < 6 holds row a of [H_kk + mu I | I]; FP64
-// Gauss-Jordan elimination leaves row a of the inverse. Without pivoting the
-// pivots of a symmetric matrix are all positive exactly when it is positive
-// definite, which is checked. Then r_0 = -g, z_0 = M r_0, x = 0 and the
-// direction before the first, p_{-1} = 0.
+// The start of PCG (pcg_start_lane), 8 lanes per node, 32 nodes per
+// workgroup, as a launch of its own: the solve forms it inside the assembly
+// fold; this launch serves stage replays.
 __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
     const Where at = locate(b);
     const FrameDesc a = *b.d[at.s];
     const int gid = at.tile * kSolveBlock + threadIdx.x;
-    const int k = gid >> 3, row = gid & 7, base = threadIdx.x & ~7;
+    const int k = gid >> 3, row = gid & 7;
     const int lane = threadIdx.x % kWave;
     const bool on = (k < a.nn) && (row < 6);
-    double m[12];
+    float hrow[6];
     const float* A = a.H + (size_t)(k < a.nn ? a.row_ptr[k] : 0) * 36;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        m[c] = on ? (double)A[row * 6 + c] : 0.0;
-        m[6 + c] = (on && c == row) ? 1.0 : 0.0;
-    }
-    bool ok = true;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double pr[12];
-#pragma unroll
-        for (int j = 0; j < 12; ++j) pr[j] = bcast8(m[j], c);
-        const double piv = pr[c];
-        ok = ok && (piv > 0.0);
-        const double inv = 1.0 / (piv > 0.0 ? piv : 1.0);
-        const double f = (row == c) ? 0.0 : m[c] * inv;
-#pragma unroll
-        for (int j = 0; j < 12; ++j) m[j] = (row == c) ? m[j] * inv : m[j] - f * pr[j];
-    }
-    if (k < a.nn && row == 0 && !ok) atomicOr(a.flags, 1);
-    float rc = on ? -a.g[6 * k + row] : 0.f;
-    double zc = 0.0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const float rj = bcast8(rc, j);
-        const double mj = ok ? m[6 + j] : (j == row ? 1.0 : 0.0);
-        zc += mj * (double)rj;
-        if (on) a.Minv[(size_t)k * 36 + row * 6 + j] = mj;
-    }
-    double rho = 0.0, rr = 0.0;
-    if (on) {
-        const float zf = (float)zc;
-        const int t = 6 * k + row;
-        a.r.b0[t] = rc;
-        a.z.b0[t] = zf;
-        a.p.b1[t] = 0.f;
-        a.x[t] = 0.f;
-        rho = (double)rc * (double)zf;
-        rr = (double)rc * (double)rc;
-    }
+    for (int c = 0; c < 6; ++c) hrow[c] = on ? A[row * 6 + c] : 0.f;
+    const float gk = on ? a.g[6 * k + row] : 0.f;
+    double rho, rr;
+    pcg_start_lane(a, k, row, on, hrow, gk, rho, rr);
     // partials per 8 nodes: one wave's sums
     rho = wave_sum(rho);
     rr = wave_sum(rr);
@@ -157,28 +121,6 @@ __global__ void __launch_bounds__(kSolveBlock) k_pcg_init(Batch b) {
         a.part_rho.b0[part] = rho;
         a.part_rr.b0[part] = rr;
     }
-}
-
-// Sum of n partials in the fixed shape of a 256-thread reduction (thread t
-// adds part[t], part[t + 256], ..., then the wave sums, then the 4 waves in
-// order), whatever the workgroup size; result in every thread.
-__device__ __forceinline__ double reduce_parts256(const double* __restrict__ part, int n, double* sh) {
-    double v = 0.0;
-    if (threadIdx.x < 256)
-        for (int i = threadIdx.x; i < n; i += 256) v += part[i];
-    v = wave_sum(v);
-    const int w = threadIdx.x / kWave;
-    if ((threadIdx.x % kWave) == 0 && w < 4) sh[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < 4; ++q) t += sh[q];
-        sh[32] = t;
-    }
-    __syncthreads();
-    const double r = sh[32];
-    __syncthreads();
-    return r;
 }
 
 // Scalars that finish PCG iteration k (rho_k = r_k.z_k from the node partials,

@@ -298,6 +298,58 @@ __device__ __forceinline__ void iteration_stats(const FrameDesc& a, int it) {
     __syncthreads();
 }
 
+// Start of PCG for one node k by a group of 8 lanes (lane `row` < 6 holds row
+// `row` of H_kk + mu I in hrow and g_k[row] in gk; on = the lane carries a row
+// of a node that exists): the block-Jacobi inverse by FP64 Gauss-Jordan
+// elimination (no pivoting: the pivots of a symmetric matrix are all positive
+// exactly when it is positive definite, which is checked; failure bit 1),
+// then r_0 = -g, z_0 = M r_0, x = 0 and the direction before the first,
+// p_{-1} = 0. Returns the lane's terms of r_0.z_0 and r_0.r_0.
+__device__ __forceinline__ void pcg_start_lane(const FrameDesc& a, int k, int row, bool on, const float (&hrow)[6],
+                                               float gk, double& rho, double& rr) {
+    double m[12];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        m[c] = on ? (double)hrow[c] : 0.0;
+        m[6 + c] = (on && c == row) ? 1.0 : 0.0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double pr[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) pr[j] = bcast8(m[j], c);
+        const double piv = pr[c];
+        ok = ok && (piv > 0.0);
+        const double inv = 1.0 / (piv > 0.0 ? piv : 1.0);
+        const double f = (row == c) ? 0.0 : m[c] * inv;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) m[j] = (row == c) ? m[j] * inv : m[j] - f * pr[j];
+    }
+    if (k < a.nn && row == 0 && !ok) atomicOr(a.flags, 1);
+    const float rc = on ? -gk : 0.f;
+    double zc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float rj = bcast8(rc, j);
+        const double mj = ok ? m[6 + j] : (j == row ? 1.0 : 0.0);
+        zc += mj * (double)rj;
+        if (on) a.Minv[(size_t)k * 36 + row * 6 + j] = mj;
+    }
+    rho = 0.0;
+    rr = 0.0;
+    if (on) {
+        const float zf = (float)zc;
+        const int t = 6 * k + row;
+        a.r.b0[t] = rc;
+        a.z.b0[t] = zf;
+        a.p.b1[t] = 0.f;
+        a.x[t] = 0.f;
+        rho = (double)rc * (double)zf;
+        rr = (double)rc * (double)rc;
+    }
+}
+
 // Launchers (one per kernel file); grid = b.off[b.n] workgroups.
 void launch_frame_stage(int stage, const Batch& b, const DepthIn* depth, hipStream_t st);
 void launch_asm_stage(int stage, const Batch& b, hipStream_t st);
