@@ -129,10 +129,13 @@ typedef struct sw_frame_stats {
     float stage_us[12];        /* with stage_timing: microseconds per kernel, summed
                                   over the frame: [0] depth preprocessing, [1] warp +
                                   index map, [2] correspondence + Jacobians +
-                                  segment Gram matrices, [3] fused PCG steps,
-                                  [4] block-Jacobi + PCG start, [5] PCG
-                                  products, [6] PCG finishes,
-                                  [7] node update, [8] assembly of the blocks,
+                                  segment Gram matrices, [3] fused PCG steps
+                                  (the last of an iteration also moves the
+                                  nodes), [4] block-Jacobi + PCG start (0: it
+                                  runs inside the assembly), [5] PCG products,
+                                  [6] PCG finishes, [7] node update of streams
+                                  without PCG iterations, [8] assembly of the
+                                  blocks with the block-Jacobi + PCG start,
                                   [9] rigid warp + index map, [10] rigid 6x6 sums,
                                   [11] rigid solve + composition; measured with HIP
                                   events */
@@ -351,7 +354,8 @@ sw_status sw_solve_batch(sw_batch b, const sw_stream* streams, int32_t n,
  * overwritten (their warp fields are not); use after a solve, so that the
  * stage's inputs hold a real frame. stage numbers as in stage_us: 1 warp +
  * index map, 2 correspondence + Jacobians + segment Gram matrices,
- * 4 block-Jacobi + PCG start, 5 PCG products (u = A z, v = A p_prev),
+ * 4 block-Jacobi + PCG start as a launch of its own (a solve runs it inside
+ * the fold), 5 PCG products (u = A z, v = A p_prev),
  * 6 PCG finish (scalars, x, r, z, p), 8 block fold, 13 fused PCG step
  * (finish of iteration pcg_it - 1 and products of pcg_it in one launch,
  * pcg_it >= 1); others give SW_EINVAL. pcg_it selects the PCG iteration for
@@ -361,8 +365,8 @@ sw_status sw_profile_stage(sw_batch b, const sw_stream* streams, int32_t n, int3
 
 /* Autotuner: for the shape bucket of this batch (stream count and the
  * powers of two of its total surfels and nodes) time each per-frame stage
- * (1 warp, 2 correspondence, 8 fold, 4 PCG start, 5 product, 6 finish,
- * 13 fused step) reps times back to back in each launch variant and keep the
+ * (1 warp, 2 correspondence, 8 fold, 5 product, 6 finish, 13 fused step)
+ * reps times back to back in each launch variant and keep the
  * fastest for later solves of batches in that bucket on this executor.
  * Variants: the tile order — linear, or XCD-contiguous (the workgroups an XCD
  * runs take one contiguous range of tiles, keeping a stream's data in few L2

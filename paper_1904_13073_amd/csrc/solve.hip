@@ -135,9 +135,10 @@ struct PcgScalars {
     float alpha, beta;
 };
 
-// Four sums of partials at once, each in the fixed shape of reduce_parts256
-// (thread t adds its strided partials, then the wave sums, then the 4 waves
-// in order): one pass of loads and one exchange instead of four.
+// Four sums of partials at once, each in the fixed shape of a 256-thread
+// reduction whatever the workgroup size (thread t < 256 adds part[t],
+// part[t + 256], ..., then the wave sums, then the 4 waves in order): one
+// pass of loads and one exchange instead of four.
 struct Sum4 {
     double s[4];
 };

@@ -372,17 +372,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-// Sum of n partials in a fixed order by one block; result valid in all threads.
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n, double* sh) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
-    double t = block_sum(v, sh);
-    if (threadIdx.x == 0) sh[32] = t;
-    __syncthreads();
-    double r = sh[32];
-    __syncthreads();
-    return r;
-}
 
 // Cross-lane sums with DPP (gfx9): every lane of a 16-lane row ends with the
 // row's sum after mirror, half-mirror and two quad permutations. The order of
