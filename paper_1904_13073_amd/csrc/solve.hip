@@ -1,8 +1,10 @@
 // Linear solve and node update of one Gauss-Newton iteration (Sec. 7, Sec. 8):
 //
-//   pcg_init     block-Jacobi preconditioner (FP64 inverses of H_kk + mu I) and
+//   PCG start    block-Jacobi preconditioner (FP64 inverses of H_kk + mu I) and
 //                the start of preconditioned conjugate gradients on
 //                (J^T J + mu I) delta = -g: r_0 = -g, z_0 = M r_0, x = 0
+//                (pcg_start_lane: in a solve, run by the assembly fold's
+//                diagonal groups; k_pcg_init runs it as a launch of its own)
 //   pcg_spmv     products of iteration i: u_i = A z_i and v_i = A p_{i-1} (one
 //                wave per block row; the row's blocks, transposes written out,
 //                in ELL layout) and the partial sums that give p_i.q_i once
