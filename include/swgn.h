@@ -154,10 +154,14 @@ const char* sw_status_string(sw_status st);
 /* Message of the last failed call on s (empty if none; never NULL). */
 const char* sw_last_error(sw_stream s);
 
-/* Create a stream. hip_stream is the hipStream_t all work is queued on, or
- * NULL for a stream the library creates and destroys. The config is copied.
- * SW_EINVAL: image size <= 0, non-finite or non-positive focal lengths,
- * iteration counts out of range, non-positive sigma, negative weights. */
+/* Create a stream: the state of one depth camera's reconstruction, its
+ * reference surfels and node-graph warp field (Sec. 3, Sec. 4), solved once
+ * per depth frame (Sec. 7, Sec. 8) with the camera intrinsics and solver
+ * parameters of the config (Table 1). hip_stream is the hipStream_t all work
+ * is queued on, or NULL for a stream the library creates and destroys. The
+ * config is copied. SW_EINVAL: image size <= 0, non-finite or non-positive
+ * focal lengths, iteration counts out of range, non-positive sigma, negative
+ * weights. */
 sw_status sw_create_stream(const sw_config* cfg, void* hip_stream, sw_stream* out);
 
 /* Destroy a stream and free its device memory (if it is attached to a
@@ -456,8 +460,9 @@ sw_status sw_server_poll(sw_server sv, uint64_t ticket, int32_t wait_ms, sw_fram
 /* Counters of the server so far. */
 sw_status sw_server_counters(sw_server sv, sw_server_info* out);
 
-/* Copy the node transforms to host memory out (n_nodes x 12 fp32 [R | t]).
- * SW_EINVAL if capacity (in nodes) < n_nodes. */
+/* Copy the node transforms T_j of the warp field (Sec. 3; the result of the
+ * last solve, Sec. 7) to host memory out (n_nodes x 12 fp32 [R | t], caller's
+ * node order). SW_EINVAL if capacity (in nodes) < n_nodes. */
 sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity);
 
 /* Sizes of the current problem (any pointer may be NULL). */
