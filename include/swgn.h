@@ -476,7 +476,7 @@ sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* worksp
 
 /* Work layout chosen at sw_set_node_graph: distinct node sets; segments (runs
  * of surfels with at most 5 nodes in all, each summed into one Gram matrix);
- * packs (runs of whole segments, at most 256 surfels, one workgroup each);
+ * packs (runs of whole segments, at most 232 surfels, one workgroup each);
  * the ELL width of the product's rows; the block fold's entries (one per
  * node pair of a segment); the floats of all segments' Gram output. */
 typedef struct sw_layout {
@@ -485,6 +485,18 @@ typedef struct sw_layout {
 } sw_layout;
 
 sw_status sw_get_layout(sw_stream s, sw_layout* out);
+
+/* Self-check of the segment layout, for tests: sw_set_node_graph cuts the
+ * sorted surfels into segments and packs on the device (greedy cuts walked as
+ * successor chains); this call redoes the cut with the plain sequential walk
+ * on the host, from the same sorted surfels and block pattern, and writes
+ * into differ[9] the number of differing elements (plus any difference in
+ * length) of: segment starts, pair masks, Gram offsets (and their total),
+ * block entry pointers, entry sub-block offsets, entry J^T r offsets, pack
+ * starts, pack first segments, per-surfel node positions. All zero means the
+ * two agree exactly. Synchronises the stream; host memory of order the
+ * surfel count. */
+sw_status sw_check_layout(sw_stream s, int64_t* differ);
 
 /* ---- parity and debug exports (host pointers, caller's surfel order) ---- */
 

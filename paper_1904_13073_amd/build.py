@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libswgn.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["setup.hip", "frame.hip", "assemble.hip", "solve.hip", "fusion.hip", "append.hip", "runtime.cpp", "segments.cpp", "batch.cpp",
+SOURCES = ["setup.hip", "segwalk.hip", "frame.hip", "assemble.hip", "solve.hip", "fusion.hip", "append.hip", "runtime.cpp", "segments.cpp", "batch.cpp",
            "server.cpp"]
 
 FLAGS = [

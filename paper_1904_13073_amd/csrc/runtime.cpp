@@ -247,65 +247,110 @@ void publish_desc(sw_stream s) {
     SWGN_HIP(hipStreamSynchronize(s->exec.st));
 }
 
-// Segments, packs and the block fold's entries (host, once per node set).
+// Segments, packs and the block fold's entries (once per node set, on the
+// device).
 //
 // A segment is a run of consecutive surfels (sorted by node set), at most
-// kCorrBlock long, whose nodes together number at most 5: its Gram matrix
+// kCorrPack long, whose nodes together number at most 5: its Gram matrix
 // [J | r]^T [J | r] (30 Jacobian columns, node blocks by position in the
 // segment's ascending node list, r in column 30) fits one 32x32 MFMA tile.
 // It keeps the 6x6 sub-blocks of the node pairs that share a surfel (bit
 // first(pa) + pb - pa of its 15-bit mask, pa <= pb), then J^T r (30) and
 // r^T r: 36 x pairs + 32 floats from offset seg_off. A pack is a greedy run
-// of whole segments with at most kCorrBlock surfels. Each block's entries
+// of whole segments with at most kCorrPack surfels. Each block's entries
 // list the float offsets of its sub-blocks (and, for a diagonal block, of the
 // matching J^T r piece) in segment order.
-// The segment layout: on the host from the runs of equal node sets (keys and
-// run starts only, a few bytes per run), then each surfel's node positions
-// on the device.
-void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* set_start, int nsets,
-                    const int4* sidx, const int* row_ptr, const int* col_idx, Arena& G, Arena& tmp) {
+// The greedy cuts are successor chains walked on the device (segwalk.hip);
+// the host reads back three sizes (segments; Gram floats, entries and packs;
+// the consistency flag) to size the resident arrays.
+void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* set_start, const int* run_pos,
+                    int nsets, const int4* sidx, const int* row_ptr, const int* col_idx, Arena& G, Arena& tmp) {
     hipStream_t st = s->exec.st;
-    const int ns = h.ns, nn = h.nn;
+    const int ns = h.ns, nb = h.nb;
+    if (kCorrPack > chain_max_hop()) throw HipFail{hipErrorInvalidValue, "segment layout: pack size above the chain hop"};
     uint64_t* d_keys = tmp.alloc<uint64_t>(std::max(1, nsets));
     launch_set_keys(nsets, key, set_start, d_keys, st);
-    std::vector<uint64_t> hkey(nsets);
-    std::vector<int> hstart(nsets + 1), hrow(nn + 1), hcol(h.nb);
-    SWGN_HIP(hipMemcpyAsync(hkey.data(), d_keys, sizeof(uint64_t) * nsets, hipMemcpyDeviceToHost, st));
-    SWGN_HIP(hipMemcpyAsync(hstart.data(), set_start, sizeof(int) * (nsets + 1), hipMemcpyDeviceToHost, st));
-    SWGN_HIP(hipMemcpyAsync(hrow.data(), row_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
-    SWGN_HIP(hipMemcpyAsync(hcol.data(), col_idx, sizeof(int) * h.nb, hipMemcpyDeviceToHost, st));
-    SWGN_HIP(hipStreamSynchronize(st));
-    SegmentLayout L;
-    std::string why;
-    if (!segment_layout_sets(nsets, hkey.data(), hstart.data(), nn, h.nb, hrow.data(), hcol.data(), kCorrPack, L,
-                             why))
-        throw HipFail{hipErrorInvalidValue, why};
-    const int nseg = (int)L.mask.size();
-    auto up = [&](auto* dst, const auto& v) {
-        SWGN_HIP(hipMemcpyAsync(dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice, st));
-    };
-    int* d_seg = G.alloc<int>(L.seg_start.size());
-    uint16_t* d_pos4 = G.alloc<uint16_t>(ns);
-    uint16_t* d_mask = G.alloc<uint16_t>(std::max(1, nseg));
-    uint32_t* d_off = G.alloc<uint32_t>(L.off.size());
-    int* d_ps = G.alloc<int>(L.pack_start.size());
-    int* d_pg = G.alloc<int>(L.pack_seg.size());
-    int* d_ep = G.alloc<int>(L.ent_ptr.size());
-    uint32_t* d_es = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_sub.size()));
-    uint32_t* d_eg = G.alloc<uint32_t>(std::max<size_t>(1, L.ent_grad.size()));
-    int* d_nodes = tmp.alloc<int>(std::max<size_t>(1, L.seg_nodes.size()));
     int* d_bad = tmp.alloc<int>(1);
-    up(d_seg, L.seg_start); up(d_mask, L.mask); up(d_off, L.off);
-    up(d_ps, L.pack_start); up(d_pg, L.pack_seg); up(d_ep, L.ent_ptr); up(d_es, L.ent_sub); up(d_eg, L.ent_grad);
-    up(d_nodes, L.seg_nodes);
+    int* d_cnt = tmp.alloc<int>(2);
+    unsigned long long* d_units = tmp.alloc<unsigned long long>(1);
     launch_fill_i32(d_bad, 1, 0, st);
+    launch_fill_i32(reinterpret_cast<int*>(d_units), 2, 0, st);
+    int* work = tmp.alloc<int>(chain_work_ints(ns, kCorrPack));
+    int* scan_tmp = tmp.alloc<int>(scan_tmp_size(std::max(ns, nb) + 16));
+
+    // segment cuts
+    int* nxt = tmp.alloc<int>(ns);
+    int* cuts = tmp.alloc<int>(ns);
+    launch_seg_next(ns, nsets, d_keys, set_start, run_pos, kCorrPack, nxt, st);
+    chain_from_zero(nxt, ns, kCorrPack, cuts, d_cnt, work, d_bad, st);
+    const int nseg = read_scalar(d_cnt, st);
+    if (read_scalar(d_bad, st) != 0 || nseg < 1 || nseg > ns)
+        throw HipFail{hipErrorInvalidValue, "segment layout: the segment cut is inconsistent"};
+    int* d_seg = G.alloc<int>(nseg + 1);
+    SWGN_HIP(hipMemcpyAsync(d_seg, cuts, sizeof(int) * nseg, hipMemcpyDeviceToDevice, st));
+    launch_fill_i32(d_seg + nseg, 1, ns, st);
+
+    // per segment: nodes, pair mask, output offsets, entry bases; packs
+    int* d_nodes = tmp.alloc<int>(5 * (size_t)nseg);
+    uint16_t* d_mask = G.alloc<uint16_t>(nseg);
+    int* units = tmp.alloc<int>(nseg);
+    int* npairs = tmp.alloc<int>(nseg);
+    launch_seg_info(nseg, d_seg, run_pos, d_keys, d_nodes, d_mask, units, npairs, d_units, d_bad, st);
+    int* off_units = tmp.alloc<int>(nseg + 1);
+    int* ebase = tmp.alloc<int>(nseg + 1);
+    exclusive_scan(units, off_units, nseg, scan_tmp, st);
+    exclusive_scan(npairs, ebase, nseg, scan_tmp, st);
+    int* pnext = tmp.alloc<int>(nseg);
+    int* pcuts = tmp.alloc<int>(nseg);
+    launch_pack_next(nseg, d_seg, kCorrPack, pnext, st);
+    chain_from_zero(pnext, nseg, kCorrPack, pcuts, d_cnt + 1, work, d_bad, st);
+    unsigned long long total_units = 0;
+    int sizes[3] = {0, 0, 0};                  // entries, packs, flag
+    SWGN_HIP(hipMemcpyAsync(&total_units, d_units, sizeof(total_units), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(&sizes[0], ebase + nseg, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(&sizes[1], d_cnt + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(&sizes[2], d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipStreamSynchronize(st));
+    if (sizes[2] != 0) throw HipFail{hipErrorInvalidValue, "segment layout: a segment has more than 5 nodes"};
+    if (total_units >= (1ull << 30)) throw HipFail{hipErrorInvalidValue, "segment Gram storage exceeds 2^32 floats"};
+    const int ne = sizes[0], npack = sizes[1];
+    if (ne < 1 || npack < 1 || npack > nseg)
+        throw HipFail{hipErrorInvalidValue, "segment layout: the pack cut is inconsistent"};
+    uint32_t* d_off = G.alloc<uint32_t>(nseg + 1);
+    launch_seg_off(nseg, off_units, d_off, st);
+
+    // the fold's entries, sorted by block (stable in segment order)
+    const int npad = pow2_at_least(ne, 1024);
+    uint64_t* ekey = tmp.alloc<uint64_t>(npad);
+    uint32_t* eval = tmp.alloc<uint32_t>(npad);
+    uint32_t* esub = tmp.alloc<uint32_t>(ne);
+    uint32_t* egrad = tmp.alloc<uint32_t>(ne);
+    int* bcount = tmp.alloc<int>(nb);
+    launch_fill_i32(bcount, nb, 0, st);
+    launch_seg_entries(nseg, nb, npad, d_nodes, d_mask, d_off, ebase, ne, row_ptr, col_idx, ekey, eval, esub, egrad,
+                       bcount, d_bad, st);
+    sort_pairs(ekey, eval, npad, st);
+    int* d_ep = G.alloc<int>(nb + 1);
+    exclusive_scan(bcount, d_ep, nb, scan_tmp, st);
+    uint32_t* d_es = G.alloc<uint32_t>(ne);
+    uint32_t* d_eg = G.alloc<uint32_t>(ne);
+    launch_ent_gather(ne, eval, esub, egrad, d_es, d_eg, st);
+
+    // packs
+    int* d_pg = G.alloc<int>(npack + 1);
+    int* d_ps = G.alloc<int>(npack + 1);
+    SWGN_HIP(hipMemcpyAsync(d_pg, pcuts, sizeof(int) * npack, hipMemcpyDeviceToDevice, st));
+    launch_pack_arrays(npack, nseg, ns, d_seg, d_pg, d_ps, st);
+
+    // each surfel's node positions in its segment
+    uint16_t* d_pos4 = G.alloc<uint16_t>(ns);
     launch_seg_pos4(ns, nseg, d_seg, d_nodes, sidx, d_pos4, d_bad, st);
     SWGN_HIP(hipGetLastError());
     if (read_scalar(d_bad, st) != 0)
-        throw HipFail{hipErrorInvalidValue, "segment layout: a surfel's slot nodes differ from its node set"};
+        throw HipFail{hipErrorInvalidValue, "segment layout: a block or a surfel's node is missing from its segment"};
     h.nseg = nseg;
-    h.npack = (int)L.pack_start.size() - 1;
-    h.part_floats = (int64_t)L.total;
+    h.npack = npack;
+    h.part_floats = 4 * (int64_t)total_units;
     h.seg_start = d_seg;
     h.pos4 = d_pos4;
     h.seg_mask = d_mask;
@@ -315,7 +360,7 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* s
     h.ent_ptr = d_ep;
     h.ent_sub = d_es;
     h.ent_grad = d_eg;
-    s->nent = (int64_t)L.ent_sub.size();
+    s->nent = ne;
 }
 
 // The library's node order: ascending Morton code of the reference positions
@@ -527,7 +572,7 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
     launch_offlist(h.nb, blk_row, col_idx, offlist, st);
     h.offlist = offlist;
 
-    build_segments(s, h, key, set_start, s->nsets, sidx, row_ptr, col_idx, G, tmp);
+    build_segments(s, h, key, set_start, fpos, s->nsets, sidx, row_ptr, col_idx, G, tmp);
 
     // in-edges of every node (j with the node in N_j), ascending j
     const int npad_i = pow2_at_least(8 * (int64_t)nn, 1024);
@@ -1595,6 +1640,67 @@ sw_status sw_get_layout(sw_stream s, sw_layout* out) {
     out->fold_entries = s->nent;
     out->gram_floats = s->h.part_floats;
     return SW_OK;
+}
+
+sw_status sw_check_layout(sw_stream s, int64_t* differ) {
+    if (!s) return SW_EINVAL;
+    if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
+    if (!differ) return fail(s->err, SW_EINVAL, "NULL output");
+    return guarded(s->err, [&]() -> sw_status {
+        const FrameDesc& h = s->h;
+        const int ns = h.ns, nn = h.nn, nb = h.nb;
+        hipStream_t st = s->exec.st;
+        std::vector<int4> idx(ns);
+        std::vector<int> rp(nn + 1), ci(nb);
+        SWGN_HIP(hipMemcpyAsync(idx.data(), h.idx, sizeof(int4) * ns, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(rp.data(), h.row_ptr, sizeof(int) * (nn + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(ci.data(), h.col_idx, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        // the sequential walk over the surfels as sorted on the device
+        std::vector<uint64_t> key(ns);
+        std::vector<int32_t> idx4(4 * (size_t)ns);
+        for (int i = 0; i < ns; ++i) {
+            int t[4] = {idx[i].x, idx[i].y, idx[i].z, idx[i].w};
+            for (int k = 0; k < 4; ++k) idx4[4 * (size_t)i + k] = t[k];
+            std::sort(t, t + 4);
+            key[i] = ((uint64_t)t[0] << 48) | ((uint64_t)t[1] << 32) | ((uint64_t)t[2] << 16) | (uint64_t)t[3];
+        }
+        SegmentLayout L;
+        std::string why;
+        if (!segment_layout(ns, nn, nb, key.data(), idx4.data(), rp.data(), ci.data(), kCorrPack, L, why))
+            return fail(s->err, SW_EINVAL, "host segment walk: " + why);
+        const int nseg = h.nseg, npack = h.npack;
+        const int64_t ne = s->nent;
+        std::vector<int> seg(nseg + 1), ep(nb + 1), ps(npack + 1), pg(npack + 1);
+        std::vector<uint16_t> mask(nseg), pos4(ns);
+        std::vector<uint32_t> off(nseg + 1), es(ne), eg(ne);
+        SWGN_HIP(hipMemcpyAsync(seg.data(), h.seg_start, sizeof(int) * (nseg + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(mask.data(), h.seg_mask, sizeof(uint16_t) * nseg, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(off.data(), h.seg_off, sizeof(uint32_t) * (nseg + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(ep.data(), h.ent_ptr, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(es.data(), h.ent_sub, sizeof(uint32_t) * ne, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(eg.data(), h.ent_grad, sizeof(uint32_t) * ne, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(ps.data(), h.pack_start, sizeof(int) * (npack + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(pg.data(), h.pack_seg, sizeof(int) * (npack + 1), hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipMemcpyAsync(pos4.data(), h.pos4, sizeof(uint16_t) * ns, hipMemcpyDeviceToHost, st));
+        SWGN_HIP(hipStreamSynchronize(st));
+        auto cmp = [](const auto& a, const auto& b) -> int64_t {
+            const size_t n = std::min(a.size(), b.size());
+            int64_t d = (int64_t)std::max(a.size(), b.size()) - (int64_t)n;
+            for (size_t i = 0; i < n; ++i) d += (int64_t)(a[i] != b[i]);
+            return d;
+        };
+        differ[0] = cmp(seg, L.seg_start);
+        differ[1] = cmp(mask, L.mask);
+        differ[2] = cmp(off, L.off) + (int64_t)((uint64_t)h.part_floats != L.total);
+        differ[3] = cmp(ep, L.ent_ptr);
+        differ[4] = cmp(es, L.ent_sub);
+        differ[5] = cmp(eg, L.ent_grad);
+        differ[6] = cmp(ps, L.pack_start);
+        differ[7] = cmp(pg, L.pack_seg);
+        differ[8] = cmp(pos4, L.pos4);
+        return SW_OK;
+    });
 }
 
 sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes) {

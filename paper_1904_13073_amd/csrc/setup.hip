@@ -375,48 +375,11 @@ __global__ void k_row_fill(int nn, const uint32_t* __restrict__ bm, int words, c
     }
 }
 
-__device__ __forceinline__ int find_block(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
-                                          int r, int c) {
-    int lo = row_ptr[r], hi = row_ptr[r + 1] - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (col_idx[mid] < c) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// Per run, its 10 (block, run, position pair) entries as sortable keys.
-__global__ void k_run_entries(int nruns, const uint64_t* __restrict__ key,
-        const int* __restrict__ run_start, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
-        uint64_t* __restrict__ ekey, uint32_t* __restrict__ eval, int* __restrict__ ecount) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nruns) return;
-    uint64_t k = key[run_start[r]];
-    int t[4] = {(int)(k >> 48), (int)((k >> 32) & 0xffff), (int)((k >> 16) & 0xffff), (int)(k & 0xffff)};
-    int e = 10 * r;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int b = a; b < 4; ++b) {
-            int blk = find_block(row_ptr, col_idx, t[a], t[b]);
-            ekey[e] = ((uint64_t)blk << 32) | (uint64_t)(((uint32_t)r << 4) | (uint32_t)(a << 2) | (uint32_t)b);
-            eval[e] = 0;
-            atomicAdd(&ecount[blk], 1);
-            ++e;
-        }
-    }
-}
-
 __global__ void k_pad_keys(uint64_t* __restrict__ key, uint32_t* __restrict__ val, int from, int to) {
     int i = from + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= to) return;
     key[i] = ~0ull;
     val[i] = 0xffffffffu;
-}
-
-__global__ void k_entries_store(int ne, const uint64_t* __restrict__ ekey, uint32_t* __restrict__ ent) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ne) ent[i] = (uint32_t)(ekey[i] & 0xffffffffull);
 }
 
 // Transposed uses of the upper off-diagonal blocks, keyed by (col, row).
@@ -576,22 +539,6 @@ void launch_row_fill(int nn, const uint32_t* bm, int words, const int* row_ptr, 
                      hipStream_t st) {
     hipLaunchKernelGGL(k_row_fill, dim3((nn + 255) / 256), dim3(256), 0, st, nn, bm, words, row_ptr,
                        col_idx, blk_row);
-}
-
-void launch_run_entries(int nruns, int npad, const uint64_t* key, const int* run_start, const int* row_ptr,
-                        const int* col_idx, uint64_t* ekey, uint32_t* eval, int* ecount, hipStream_t st) {
-    if (nruns > 0)
-        hipLaunchKernelGGL(k_run_entries, dim3((nruns + 255) / 256), dim3(256), 0, st, nruns, key,
-                           run_start, row_ptr, col_idx, ekey, eval, ecount);
-    int from = nruns * 10;
-    if (npad > from)
-        hipLaunchKernelGGL(k_pad_keys, dim3((npad - from + 255) / 256), dim3(256), 0, st, ekey, eval, from,
-                           npad);
-}
-
-void launch_entries_store(int ne, const uint64_t* ekey, uint32_t* ent, hipStream_t st) {
-    if (ne > 0)
-        hipLaunchKernelGGL(k_entries_store, dim3((ne + 255) / 256), dim3(256), 0, st, ne, ekey, ent);
 }
 
 void launch_transpose_keys(int nb, int npad, const int* blk_row, const int* col_idx, uint64_t* tkey,

@@ -25,9 +25,6 @@ void launch_pattern(int nruns, const uint64_t* key, const int* run_start, int nn
 void launch_row_counts(int nn, const uint32_t* bm, int words, int* cnt, hipStream_t st);
 void launch_row_fill(int nn, const uint32_t* bm, int words, const int* row_ptr, int* col_idx, int* blk_row,
                      hipStream_t st);
-void launch_run_entries(int nruns, int npad, const uint64_t* key, const int* run_start, const int* row_ptr,
-                        const int* col_idx, uint64_t* ekey, uint32_t* eval, int* ecount, hipStream_t st);
-void launch_entries_store(int ne, const uint64_t* ekey, uint32_t* ent, hipStream_t st);
 void launch_transpose_keys(int nb, int npad, const int* blk_row, const int* col_idx, uint64_t* tkey, uint32_t* tval,
                            int* tcount, hipStream_t st);
 void launch_full_counts(int nn, const int* row_ptr, const int* tcount, int* fcount, hipStream_t st);

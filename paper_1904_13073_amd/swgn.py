@@ -126,7 +126,7 @@ EXPORTS = ["sw_config_default", "sw_status_string", "sw_last_error", "sw_create_
            "sw_solve_batch", "sw_profile_stage", "sw_server_config_default", "sw_create_server",
            "sw_destroy_server", "sw_server_last_error", "sw_server_attach", "sw_server_detach",
            "sw_server_submit", "sw_server_poll", "sw_server_counters", "sw_get_footprint",
-           "sw_batch_autotune", "sw_get_layout", "sw_set_surfel_attributes", "sw_get_surfel_attributes",
+           "sw_batch_autotune", "sw_get_layout", "sw_check_layout", "sw_set_surfel_attributes", "sw_get_surfel_attributes",
            "sw_get_reference_surfels", "sw_set_frame_time", "sw_fuse_frame", "sw_get_last_fusion",
            "sw_append_candidates", "sw_get_live_nodes", "sw_update_geometry"]
 
@@ -194,6 +194,7 @@ def lib() -> C.CDLL:
         "sw_get_footprint": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "sw_batch_autotune": (i32, [vp, C.POINTER(vp), i32, i32, C.POINTER(i32)]),
         "sw_get_layout": (i32, [vp, C.POINTER(SwLayout)]),
+        "sw_check_layout": (i32, [vp, C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -651,6 +652,15 @@ class Stream:
         out = SwLayout()
         _check(self.h, lib().sw_get_layout(self.h, C.byref(out)))
         return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def check_layout(self) -> dict:
+        """Differing element counts between the device's segment layout and
+        the host's sequential walk over the same sorted surfels (all 0 when
+        they agree)."""
+        out = (C.c_int64 * 9)()
+        _check(self.h, lib().sw_check_layout(self.h, out))
+        names = ("seg_start", "mask", "off", "ent_ptr", "ent_sub", "ent_grad", "pack_start", "pack_seg", "pos4")
+        return {k: int(v) for k, v in zip(names, out)}
 
     def footprint(self):
         """(resident bytes, workspace bytes of one frame in flight)."""

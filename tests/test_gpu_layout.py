@@ -1,0 +1,77 @@
+"""The segment layout built on the device at sw_set_node_graph (greedy cuts of
+the sorted surfels into segments of at most 5 nodes and 232 surfels, packs of
+whole segments, the block fold's entries, each surfel's node positions) against
+the plain sequential walk over the same sorted surfels and block pattern
+(sw_check_layout), element by element, on the workload scenes and on node sets
+built to stress the cut: long runs of one node set (cuts inside a run, then
+inside the run a merged segment reaches) and many short runs."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_lib, stream_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swgn():
+    return gpu_lib()
+
+
+def _assert_same(st):
+    d = st.check_layout()
+    assert all(v == 0 for v in d.values()), d
+    return st.layout()
+
+
+@pytest.mark.parametrize("name,seed", [("tiny", None), ("c1", None), ("c2", None), ("random", 400),
+                                       ("random", 401)])
+def test_device_layout_matches_sequential_walk(swgn, scene_cache, name, seed):
+    s = scene_cache(name, seed)
+    st = stream_for(swgn, s)
+    lay = _assert_same(st)
+    st.close()
+    ns = s.surfel_pos.shape[0]
+    print(name, seed, lay, flush=True)
+    assert -(-ns // 232) <= lay["packs"] <= lay["segments"] <= ns
+
+
+def _cloud_stream(swgn, pos, nodes):
+    cfg = swgn.sw_config_default(width=64, height=48, fx=50.0, fy=50.0, cx=32.0, cy=24.0, node_sigma=0.5)
+    st = swgn.Stream(cfg)
+    nrm = np.zeros_like(pos)
+    nrm[:, 2] = -1.0
+    st.set_reference_surfels(pos.astype(np.float32), nrm.astype(np.float32))
+    st.set_node_graph(nodes.astype(np.float32))
+    return st
+
+
+@pytest.mark.parametrize("case", ["one_set", "few_nodes", "clustered", "many_sets"])
+def test_device_layout_on_constructed_node_sets(swgn, case):
+    rng = np.random.default_rng({"one_set": 1, "few_nodes": 2, "clustered": 3, "many_sets": 4}[case])
+    if case == "one_set":
+        # 9 nodes, every surfel beside node 0 and far from the rest but nodes 1-3:
+        # one node set, one run of 5000 surfels, cut every 232
+        nodes = np.array([[0, 0, 1], [0.1, 0, 1], [0, 0.1, 1], [0.1, 0.1, 1]] +
+                         [[2 + k, 2, 1] for k in range(5)], np.float64)
+        pos = np.array([0.02, 0.02, 1.0]) + rng.uniform(-0.004, 0.004, (5000, 3))
+    elif case == "few_nodes":
+        # 9 nodes on a line, surfels along it: few node sets, runs of hundreds
+        nodes = np.stack([np.linspace(0, 1, 9), np.zeros(9), np.ones(9)], axis=1)
+        pos = np.stack([rng.uniform(0, 1, 20000), rng.uniform(-0.01, 0.01, 20000), np.ones(20000)], axis=1)
+    elif case == "clustered":
+        # 12 nodes, surfels in clumps of uneven size: long and short runs mixed
+        nodes = rng.uniform(0, 1, (12, 3))
+        centers = rng.uniform(0, 1, (40, 3))
+        sizes = rng.integers(1, 700, 40)
+        pos = np.concatenate([c + rng.normal(0, 0.01, (n, 3)) for c, n in zip(centers, sizes)])
+    else:
+        # 400 nodes and 30000 surfels spread evenly: thousands of short runs
+        nodes = rng.uniform(0, 1, (400, 3))
+        pos = rng.uniform(0, 1, (30000, 3))
+    st = _cloud_stream(swgn, pos, nodes)
+    lay = _assert_same(st)
+    st.close()
+    print(case, lay, flush=True)
+    if case == "one_set":
+        assert lay["node_sets"] == 1 and lay["segments"] == -(-5000 // 232)
