@@ -8,9 +8,10 @@
 // that opens at surfel s always starts with the node set of s's run, so the
 // next opening after s is a function next(s) of s alone, with
 // s < next(s) <= s + M. next is formed for every surfel at once; the chain
-// from surfel 0 is then walked in chunks of kChainChunk positions (each chunk
-// from each of the M positions a chain can enter it by, in parallel; the
-// chunks linked by one thread; the chosen walk of each chunk written out).
+// from surfel 0 is then walked in chunks of C positions, M <= C <= kChainChunk
+// (each chunk from each of the M positions a chain can enter it by, in
+// parallel; the chunks linked by one thread; the chosen walk of each chunk
+// written out).
 // Packs are the same chain over segments. Every result is an integer that
 // does not depend on the order of any atomic.
 #include "swgn_impl.h"
@@ -21,7 +22,7 @@ namespace swgn {
 
 namespace {
 
-constexpr int kChainChunk = 8192;   // positions per workgroup of the chain walk (LDS ints)
+constexpr int kChainChunk = 8192;   // most positions per workgroup of the chain walk (LDS ints)
 constexpr int kChainBlock = 256;    // threads per workgroup; >= M
 
 __device__ __forceinline__ void set_nodes(uint64_t k, int (&t)[4]) {
@@ -105,11 +106,11 @@ __device__ __forceinline__ void stage_chunk(const int* __restrict__ next, int lo
 // Per chunk q and entry position lo + t (t < M): where the walk from it leaves
 // the chunk and how many positions it visits inside. A successor that does not
 // move forward ends the walk and flags the input.
-__global__ void __launch_bounds__(kChainBlock) k_chain_chunks(const int* __restrict__ next, int n, int M,
+__global__ void __launch_bounds__(kChainBlock) k_chain_chunks(const int* __restrict__ next, int n, int M, int C,
                                                                int* __restrict__ exit_pos, int* __restrict__ hops,
                                                                int* __restrict__ bad) {
     __shared__ int nx[kChainChunk];
-    const int q = blockIdx.x, lo = q * kChainChunk, hi = min(n, lo + kChainChunk);
+    const int q = blockIdx.x, lo = q * C, hi = min(n, lo + C);
     stage_chunk(next, lo, hi, nx);
     const int t = threadIdx.x;
     if (t >= M) return;
@@ -128,14 +129,14 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_chunks(const int* __restr
 // position and the number of chain positions before it; *count = the chain's
 // length. An entry outside the chunk's M entry positions flags the input and
 // marks the remaining chunks unused (entry -1).
-__global__ void k_chain_link(int nchunks, int n, int M, const int* __restrict__ exit_pos,
+__global__ void k_chain_link(int nchunks, int n, int M, int C, const int* __restrict__ exit_pos,
                              const int* __restrict__ hops, int* __restrict__ entry, int* __restrict__ base,
                              int* __restrict__ count, int* __restrict__ bad) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int e = 0, b = 0;
     bool ok = true;
     for (int q = 0; q < nchunks; ++q) {
-        const int t = e - q * kChainChunk;
+        const int t = e - q * C;
         ok = ok && t >= 0 && t < M;
         entry[q] = ok ? e : -1;
         base[q] = b;
@@ -149,11 +150,11 @@ __global__ void k_chain_link(int nchunks, int n, int M, const int* __restrict__ 
 }
 
 // The chain's positions inside each chunk, from its entry, at out[base ...].
-__global__ void __launch_bounds__(kChainBlock) k_chain_emit(const int* __restrict__ next, int n,
+__global__ void __launch_bounds__(kChainBlock) k_chain_emit(const int* __restrict__ next, int n, int C,
                                                              const int* __restrict__ entry,
                                                              const int* __restrict__ base, int* __restrict__ out) {
     __shared__ int nx[kChainChunk];
-    const int q = blockIdx.x, lo = q * kChainChunk, hi = min(n, lo + kChainChunk);
+    const int q = blockIdx.x, lo = q * C, hi = min(n, lo + C);
     stage_chunk(next, lo, hi, nx);
     if (threadIdx.x != 0 || entry[q] < 0) return;
     int pos = entry[q], j = base[q];
@@ -304,21 +305,31 @@ inline int grid_of(int64_t n, int block) { return (int)((n + block - 1) / block)
 
 }  // namespace
 
+// Chunk size: a walk inside a chunk costs a dependent LDS read per step and
+// the link a dependent global read per chunk, so C ~ sqrt(32 n) (a power of
+// two in [256, kChainChunk]; at least M, so that a chain enters every chunk).
+int chain_chunk(int n, int M) {
+    int c = 256;
+    while (c < kChainChunk && (int64_t)c * c < 32 * (int64_t)n) c <<= 1;
+    return c < M ? kChainChunk : c;
+}
+
 size_t chain_work_ints(int n, int M) {
-    const int64_t nchunks = (n + kChainChunk - 1) / kChainChunk;
+    const int64_t nchunks = (n + 255) / 256;
     return (size_t)(nchunks * (2 * (int64_t)M + 2) + 1);
 }
 
 void chain_from_zero(const int* next, int n, int M, int* out, int* count, int* work, int* bad, hipStream_t st) {
-    const int nchunks = (n + kChainChunk - 1) / kChainChunk;
+    const int C = chain_chunk(n, M);
+    const int nchunks = (n + C - 1) / C;
     int* exit_pos = work;
     int* hops = exit_pos + (size_t)nchunks * M;
     int* entry = hops + (size_t)nchunks * M;
     int* base = entry + nchunks;
-    hipLaunchKernelGGL(k_chain_chunks, dim3(nchunks), dim3(kChainBlock), 0, st, next, n, M, exit_pos, hops, bad);
-    hipLaunchKernelGGL(k_chain_link, dim3(1), dim3(kWave), 0, st, nchunks, n, M, exit_pos, hops, entry, base, count,
-                       bad);
-    hipLaunchKernelGGL(k_chain_emit, dim3(nchunks), dim3(kChainBlock), 0, st, next, n, entry, base, out);
+    hipLaunchKernelGGL(k_chain_chunks, dim3(nchunks), dim3(kChainBlock), 0, st, next, n, M, C, exit_pos, hops, bad);
+    hipLaunchKernelGGL(k_chain_link, dim3(1), dim3(kWave), 0, st, nchunks, n, M, C, exit_pos, hops, entry, base,
+                       count, bad);
+    hipLaunchKernelGGL(k_chain_emit, dim3(nchunks), dim3(kChainBlock), 0, st, next, n, C, entry, base, out);
 }
 
 int chain_max_hop() { return kChainBlock; }
