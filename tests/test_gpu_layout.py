@@ -46,9 +46,10 @@ def _cloud_stream(swgn, pos, nodes):
     return st
 
 
-@pytest.mark.parametrize("case", ["one_set", "few_nodes", "clustered", "many_sets"])
+@pytest.mark.parametrize("case", ["one_set", "few_nodes", "clustered", "many_sets", "whole_chunks", "large"])
 def test_device_layout_on_constructed_node_sets(swgn, case):
-    rng = np.random.default_rng({"one_set": 1, "few_nodes": 2, "clustered": 3, "many_sets": 4}[case])
+    rng = np.random.default_rng({"one_set": 1, "few_nodes": 2, "clustered": 3, "many_sets": 4, "whole_chunks": 5,
+                                 "large": 6}[case])
     if case == "one_set":
         # 9 nodes, every surfel beside node 0 and far from the rest but nodes 1-3:
         # one node set, one run of 5000 surfels, cut every 232
@@ -65,10 +66,18 @@ def test_device_layout_on_constructed_node_sets(swgn, case):
         centers = rng.uniform(0, 1, (40, 3))
         sizes = rng.integers(1, 700, 40)
         pos = np.concatenate([c + rng.normal(0, 0.01, (n, 3)) for c, n in zip(centers, sizes)])
-    else:
+    elif case == "many_sets":
         # 400 nodes and 30000 surfels spread evenly: thousands of short runs
         nodes = rng.uniform(0, 1, (400, 3))
         pos = rng.uniform(0, 1, (30000, 3))
+    elif case == "whole_chunks":
+        # 32768 surfels: the segment chain is walked in exactly 32 chunks of 1024
+        nodes = rng.uniform(0, 1, (300, 3))
+        pos = rng.uniform(0, 1, (32768, 3))
+    else:
+        # 2M surfels and 4000 nodes: the chain over 245 chunks of 8192
+        nodes = rng.uniform(0, 1, (4000, 3))
+        pos = rng.uniform(0, 1, (2000000, 3))
     st = _cloud_stream(swgn, pos, nodes)
     lay = _assert_same(st)
     st.close()
