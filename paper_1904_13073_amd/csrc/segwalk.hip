@@ -193,7 +193,6 @@ __global__ void __launch_bounds__(256) k_seg_info(int nseg, const int* __restric
             set_nodes(set_key[r0], t);
             cur[0] = t[0]; cur[1] = t[1]; cur[2] = t[2]; cur[3] = t[3]; cur[4] = 0x7fffffff;
         }
-        if (cn < 5) cur[4] = 0x7fffffff;
         // ascending (an unused slot holds the largest int and sorts last)
         int tmp;
 #define SWGN_CS(p, q) if (cur[p] > cur[q]) { tmp = cur[p]; cur[p] = cur[q]; cur[q] = tmp; }
