@@ -48,6 +48,9 @@ def test_defaults_and_status_strings():
     assert L.sw_destroy_stream(None) == 0
     assert L.sw_solve_frame(None, None, 0, None) == swgn.SW_EINVAL
     assert L.sw_get_sizes(None, None, None, None) == swgn.SW_EINVAL
+    diff = (C.c_int64 * 9)()
+    assert L.sw_check_layout(None, diff) == swgn.SW_EINVAL
+    assert L.sw_get_layout(None, None) == swgn.SW_EINVAL
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
