@@ -469,8 +469,10 @@ sw_status sw_get_node_se3(sw_stream s, float* out, int32_t capacity);
 sw_status sw_get_sizes(sw_stream s, int64_t* n_surfels, int32_t* n_nodes, int32_t* n_blocks);
 
 /* Device memory of the stream: resident state (surfels, skinning, node state,
- * graph, block pattern, work lists, capture buffers) and the workspace one
- * frame in flight needs (the admission footprint of sw_server_attach).
+ * graph, block pattern, work lists, capture buffers, and the temporaries of
+ * the last node-set build, whose memory the next build reuses) and the
+ * workspace one frame in flight needs (the admission footprint of
+ * sw_server_attach).
  * SW_ESTATE before sw_set_node_graph. */
 sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* workspace_bytes);
 

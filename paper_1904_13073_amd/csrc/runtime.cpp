@@ -41,8 +41,8 @@ namespace rt {
 void* Arena::raw(size_t bytes) {
     constexpr size_t kFirstChunk = (size_t)4 << 20, kMaxChunk = (size_t)256 << 20;
     bytes = ((bytes == 0 ? 1 : bytes) + 255) & ~size_t(255);
-    if (!chunks_.empty()) {
-        Chunk& c = chunks_.back();
+    for (; cur_ < chunks_.size(); ++cur_) {
+        Chunk& c = chunks_[cur_];
         if (c.size - c.used >= bytes) {
             char* p = c.base + c.used;
             c.used += bytes;
@@ -55,6 +55,7 @@ void* Arena::raw(size_t bytes) {
     void* p = nullptr;
     SWGN_HIP(hipMalloc(&p, size));
     chunks_.push_back(Chunk{static_cast<char*>(p), size, bytes});
+    cur_ = chunks_.size() - 1;
     bytes_ += bytes;
     return p;
 }
@@ -62,6 +63,13 @@ void* Arena::raw(size_t bytes) {
 void Arena::release() {
     for (const Chunk& c : chunks_) (void)hipFree(c.base);
     chunks_.clear();
+    cur_ = 0;
+    bytes_ = 0;
+}
+
+void Arena::reset() {
+    for (Chunk& c : chunks_) c.used = 0;
+    cur_ = 0;
     bytes_ = 0;
 }
 
@@ -405,12 +413,16 @@ static std::vector<int> morton_order(const std::vector<float>& pos, int nn) {
 void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_se3, int32_t on_device,
                  const float4* keep_rq, const float4* keep_tt, bool keep_order) {
     hipStream_t st = s->exec.st;
-    s->graph_mem.release();
+    // the node-set arrays and temporaries reuse their device memory: no work
+    // of the device may still use it
+    SWGN_HIP(hipDeviceSynchronize());
+    s->graph_mem.reset();
     s->ws_mem.release();
     s->graph_set = false;
     s->captured = false;
     ++s->generation;
-    Arena tmp;
+    Arena& tmp = s->setup_mem;
+    tmp.reset();
     Arena& G = s->graph_mem;
     const int ns = (int)s->ns;
     FrameDesc h{};
@@ -1707,7 +1719,8 @@ sw_status sw_get_footprint(sw_stream s, int64_t* resident_bytes, int64_t* worksp
     if (!s) return SW_EINVAL;
     if (!s->graph_set) return fail(s->err, SW_ESTATE, "node graph not set");
     if (resident_bytes)
-        *resident_bytes = (int64_t)(s->surf_mem.bytes() + s->graph_mem.bytes() + s->frame_mem.bytes());
+        *resident_bytes = (int64_t)(s->surf_mem.bytes() + s->graph_mem.bytes() + s->frame_mem.bytes() +
+                                     s->setup_mem.bytes());
     if (workspace_bytes) *workspace_bytes = (int64_t)s->ws_bytes;
     return SW_OK;
 }

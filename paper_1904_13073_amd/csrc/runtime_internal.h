@@ -47,9 +47,13 @@ public:
         return static_cast<T*>(raw(n * sizeof(T)));
     }
     void release();
+    // hands the chunks out again from the start (no device memory is freed;
+    // the caller makes sure no work still uses what they held)
+    void reset();
     size_t bytes() const { return bytes_; }   // bytes handed out (aligned)
     void swap(Arena& o) {
         chunks_.swap(o.chunks_);
+        std::swap(cur_, o.cur_);
         std::swap(bytes_, o.bytes_);
     }
 
@@ -59,6 +63,7 @@ private:
         size_t size, used;
     };
     std::vector<Chunk> chunks_;
+    size_t cur_ = 0;                      // chunk handed out from
     size_t bytes_ = 0;
 };
 
@@ -117,6 +122,7 @@ struct sw_stream_s {
     std::string err;
     swgn::rt::Executor exec;              // the stream's own HIP stream
     swgn::rt::Arena frame_mem, surf_mem, graph_mem, ws_mem;
+    swgn::rt::Arena setup_mem;            // temporaries of the node-set build, kept for the next one
     uint64_t generation = 0;              // bumped whenever device buffers are replaced
 
     // surfels as given
