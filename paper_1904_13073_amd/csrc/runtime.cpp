@@ -291,8 +291,12 @@ void build_segments(sw_stream s, FrameDesc& h, const uint64_t* key, const int* s
     int* cuts = tmp.alloc<int>(ns);
     launch_seg_next(ns, nsets, d_keys, set_start, run_pos, kCorrPack, nxt, st);
     chain_from_zero(nxt, ns, kCorrPack, cuts, d_cnt, work, d_bad, st);
-    const int nseg = read_scalar(d_cnt, st);
-    if (read_scalar(d_bad, st) != 0 || nseg < 1 || nseg > ns)
+    int cut[2] = {0, 0};                       // segments, flag
+    SWGN_HIP(hipMemcpyAsync(&cut[0], d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipMemcpyAsync(&cut[1], d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    SWGN_HIP(hipStreamSynchronize(st));
+    const int nseg = cut[0];
+    if (cut[1] != 0 || nseg < 1 || nseg > ns)
         throw HipFail{hipErrorInvalidValue, "segment layout: the segment cut is inconsistent"};
     int* d_seg = G.alloc<int>(nseg + 1);
     SWGN_HIP(hipMemcpyAsync(d_seg, cuts, sizeof(int) * nseg, hipMemcpyDeviceToDevice, st));

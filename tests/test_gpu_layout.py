@@ -84,3 +84,26 @@ def test_device_layout_on_constructed_node_sets(swgn, case):
     print(case, lay, flush=True)
     if case == "one_set":
         assert lay["node_sets"] == 1 and lay["segments"] == -(-5000 // 232)
+
+
+def test_rebuilds_on_one_stream_equal_fresh_streams(swgn, scene_cache):
+    """A node set rebuilt on a stream reuses the device memory of the last
+    build (node-set arrays and temporaries); node sets of other sizes in turn
+    must give the layout and the solve of a fresh stream, bit for bit."""
+    s = scene_cache("c1")
+    nodes = s.node_pos
+    subsets = [nodes, nodes[: len(nodes) // 2], nodes, nodes[: (2 * len(nodes)) // 3]]
+    st = swgn.Stream(swgn.config_for(s))
+    st.set_reference_surfels(s.surfel_pos, s.surfel_nrm)
+    for k, nd in enumerate(subsets):
+        st.set_node_graph(nd)
+        assert all(v == 0 for v in st.check_layout().values())
+        st.solve_frame(s.depth)
+        fresh = swgn.Stream(swgn.config_for(s))
+        fresh.set_reference_surfels(s.surfel_pos, s.surfel_nrm)
+        fresh.set_node_graph(nd)
+        fresh.solve_frame(s.depth)
+        assert st.layout() == fresh.layout()
+        assert np.array_equal(st.node_se3(), fresh.node_se3()), k
+        fresh.close()
+    st.close()
