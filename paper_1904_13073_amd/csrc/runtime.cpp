@@ -518,12 +518,14 @@ void build_graph(sw_stream s, int nn, const float* node_pos, const float* node_s
         launch_nodes_from_se3(nn, se3_in, pref, h.rq, h.tt, h.dq, h.cl, st);
     }
 
-    // skinning and node graph, searched in the caller's node order (so that
-    // equal distances go to the lower caller index), then renumbered
+    // skinning and node graph: equal distances go to the lower caller index
+    // (the skinning scans the library's order and orders candidates by
+    // caller index; the graph scans the caller's order), then renumbered
     int4* idx_in = tmp.alloc<int4>(ns);
     float4* w_in = tmp.alloc<float4>(ns);
     const float sig = s->cfg.node_sigma;
-    launch_knn_skin(ns, s->in_pos, nn, pcall, 1.0f / (2.0f * sig * sig), idx_in, w_in, st);
+    float4* boxes = tmp.alloc<float4>(knn_box_count(nn));
+    launch_knn_skin(ns, s->in_pos, nn, pref, d_id, boxes, 1.0f / (2.0f * sig * sig), idx_in, w_in, st);
     launch_map_ids(reinterpret_cast<int*>(idx_in), 4 * ns, d_inv, st);
     int* nbr_call = tmp.alloc<int>(8 * (size_t)nn);
     launch_node_graph(nn, pcall, nbr_call, st);

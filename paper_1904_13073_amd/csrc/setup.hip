@@ -13,34 +13,130 @@
 namespace swgn {
 
 // ---------------------------------------------------------------------------
-// Nearest nodes. Key ((dx*dx + dy*dy) + dz*dz), dx = x_query - x_node. The
-// list stays sorted by key; a candidate enters only with a key strictly below
-// the current last one and goes after every kept entry whose key is <= its
-// own. Nodes are visited in ascending index, so equal keys keep the lower
-// index first.
+// Nearest nodes. Key ((dx*dx + dy*dy) + dz*dz), dx = x_query - x_node; the 4
+// nearest are the 4 smallest (key, caller index) pairs, which is what a scan
+// in ascending caller index that admits a candidate only strictly below the
+// current fourth key gives. Here the nodes are scanned in the library's
+// (Morton) order with candidates ordered by (key, caller index), so the
+// result is the same whatever the order, and whole runs of 32 nodes are
+// skipped when no lane of the wave can admit any of them: the wave first
+// takes the runs whose bounding box meets its surfels' box (else the nearest
+// one), then skips every other run whose box distance, less a margin above
+// FP32 rounding, exceeds every lane's current fourth key (a candidate enters
+// only at or below it).
+// A non-finite position enters no list (its keys are NaN or infinite).
 // ---------------------------------------------------------------------------
-constexpr int kKnnTile = 1024;
+constexpr int kKnnTile = 1024;          // nodes staged in LDS per round
+constexpr int kKnnRun = 32;             // nodes per bounding box
+
+__global__ void k_node_boxes(int nn, const float4* __restrict__ nodes, float4* __restrict__ boxes) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q * kKnnRun >= nn) return;
+    float3 lo = make_float3(INFINITY, INFINITY, INFINITY), hi = make_float3(-INFINITY, -INFINITY, -INFINITY);
+    for (int t = q * kKnnRun; t < min(nn, (q + 1) * kKnnRun); ++t) {
+        const float4 p = nodes[t];
+        lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
+        hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
+    }
+    boxes[2 * q] = make_float4(lo.x, lo.y, lo.z, 0.f);
+    boxes[2 * q + 1] = make_float4(hi.x, hi.y, hi.z, 0.f);
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+    v = fminf(v, xchg<32>(v)); v = fminf(v, xchg<16>(v)); v = fminf(v, xchg<8>(v));
+    v = fminf(v, xchg<4>(v)); v = fminf(v, xchg<2>(v)); v = fminf(v, xchg<1>(v));
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+    v = fmaxf(v, xchg<32>(v)); v = fmaxf(v, xchg<16>(v)); v = fmaxf(v, xchg<8>(v));
+    v = fmaxf(v, xchg<4>(v)); v = fmaxf(v, xchg<2>(v)); v = fmaxf(v, xchg<1>(v));
+    return v;
+}
+
+// A lower bound of every key between the wave's box (lo, hi) and a node box:
+// each point pair is at least the boxes' gap apart per axis; the computed key
+// is within 5 roundings of the exact sum of squares and so is this bound, so
+// shrinking it by 2^-20 (and 1e-30 for tiny values) keeps it below every key.
+__device__ __forceinline__ float box_key_bound(float3 lo, float3 hi, float4 blo, float4 bhi) {
+    const float gx = fmaxf(fmaxf(lo.x - bhi.x, blo.x - hi.x), 0.f);
+    const float gy = fmaxf(fmaxf(lo.y - bhi.y, blo.y - hi.y), 0.f);
+    const float gz = fmaxf(fmaxf(lo.z - bhi.z, blo.z - hi.z), 0.f);
+    const float d2 = (gx * gx + gy * gy) + gz * gz;
+    return d2 * (1.0f - 0x1p-20f) - 1e-30f;
+}
+
+// (key, j) into the 4 smallest (key, index) pairs kept ascending, by selects
+// only (the list stays in registers): the entries below the candidate stay,
+// it takes the first place above it, the rest move down one.
+__device__ __forceinline__ void admit4(float (&kd)[4], int (&ki)[4], float key, int j) {
+    if (!(key < kd[3] || (key == kd[3] && j < ki[3]))) return;
+    const bool c0 = key < kd[0] || (key == kd[0] && j < ki[0]);
+    const bool c1 = key < kd[1] || (key == kd[1] && j < ki[1]);
+    const bool c2 = key < kd[2] || (key == kd[2] && j < ki[2]);
+    kd[3] = c2 ? kd[2] : key;                ki[3] = c2 ? ki[2] : j;
+    kd[2] = c1 ? kd[1] : (c2 ? key : kd[2]); ki[2] = c1 ? ki[1] : (c2 ? j : ki[2]);
+    kd[1] = c0 ? kd[0] : (c1 ? key : kd[1]); ki[1] = c0 ? ki[0] : (c1 ? j : ki[1]);
+    kd[0] = c0 ? key : kd[0];                ki[0] = c0 ? j : ki[0];
+}
 
 __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restrict__ pos, int nn,
-        const float4* __restrict__ nodes, float inv_two_sigma2, int4* __restrict__ out_idx,
-        float4* __restrict__ out_w) {
+        const float4* __restrict__ nodes, const int* __restrict__ caller, const float4* __restrict__ boxes,
+        float inv_two_sigma2, int4* __restrict__ out_idx, float4* __restrict__ out_w) {
     __shared__ float4 tile[kKnnTile];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int tid[kKnnTile];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     float x = 0.f, y = 0.f, z = 0.f;
     if (i < ns) { x = pos[3 * i]; y = pos[3 * i + 1]; z = pos[3 * i + 2]; }
+    const bool fin = i < ns && isfinite(x) && isfinite(y) && isfinite(z);
     float kd[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    int ki[4] = {0, 0, 0, 0};
+    int ki[4] = {0, 0, 0, 0};              // (INFINITY, 0) admits no infinite key
+    // the box of the wave's finite surfels (empty: every run is skipped)
+    const float3 lo = make_float3(wave_minf(fin ? x : INFINITY), wave_minf(fin ? y : INFINITY),
+                                  wave_minf(fin ? z : INFINITY));
+    const float3 hi = make_float3(wave_maxf(fin ? x : -INFINITY), wave_maxf(fin ? y : -INFINITY),
+                                  wave_maxf(fin ? z : -INFINITY));
+    const int nruns = (nn + kKnnRun - 1) / kKnnRun;
+    // first the runs whose box meets the wave's (or the nearest one)
+    int seed = 0;
+    float sb = INFINITY;
+    for (int q = 0; q < nruns; ++q) {
+        const float b = box_key_bound(lo, hi, boxes[2 * q], boxes[2 * q + 1]);
+        if (b < sb) { sb = b; seed = q; }
+        if (b > 0.f) continue;
+        for (int t = q * kKnnRun; t < min(nn, (q + 1) * kKnnRun); ++t) {
+            const float4 p = nodes[t];
+            const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
+            admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, caller[t]);
+        }
+    }
+    if (sb > 0.f) {
+        for (int t = seed * kKnnRun; t < min(nn, (seed + 1) * kKnnRun); ++t) {
+            const float4 p = nodes[t];
+            const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
+            admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, caller[t]);
+        }
+    } else {
+        seed = -1;                          // (the meeting runs are done)
+    }
     for (int base = 0; base < nn; base += kKnnTile) {
-        int cnt = min(kKnnTile, nn - base);
+        const int cnt = min(kKnnTile, nn - base);
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = nodes[base + t];
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            tile[t] = nodes[base + t];
+            tid[t] = caller[base + t];
+        }
         __syncthreads();
-        if (i < ns) {
-            for (int t = 0; t < cnt; ++t) {
-                float4 p = tile[t];
-                float dx = x - p.x, dy = y - p.y, dz = z - p.z;
-                float key = (dx * dx + dy * dy) + dz * dz;
-                knn_insert<4>(kd, ki, key, base + t);
+        for (int r0 = 0; r0 < cnt; r0 += kKnnRun) {
+            const int q = (base + r0) / kKnnRun;
+            const float b = box_key_bound(lo, hi, boxes[2 * q], boxes[2 * q + 1]);
+            if (q == seed || b <= 0.f) continue;
+            // every lane's fourth key bounds what it could still admit
+            const float worst = wave_maxf(fin ? kd[3] : -INFINITY);
+            if (b > worst) continue;
+            for (int t = r0; t < min(cnt, r0 + kKnnRun); ++t) {
+                const float4 p = tile[t];
+                const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
+                admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, tid[t]);
             }
         }
     }
@@ -483,10 +579,14 @@ __global__ void k_ell_slots(int nn, int ell_w, const uint32_t* __restrict__ ell_
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, float inv_two_sigma2, int4* idx,
-                     float4* w, hipStream_t st) {
-    if (ns <= 0) return;
-    hipLaunchKernelGGL(k_knn_skin, dim3((ns + 255) / 256), dim3(256), 0, st, ns, pos_aos, nn, nodes,
+size_t knn_box_count(int nn) { return 2 * (size_t)((nn + kKnnRun - 1) / kKnnRun); }
+
+void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, const int* caller, float4* boxes,
+                     float inv_two_sigma2, int4* idx, float4* w, hipStream_t st) {
+    if (ns <= 0 || nn <= 0) return;
+    const int nruns = (nn + kKnnRun - 1) / kKnnRun;
+    hipLaunchKernelGGL(k_node_boxes, dim3((nruns + 255) / 256), dim3(256), 0, st, nn, nodes, boxes);
+    hipLaunchKernelGGL(k_knn_skin, dim3((ns + 255) / 256), dim3(256), 0, st, ns, pos_aos, nn, nodes, caller, boxes,
                        inv_two_sigma2, idx, w);
 }
 

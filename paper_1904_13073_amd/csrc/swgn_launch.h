@@ -9,8 +9,12 @@
 namespace swgn {
 
 // setup
-void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, float inv_two_sigma2, int4* idx,
-                     float4* w, hipStream_t st);
+// 4 nearest nodes (caller indices) and weights of every surfel; nodes in the
+// library's order with their caller indices; boxes holds knn_box_count(nn)
+// float4 of scratch.
+size_t knn_box_count(int nn);
+void launch_knn_skin(int ns, const float* pos_aos, int nn, const float4* nodes, const int* caller, float4* boxes,
+                     float inv_two_sigma2, int4* idx, float4* w, hipStream_t st);
 void launch_node_graph(int nn, const float4* nodes, int* nbr, hipStream_t st);
 void sort_pairs(uint64_t* key, uint32_t* val, int n_pow2, hipStream_t st);
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t st);
