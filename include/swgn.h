@@ -181,9 +181,11 @@ sw_status sw_set_reference_surfels(sw_stream s, int64_t n, const float* pos_xyz,
  * x_live = R x + t), or NULL for the identity. Runs the skinning (each surfel's
  * 4 nearest nodes by squared distance, ties to the lower node index, and the
  * blend weights exp(-d^2 / (2 sigma^2)) normalised), the node graph (each
- * node's 8 nearest other nodes) and the block pattern of J^T J. The node order
- * defines the node indices. n_nodes in [9, 32768]; surfels must be set
- * (SW_ESTATE otherwise). */
+ * node's 8 nearest other nodes) and the block pattern of J^T J with its
+ * segment layout, all on the device. The node order defines the node
+ * indices. n_nodes in [9, 32768]; surfels must be set (SW_ESTATE otherwise).
+ * A repeated call reuses the device memory of the stream's previous node set
+ * and so first waits for all work on the device (as freeing it would). */
 sw_status sw_set_node_graph(sw_stream s, int32_t n_nodes, const float* node_pos_xyz,
                             const float* node_se3, int32_t on_device);
 
