@@ -65,18 +65,23 @@ __device__ __forceinline__ float box_key_bound(float3 lo, float3 hi, float4 blo,
     return d2 * (1.0f - 0x1p-20f) - 1e-30f;
 }
 
-// (key, j) into the 4 smallest (key, index) pairs kept ascending, by selects
-// only (the list stays in registers): the entries below the candidate stay,
-// it takes the first place above it, the rest move down one.
-__device__ __forceinline__ void admit4(float (&kd)[4], int (&ki)[4], float key, int j) {
-    if (!(key < kd[3] || (key == kd[3] && j < ki[3]))) return;
-    const bool c0 = key < kd[0] || (key == kd[0] && j < ki[0]);
-    const bool c1 = key < kd[1] || (key == kd[1] && j < ki[1]);
-    const bool c2 = key < kd[2] || (key == kd[2] && j < ki[2]);
-    kd[3] = c2 ? kd[2] : key;                ki[3] = c2 ? ki[2] : j;
-    kd[2] = c1 ? kd[1] : (c2 ? key : kd[2]); ki[2] = c1 ? ki[1] : (c2 ? j : ki[2]);
-    kd[1] = c0 ? kd[0] : (c1 ? key : kd[1]); ki[1] = c0 ? ki[0] : (c1 ? j : ki[1]);
-    kd[0] = c0 ? key : kd[0];                ki[0] = c0 ? j : ki[0];
+// A candidate as one 64-bit word, (key bits, index): keys are >= +0 or +inf
+// or NaN, whose bit patterns order as the values do and sort NaN last, so
+// comparing words compares (key, index) pairs, ties to the lower index.
+__device__ __forceinline__ uint64_t knn_word(float key, int j) {
+    return ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)j;
+}
+
+// A word into the 4 smallest kept ascending, by selects only (the list stays
+// in registers): the words below it stay, it takes the first place above
+// them, the rest move down one.
+__device__ __forceinline__ void admit4(uint64_t (&kk)[4], uint64_t c) {
+    if (c >= kk[3]) return;
+    const bool c0 = c < kk[0], c1 = c < kk[1], c2 = c < kk[2];
+    kk[3] = c2 ? kk[2] : c;
+    kk[2] = c1 ? kk[1] : (c2 ? c : kk[2]);
+    kk[1] = c0 ? kk[0] : (c1 ? c : kk[1]);
+    kk[0] = c0 ? c : kk[0];
 }
 
 __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restrict__ pos, int nn,
@@ -88,8 +93,10 @@ __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restric
     float x = 0.f, y = 0.f, z = 0.f;
     if (i < ns) { x = pos[3 * i]; y = pos[3 * i + 1]; z = pos[3 * i + 2]; }
     const bool fin = i < ns && isfinite(x) && isfinite(y) && isfinite(z);
-    float kd[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    int ki[4] = {0, 0, 0, 0};              // (INFINITY, 0) admits no infinite key
+    // (INFINITY, 0) admits no infinite key
+    uint64_t kk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kk[q] = knn_word(INFINITY, 0);
     // the box of the wave's finite surfels (empty: every run is skipped)
     const float3 lo = make_float3(wave_minf(fin ? x : INFINITY), wave_minf(fin ? y : INFINITY),
                                   wave_minf(fin ? z : INFINITY));
@@ -106,14 +113,14 @@ __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restric
         for (int t = q * kKnnRun; t < min(nn, (q + 1) * kKnnRun); ++t) {
             const float4 p = nodes[t];
             const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
-            admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, caller[t]);
+            admit4(kk, knn_word((dx * dx + dy * dy) + dz * dz, caller[t]));
         }
     }
     if (sb > 0.f) {
         for (int t = seed * kKnnRun; t < min(nn, (seed + 1) * kKnnRun); ++t) {
             const float4 p = nodes[t];
             const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
-            admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, caller[t]);
+            admit4(kk, knn_word((dx * dx + dy * dy) + dz * dz, caller[t]));
         }
     } else {
         seed = -1;                          // (the meeting runs are done)
@@ -131,14 +138,21 @@ __global__ void __launch_bounds__(256) k_knn_skin(int ns, const float* __restric
             const float b = box_key_bound(lo, hi, boxes[2 * q], boxes[2 * q + 1]);
             if (q == seed || b <= 0.f) continue;
             // every lane's fourth key bounds what it could still admit
-            const float worst = wave_maxf(fin ? kd[3] : -INFINITY);
+            const float worst = wave_maxf(fin ? __uint_as_float((uint32_t)(kk[3] >> 32)) : -INFINITY);
             if (b > worst) continue;
             for (int t = r0; t < min(cnt, r0 + kKnnRun); ++t) {
                 const float4 p = tile[t];
                 const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
-                admit4(kd, ki, (dx * dx + dy * dy) + dz * dz, tid[t]);
+                admit4(kk, knn_word((dx * dx + dy * dy) + dz * dz, tid[t]));
             }
         }
+    }
+    float kd[4];
+    int ki[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        kd[q] = __uint_as_float((uint32_t)(kk[q] >> 32));
+        ki[q] = (int)(uint32_t)kk[q];
     }
     if (i >= ns) return;
     // weights exp(-(d_k^2 - d_0^2) / (2 sigma^2)), normalised
