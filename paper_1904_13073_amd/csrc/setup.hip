@@ -216,19 +216,42 @@ __device__ __forceinline__ bool pair_less(uint64_t ka, uint32_t va, uint64_t kb,
     return ka < kb || (ka == kb && va < vb);
 }
 
-__global__ void k_bitonic_global(uint64_t* __restrict__ key, uint32_t* __restrict__ val, int n,
-                                 int k, int j) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int p = i ^ j;
-    if (p <= i) return;
-    bool asc = (i & k) == 0;
-    uint64_t ka = key[i], kb = key[p];
-    uint32_t va = val[i], vb = val[p];
-    bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
-    if (sw) {
-        key[i] = kb; key[p] = ka;
-        val[i] = vb; val[p] = va;
+// S consecutive stages j, j/2, ..., j/2^(S-1) of block size k in one pass:
+// each thread holds the 2^S elements whose indices differ only in those S
+// bits (all in one k-block, so one direction) and applies the stages to them
+// in order, as the one-stage passes would.
+template <int S>
+__global__ void k_bitonic_global(uint64_t* __restrict__ key, uint32_t* __restrict__ val, int n, int k, int jlow) {
+    constexpr int E = 1 << S;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (n >> S)) return;
+    // insert S zero bits at the stage bits (jlow is the lowest stage)
+    const int a = ((t & ~(jlow - 1)) << S) | (t & (jlow - 1));
+    const bool asc = (a & k) == 0;
+    uint64_t kk[E];
+    uint32_t vv[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        kk[m] = key[a + m * jlow];
+        vv[m] = val[a + m * jlow];
+    }
+#pragma unroll
+    for (int st = S - 1; st >= 0; --st) {
+        const int d = 1 << st;              // partner offset in units of jlow
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            if (m & d) continue;
+            const uint64_t ka = kk[m], kb = kk[m | d];
+            const uint32_t va = vv[m], vb = vv[m | d];
+            const bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
+            kk[m] = sw ? kb : ka; kk[m | d] = sw ? ka : kb;
+            vv[m] = sw ? vb : va; vv[m | d] = sw ? va : vb;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        key[a + m * jlow] = kk[m];
+        val[a + m * jlow] = vv[m];
     }
 }
 
@@ -274,9 +297,21 @@ void sort_pairs(uint64_t* key, uint32_t* val, int n_pow2, hipStream_t st) {
     int blocks = n_pow2 / kSortLds;
     hipLaunchKernelGGL(k_bitonic_lds, dim3(blocks), dim3(512), 0, st, key, val, n_pow2, 2, kSortLds);
     for (int k = 2 * kSortLds; k <= n_pow2; k <<= 1) {
-        for (int j = k >> 1; j >= kSortLds; j >>= 1) {
-            hipLaunchKernelGGL(k_bitonic_global, dim3((n_pow2 + 255) / 256), dim3(256), 0, st,
-                               key, val, n_pow2, k, j);
+        // the stages j >= kSortLds, up to three per pass
+        for (int j = k >> 1; j >= kSortLds;) {
+            if (j >= 4 * kSortLds) {
+                hipLaunchKernelGGL(k_bitonic_global<3>, dim3((n_pow2 / 8 + 255) / 256), dim3(256), 0, st,
+                                   key, val, n_pow2, k, j / 4);
+                j /= 8;
+            } else if (j >= 2 * kSortLds) {
+                hipLaunchKernelGGL(k_bitonic_global<2>, dim3((n_pow2 / 4 + 255) / 256), dim3(256), 0, st,
+                                   key, val, n_pow2, k, j / 2);
+                j /= 4;
+            } else {
+                hipLaunchKernelGGL(k_bitonic_global<1>, dim3((n_pow2 / 2 + 255) / 256), dim3(256), 0, st,
+                                   key, val, n_pow2, k, j);
+                j /= 2;
+            }
         }
         hipLaunchKernelGGL(k_bitonic_lds, dim3(blocks), dim3(512), 0, st, key, val, n_pow2, k, k);
     }
