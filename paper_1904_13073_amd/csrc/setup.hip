@@ -258,7 +258,8 @@ __global__ void k_bitonic_global(uint64_t* __restrict__ key, uint32_t* __restric
 constexpr int kSortLds = 1024;  // elements per block in the LDS stages
 
 // All stages with j < kSortLds for a given k (and, when k <= kSortLds, all k
-// up to it) on one 1024-element slice held in LDS.
+// up to it) on one 1024-element slice held in LDS, 512 threads.
+static_assert(kSortLds == 2 * 512, "one compare-exchange per thread and stage");
 __global__ void __launch_bounds__(512) k_bitonic_lds(uint64_t* __restrict__ key,
         uint32_t* __restrict__ val, int n, int k_from, int k_to) {
     __shared__ uint64_t sk[kSortLds];
@@ -272,17 +273,14 @@ __global__ void __launch_bounds__(512) k_bitonic_lds(uint64_t* __restrict__ key,
     for (int k = k_from; k <= k_to; k <<= 1) {
         int jstart = min(k >> 1, kSortLds >> 1);
         for (int j = jstart; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < kSortLds; t += blockDim.x) {
-                int p = t ^ j;
-                if (p > t) {
-                    int gi = base + t;
-                    bool asc = (gi & k) == 0;
-                    uint64_t ka = sk[t], kb = sk[p];
-                    uint32_t va = sv[t], vb = sv[p];
-                    bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
-                    if (sw) { sk[t] = kb; sk[p] = ka; sv[t] = vb; sv[p] = va; }
-                }
-            }
+            // one pair per thread: the lower index has a 0 at bit j
+            const int q = threadIdx.x;
+            const int t = ((q & ~(j - 1)) << 1) | (q & (j - 1)), p = t + j;
+            const bool asc = ((base + t) & k) == 0;
+            const uint64_t ka = sk[t], kb = sk[p];
+            const uint32_t va = sv[t], vb = sv[p];
+            const bool sw = asc ? pair_less(kb, vb, ka, va) : pair_less(ka, va, kb, vb);
+            if (sw) { sk[t] = kb; sk[p] = ka; sv[t] = vb; sv[p] = va; }
             __syncthreads();
         }
     }
